@@ -1,0 +1,222 @@
+"""Seeded synthetic particle scenes (inputs only; no force arithmetic).
+
+Both the HIP path and the CPU oracle take their inputs from here, so this
+module holds nothing of the method itself: lattices, jitter, species
+assignment, Maxwell-Boltzmann velocities and random-sequential-addition
+(Poisson-disk) droplets.  Every generator takes an explicit seed and uses
+NumPy's PCG64.
+
+A scene is a dict with keys
+  pos   (n, 3) float64, wrapped into [0, L)
+  box   (3,)   float64, orthorhombic periodic box edges
+  types (n,)   int32 species index
+  eps, sig, mass  per-species parameters (lists)
+  rc, skin, rebuild_every, T, dt  physics and method settings
+  name  short description
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+FCC_BASIS = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]])
+
+
+def _wrap(pos, box):
+    return pos - box * np.floor(pos / box)
+
+
+def sc_lattice(nx, ny, nz, spacing, jitter=0.0, seed=0):
+    """Simple-cubic lattice of nx*ny*nz sites, uniform +-jitter per coordinate."""
+    g = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"),
+                 -1).reshape(-1, 3).astype(np.float64)
+    box = np.array([nx, ny, nz], np.float64) * spacing
+    pos = (g + 0.5) * spacing
+    if jitter:
+        rng = np.random.default_rng(seed)
+        pos = pos + rng.uniform(-jitter, jitter, pos.shape)
+    return _wrap(pos, box), box
+
+
+def fcc_lattice(nx, ny, nz, rho, jitter=0.0, seed=0):
+    """FCC lattice of nx*ny*nz unit cells (4 sites each) at number density rho."""
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    g = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"),
+                 -1).reshape(-1, 3).astype(np.float64)
+    pos = ((g[:, None, :] + FCC_BASIS[None] + 0.25) * a).reshape(-1, 3)
+    box = np.array([nx, ny, nz], np.float64) * a
+    if jitter:
+        rng = np.random.default_rng(seed)
+        pos = pos + rng.uniform(-jitter, jitter, pos.shape)
+    return _wrap(pos, box), box
+
+
+def mb_velocities(n, T, mass=1.0, seed=0):
+    """Maxwell-Boltzmann velocities: N(0, sqrt(T/m)) per component, zero total
+    momentum, rescaled to temperature T with 3n-3 degrees of freedom."""
+    rng = np.random.default_rng(seed)
+    m = np.broadcast_to(np.asarray(mass, np.float64), (n,))
+    v = rng.normal(0.0, 1.0, (n, 3)) * np.sqrt(T / m)[:, None]
+    p = (m[:, None] * v).sum(0) / m.sum()
+    v -= p
+    if n > 1:
+        ke2 = (m[:, None] * v * v).sum()
+        v *= math.sqrt(T * (3 * n - 3) / ke2)
+    return v
+
+
+def random_species(n, nspec, seed=0):
+    """Independent uniform species assignment (50/50 for two species)."""
+    if nspec == 1:
+        return np.zeros(n, np.int32)
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, nspec, n).astype(np.int32)
+
+
+def random_box(n, box, seed=0):
+    """Uniformly random positions in a box (used for tiny brute-force checks)."""
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, np.float64)
+    return rng.uniform(0.0, 1.0, (n, 3)) * box
+
+
+def rsa_points(box, count, dmin, seed, inside=None, existing=None, batch=4096,
+               max_tries=400):
+    """Random sequential addition: uniform darts kept when no accepted point
+    lies closer than dmin (periodic); ``inside(p)->bool mask`` restricts the
+    region.  Returns the new points (count, 3).  A uniform hash grid of edge
+    >= dmin bounds the neighbour test to 27 cells."""
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, np.float64)
+    nc = np.maximum(np.floor(box / dmin).astype(np.int64), 1)
+    edge = box / nc
+    cells: dict = {}
+    pts = []
+
+    def key(p):
+        c = np.minimum((p / edge).astype(np.int64), nc - 1)
+        return (int(c[0]), int(c[1]), int(c[2]))
+
+    def ok(p):
+        c = key(p)
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    k = ((c[0] + dx) % nc[0], (c[1] + dy) % nc[1], (c[2] + dz) % nc[2])
+                    for q in cells.get(k, ()):
+                        d = p - q
+                        d -= box * np.rint(d / box)
+                        if d @ d < dmin * dmin:
+                            return False
+        return True
+
+    if existing is not None:
+        for q in existing:
+            cells.setdefault(key(q), []).append(q)
+    tries = 0
+    while len(pts) < count:
+        cand = rng.uniform(0.0, 1.0, (batch, 3)) * box
+        if inside is not None:
+            cand = cand[inside(cand)]
+        for p in cand:
+            if ok(p):
+                pts.append(p)
+                cells.setdefault(key(p), []).append(p)
+                if len(pts) == count:
+                    break
+        tries += 1
+        if tries > max_tries * max(1, count // batch + 1):
+            raise RuntimeError("RSA did not reach the requested count")
+    return np.array(pts, np.float64).reshape(-1, 3)
+
+
+def droplet_scene(n_total, r_drop, rho_drop, rho_vap, dmin, seed):
+    """Spherical droplet at rho_drop in vapour at rho_vap, periodic cube; RSA
+    darts with minimum spacing dmin, droplet first, then vapour outside it."""
+    v_drop = 4.0 / 3.0 * math.pi * r_drop ** 3
+    n_drop = int(round(rho_drop * v_drop))
+    n_vap = n_total - n_drop
+    L = (v_drop + n_vap / rho_vap) ** (1.0 / 3.0)
+    box = np.array([L, L, L])
+    c = box / 2
+
+    def in_drop(p):
+        return ((p - c) ** 2).sum(1) < r_drop * r_drop
+
+    def out_drop(p):
+        return ~in_drop(p)
+
+    drop = rsa_points(box, n_drop, dmin, seed, inside=in_drop)
+    vap = rsa_points(box, n_vap, dmin, seed + 1, inside=out_drop, existing=drop)
+    return np.concatenate([drop, vap]), box
+
+
+def _scene(pos, box, **kw):
+    s = dict(pos=np.ascontiguousarray(pos, np.float64), box=np.asarray(box, np.float64))
+    s.update(kw)
+    n = len(s["pos"])
+    s.setdefault("types", np.zeros(n, np.int32))
+    s.setdefault("eps", [1.0])
+    s.setdefault("sig", [1.0])
+    s.setdefault("mass", [1.0])
+    return s
+
+
+def config1(seed=1001):
+    """1,000 particles, 10x10x10 simple cubic, spacing 1.08 sigma, +-0.05 jitter,
+    periodic cube, rc 2.5, FP64, T = 1.0, dt = 0.002."""
+    pos, box = sc_lattice(10, 10, 10, 1.08, 0.05, seed)
+    return _scene(pos, box, rc=2.5, skin=0.3, rebuild_every=10, T=1.0, dt=0.002,
+                  vel=mb_velocities(len(pos), 1.0, 1.0, seed + 7),
+                  name="1k simple-cubic rho~0.79 rc2.5")
+
+
+def config2(seed=1002):
+    """100,000 particles: 25x25x40 FCC unit cells at rho = 0.75, +-0.05 jitter,
+    rc 2.5, skin 0.3, rebuild every 10 steps, T = 1.0."""
+    pos, box = fcc_lattice(25, 25, 40, 0.75, 0.05, seed)
+    return _scene(pos, box, rc=2.5, skin=0.3, rebuild_every=10, T=1.0, dt=0.002,
+                  vel=mb_velocities(len(pos), 1.0, 1.0, seed + 7),
+                  name="100k FCC rho0.75 rc2.5")
+
+
+def headline(seed=20251203):
+    """1,000,000 particles: 50x50x100 FCC unit cells at rho = 0.75 (box
+    87.358 x 87.358 x 174.716), +-0.05 jitter, rc 2.5, skin 0.3, rebuild
+    every 10 steps, T = 1.0."""
+    pos, box = fcc_lattice(50, 50, 100, 0.75, 0.05, seed)
+    return _scene(pos, box, rc=2.5, skin=0.3, rebuild_every=10, T=1.0, dt=0.002,
+                  name="1M FCC rho0.75 rc2.5 skin0.3")
+
+
+def config4(seed=1004, ncell=100):
+    """Two species (sigma 1.0/1.2, eps 1.0/0.8, Lorentz-Berthelot), 50/50
+    random, ncell^3 FCC unit cells at rho = 0.7 (4M at ncell = 100),
+    rc = 2.5 * sigma_max = 3.0, +-0.05 jitter."""
+    pos, box = fcc_lattice(ncell, ncell, ncell, 0.7, 0.05, seed)
+    types = random_species(len(pos), 2, seed + 3)
+    return _scene(pos, box, types=types, eps=[1.0, 0.8], sig=[1.0, 1.2], mass=[1.0, 1.0],
+                  rc=3.0, skin=0.3, rebuild_every=10, T=1.0, dt=0.002,
+                  name=f"{len(pos)} two-species FCC rho0.7 rc3.0")
+
+
+def config3(seed=1003, n_total=1_000_000, r_drop=40.0):
+    """Droplet of radius r_drop at rho 0.8 inside vapour at rho 0.05, periodic
+    cube, RSA with minimum spacing 0.9, rc 3.0, T = 0.9."""
+    pos, box = droplet_scene(n_total, r_drop, 0.8, 0.05, 0.9, seed)
+    return _scene(pos, box, rc=3.0, skin=0.3, rebuild_every=10, T=0.9, dt=0.002,
+                  name=f"{len(pos)} droplet r{r_drop}")
+
+
+def homogeneous_scene(n, rho, rc, nspec, seed):
+    """Jittered FCC block of about n particles at density rho (nearly cubic
+    box), one or two species; used for tuner training scenes."""
+    m = max(2, int(round((n / 4.0) ** (1.0 / 3.0))))
+    nz = max(2, int(round(n / (4.0 * m * m))))
+    pos, box = fcc_lattice(m, m, nz, rho, 0.05, seed)
+    if nspec == 2:
+        return _scene(pos, box, types=random_species(len(pos), 2, seed + 3), eps=[1.0, 0.8],
+                      sig=[1.0, 1.2], mass=[1.0, 1.0], rc=rc, skin=0.3, rebuild_every=10,
+                      T=1.0, dt=0.002, name="homog2")
+    return _scene(pos, box, rc=rc, skin=0.3, rebuild_every=10, T=1.0, dt=0.002, name="homog")
