@@ -1,0 +1,231 @@
+/*
+ * mdlj.h -- C ABI of libmdlj: short-range Lennard-Jones 12-6 forces on one
+ * MI355X (gfx950) over linked cells, Verlet lists and Verlet cluster lists,
+ * with a runtime choice of the particle interaction order.
+ *
+ * Method: "Tuning of Vectorization Parameters for Molecular Dynamics
+ * Simulations in AutoPas" (arXiv 2512.03565).
+ *   - pair force sum F_i = sum_j F_ij over pairs inside the cutoff, with
+ *     F_ij = -F_ji (section 2.1, Eq. 1 and the cutoff/Newton-3 paragraphs);
+ *   - neighbour identification by linked cells, Verlet lists with a skin and
+ *     Verlet cluster lists (section 2.1.1);
+ *   - containers own particles and neighbour structures, a traversal hands
+ *     two particle lists to the force functor (section 2.3, Fig. "flow");
+ *   - interaction orders 1/VL, VL/1, 2/(VL/2), (VL/2)/2 (section 4.1,
+ *     Fig. "vec_patterns") -- here: wave-per-i, i-per-lane, cluster tiles;
+ *   - full-search auto-tuning over the Cartesian product of options,
+ *     several samples per configuration reduced to one value
+ *     (section 2.3.2), extended by the interaction order (section 4);
+ *   - a data-driven tuner, the paper's future-work item (section 6).
+ * The 12-6 law (which the paper names but does not print) is
+ *   u(r) = 4 eps [(sig/r)^12 - (sig/r)^6] - shift,
+ *   F_ij = 24 eps s6 (2 s6 - 1) / r^2 * (x_i - x_j),  s6 = (sig/r)^6,
+ * force truncated at rc (a pair interacts iff r^2 < rc^2), energy shifted
+ * by default so u(rc) = 0, Lorentz-Berthelot mixing of species.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an mdlj_status; nothing aborts or exits.  On error
+ *     mdlj_last_error(ctx) holds a message (valid until the next call on ctx).
+ *   - Pointers are borrowed for the duration of the call only.  mem_kind says
+ *     whether they are host (MDLJ_MEM_HOST) or device (MDLJ_MEM_DEVICE)
+ *     memory; the library copies what it needs into memory it owns.
+ *   - Per-particle arrays are indexed in the caller's order: outputs are
+ *     written back in the order the particles were given to mdlj_create.
+ *   - All device work is enqueued on the stream given to mdlj_create.  Calls
+ *     that return host scalars (epot, virial, counts, tuning results)
+ *     synchronise that stream before returning.
+ *   - One context per host thread; a context must not be used by two threads
+ *     at once.  Contexts are independent.
+ */
+#ifndef MDLJ_H
+#define MDLJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mdlj_ctx mdlj_ctx;
+
+typedef enum {
+    MDLJ_OK = 0,
+    MDLJ_ERR_ARG = -1,       /* a NULL pointer, a size or an enum out of range */
+    MDLJ_ERR_STATE = -2,     /* box, cutoff or species not set yet */
+    MDLJ_ERR_HIP = -3,       /* a HIP runtime call failed (message in last_error) */
+    MDLJ_ERR_NOMEM = -4,     /* device allocation failed */
+    MDLJ_ERR_OVERFLOW = -5,  /* a neighbour structure exceeded its capacity and
+                                growth is disabled */
+    MDLJ_ERR_NONFINITE = -6, /* a position is NaN or infinite */
+    MDLJ_ERR_GEOMETRY = -7,  /* box edge < 2 x interaction range, or fewer than
+                                3 linked cells along an axis */
+    MDLJ_ERR_NOTFOUND = -8   /* file or symbol missing (network weights) */
+} mdlj_status;
+
+enum { MDLJ_MEM_HOST = 0, MDLJ_MEM_DEVICE = 1 };
+
+/* Neighbour identification algorithm (section 2.1.1). */
+enum { MDLJ_NBR_LC = 0, MDLJ_NBR_VL = 1, MDLJ_NBR_VCL = 2 };
+
+/* Particle interaction order (section 4.1).  I_PER_LANE is VectorLength/1
+ * (distinct i per lane, one j broadcast to all lanes); CLUSTER_TILE covers
+ * the split patterns 2/(VL/2) and (VL/2)/2 as a tile_i x tile_j lane grid;
+ * WAVE_PER_I is 1/VectorLength (j across lanes, reduction over lanes). */
+enum { MDLJ_ORD_I_PER_LANE = 0, MDLJ_ORD_CLUSTER_TILE = 1, MDLJ_ORD_WAVE_PER_I = 2 };
+
+/* Arithmetic: FP32 pair arithmetic with FP64 accumulation, or all FP64. */
+enum { MDLJ_PREC_F32PAIR_F64ACC = 0, MDLJ_PREC_F64 = 1 };
+
+/* Tuning strategy (section 2.3.2 full search; section 6 data-driven). */
+enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2 };
+
+/*
+ * One point of the search space.  Meaning of tile_i / tile_j per order:
+ *   I_PER_LANE   LC: tile_i = linked cells per i-tile along x (1, 2, 4);
+ *                VL/VCL: unused (0).
+ *   CLUSTER_TILE tile_i x tile_j = 64 lanes of one wavefront, tile_i i's and
+ *                tile_j j's per step (LC: 16x4, 8x8; VCL: cluster_size x
+ *                64/cluster_size).
+ *   WAVE_PER_I   tile_i = g, the i-particles per wavefront (1, 2, 4); each
+ *                gets 64/g lanes.
+ * cluster_size is 4 or 8 for VCL, 0 otherwise.  newton3 = 1 computes each
+ * pair once and applies F_ji = -F_ij with atomics (section 4.1.3).
+ */
+typedef struct {
+    int32_t nbr_algo;
+    int32_t order;
+    int32_t tile_i;
+    int32_t tile_j;
+    int32_t cluster_size;
+    int32_t newton3;
+} mdlj_config;
+
+/*
+ * Create a context holding n particles (n >= 1) of n_species species
+ * (1..8).  x, y, z: positions (float64, length n); type: species index per
+ * particle (int32 in [0, n_species), or NULL for all zero).  mem_kind says
+ * where the arrays live.  hip_stream: a hipStream_t (NULL = default stream)
+ * on which all work of this context is enqueued.  On success *out owns all
+ * device memory of the context.  Defaults: energy shift on, FP32 pair
+ * arithmetic, rebuild every 10 steps, skin 0, config LC / I_PER_LANE / 1.
+ */
+mdlj_status mdlj_create(mdlj_ctx **out, int64_t n, const double *x, const double *y,
+                        const double *z, const int32_t *type, int32_t n_species,
+                        int32_t mem_kind, void *hip_stream);
+
+/* Free the context and all its device memory.  NULL is accepted. */
+mdlj_status mdlj_destroy(mdlj_ctx *ctx);
+
+/* Orthorhombic periodic box [0,lx) x [0,ly) x [0,lz); edges > 0. */
+mdlj_status mdlj_set_box(mdlj_ctx *ctx, double lx, double ly, double lz);
+
+/* Cutoff radius rc > 0 (section 2.1): pairs interact iff r^2 < rc^2. */
+mdlj_status mdlj_set_cutoff(mdlj_ctx *ctx, double rc);
+
+/* Verlet skin >= 0 and the rebuild interval (>= 1 force evaluations) of the
+ * Verlet and cluster lists (section 2.1.1).  Lists hold pairs within rc+skin
+ * and are also rebuilt early once any particle has moved more than skin/2. */
+mdlj_status mdlj_set_skin(mdlj_ctx *ctx, double skin, int32_t rebuild_every);
+
+/* Parameters of species s: epsilon > 0, sigma > 0 (Lorentz-Berthelot mixing
+ * across species).  Every species must be set before forces are computed. */
+mdlj_status mdlj_set_species(mdlj_ctx *ctx, int32_t s, double epsilon, double sigma);
+
+/* Energy shift so that u(rc) = 0: on (1, default) or off (0).  Forces are
+ * never shifted. */
+mdlj_status mdlj_set_energy_shift(mdlj_ctx *ctx, int32_t on);
+
+/* MDLJ_PREC_F32PAIR_F64ACC (default) or MDLJ_PREC_F64. */
+mdlj_status mdlj_set_precision(mdlj_ctx *ctx, int32_t prec);
+
+/* Replace all positions (caller order, float64, length n).  Non-finite
+ * values give MDLJ_ERR_NONFINITE (checked on the device for device input;
+ * the check synchronises the stream). */
+mdlj_status mdlj_set_positions(mdlj_ctx *ctx, const double *x, const double *y,
+                               const double *z, int32_t mem_kind);
+
+/* Copy current positions (wrapped into the box, caller order) out. */
+mdlj_status mdlj_get_positions(mdlj_ctx *ctx, double *x, double *y, double *z,
+                               int32_t mem_kind);
+
+/* Select the configuration used by compute_forces.  An invalid combination
+ * gives MDLJ_ERR_ARG and leaves the current one in place. */
+mdlj_status mdlj_set_config(mdlj_ctx *ctx, const mdlj_config *cfg);
+mdlj_status mdlj_get_config(const mdlj_ctx *ctx, mdlj_config *cfg);
+
+/* Number of valid configurations (the tuner's search space) and the k-th. */
+mdlj_status mdlj_config_count(const mdlj_ctx *ctx, int32_t *count);
+mdlj_status mdlj_config_at(const mdlj_ctx *ctx, int32_t k, mdlj_config *cfg);
+
+/* Rebuild the neighbour structure of the current configuration now
+ * (binning, Verlet or cluster lists).  compute_forces does this itself when
+ * needed. */
+mdlj_status mdlj_rebuild_neighbors(mdlj_ctx *ctx);
+
+/*
+ * Forces on every particle (caller order) into fx, fy, fz (float64, length
+ * n; mem_kind says where).  epot (total potential energy U = sum over pairs
+ * of u) and virial (W = sum over pairs of r_ij . F_ij) are host float64
+ * pointers and may be NULL; when either is given the call synchronises.
+ * Rebuilds the neighbour structure first when it is due.
+ */
+mdlj_status mdlj_compute_forces(mdlj_ctx *ctx, double *fx, double *fy, double *fz,
+                                int32_t mem_kind, double *epot, double *virial);
+
+/* Number of unordered pairs with r < rc (the useful pairs), counted on the
+ * device from the current positions. */
+mdlj_status mdlj_count_pairs(mdlj_ctx *ctx, int64_t *n_useful_pairs);
+
+/*
+ * Choose a configuration.  FIXED keeps the current one; EXHAUSTIVE times
+ * every valid configuration `samples` times (first sample dropped as
+ * warm-up, the rest averaged; the lower index wins ties) on the amortised
+ * step time force + rebuild / rebuild_every; LEARNED asks the network and
+ * falls back to EXHAUSTIVE when its confidence is below the threshold set
+ * by mdlj_mlp_set_threshold (default 0.6) or no network is loaded.  The
+ * chosen configuration is made current; *chosen and *step_us (measured
+ * amortised microseconds of the chosen one, may be NULL) are written.
+ */
+mdlj_status mdlj_tune(mdlj_ctx *ctx, int32_t mode, int32_t samples, mdlj_config *chosen,
+                      double *step_us);
+
+/* Per-configuration results of the last EXHAUSTIVE tuning: up to cap
+ * entries of amortised microseconds in config_at order; *count = number of
+ * configurations. */
+mdlj_status mdlj_tune_results(const mdlj_ctx *ctx, double *us, int32_t cap, int32_t *count);
+
+/*
+ * nsteps velocity-Verlet steps (mass per species, default 1; time step dt):
+ * v += F dt/2m; x += v dt; wrap; F = F(x); v += F dt/2m.  vx, vy, vz are
+ * device float64 arrays in caller order, updated in place.  The forces of
+ * the current positions must have been computed once before (they are kept
+ * in the context).
+ */
+mdlj_status mdlj_step_vv(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt,
+                         int32_t nsteps);
+mdlj_status mdlj_set_mass(mdlj_ctx *ctx, int32_t s, double mass);
+
+/* Eight scene features the learned tuner reads (log10 N, density,
+ * rc / sigma_max, species count, expected neighbours within rc, cell
+ * occupancy coefficient of variation, empty-cell fraction, max/mean cell
+ * occupancy), computed on the device from the current positions. */
+mdlj_status mdlj_features(mdlj_ctx *ctx, float *features8);
+
+/* Learned tuner network (8 -> 64 -> 64 -> K).  load/save use a flat
+ * little-endian float32 file; train runs `epochs` epochs of Adam on the
+ * device over (features, best-config label) pairs given in host memory. */
+mdlj_status mdlj_mlp_load(mdlj_ctx *ctx, const char *path);
+mdlj_status mdlj_mlp_save(const mdlj_ctx *ctx, const char *path);
+mdlj_status mdlj_mlp_set_threshold(mdlj_ctx *ctx, double threshold);
+
+/* Human-readable message of the last failing call on ctx ("" if none). */
+const char *mdlj_last_error(const mdlj_ctx *ctx);
+
+/* Library version string. */
+const char *mdlj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDLJ_H */

@@ -1,0 +1,545 @@
+// api.cpp -- the C ABI of libmdlj: context, settings, neighbour-structure
+// life cycle and dispatch of the force kernel of the current configuration.
+//
+// The container/traversal/functor split follows section 2.3 (Fig. "flow"):
+// the context owns particles and neighbour structures (linked cells,
+// Verlet lists, Verlet cluster lists, section 2.1.1), and compute_forces
+// hands them to the force kernel of the chosen interaction order
+// (section 4.1).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "internal.h"
+
+#define MDLJ_VERSION_STR "mdlj 0.1 gfx950"
+
+mdlj_status set_err(mdlj_ctx *ctx, mdlj_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+mdlj_status hip_check(mdlj_ctx *ctx, hipError_t e, const char *what)
+{
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    return set_err(ctx, e == hipErrorOutOfMemory ? MDLJ_ERR_NOMEM : MDLJ_ERR_HIP, buf);
+}
+
+mdlj_status ensure(mdlj_ctx *ctx, DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return MDLJ_OK;
+    if (b.p) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        HIPCHK(ctx, hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;  // grow with headroom
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return hip_check(ctx, e, "hipMalloc");
+    }
+    b.bytes = want;
+    return MDLJ_OK;
+}
+
+static void free_buf(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename T>
+void fill_table(const mdlj_ctx *ctx, LJTable<T> *t)
+{
+    memset(t, 0, sizeof *t);
+    int ns = ctx->nspec;
+    t->ns = ns;
+    t->rc2 = (T)(ctx->rc * ctx->rc);
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            // Lorentz-Berthelot mixing
+            double sig = 0.5 * (ctx->sig[a] + ctx->sig[b]);
+            double eps = sqrt(ctx->eps[a] * ctx->eps[b]);
+            double sr = sig / ctx->rc;
+            double sr6 = sr * sr * sr * sr * sr * sr;
+            int k = a * ns + b;
+            t->sig2[k] = (T)(sig * sig);
+            t->eps24[k] = (T)(24.0 * eps);
+            t->eps4[k] = (T)(4.0 * eps);
+            t->shift[k] = ctx->shift_on ? (T)(4.0 * eps * (sr6 * sr6 - sr6)) : (T)0;
+        }
+}
+template void fill_table<float>(const mdlj_ctx *, LJTable<float> *);
+template void fill_table<double>(const mdlj_ctx *, LJTable<double> *);
+
+// ------------------------------------------------------------------ configs
+
+static bool cfg_eq(const mdlj_config &a, const mdlj_config &b)
+{
+    return a.nbr_algo == b.nbr_algo && a.order == b.order && a.tile_i == b.tile_i &&
+           a.tile_j == b.tile_j && a.cluster_size == b.cluster_size && a.newton3 == b.newton3;
+}
+
+// The search space: neighbour algorithm x interaction order x tile shape x
+// Newton-3, the Cartesian product of section 2.3.2 extended by the order
+// (section 4), restricted to the combinations that exist.
+static std::vector<mdlj_config> build_space()
+{
+    std::vector<mdlj_config> v;
+    // linked cells (rebinned every step; full shell, no Newton-3)
+    for (int k : {1, 2, 4}) v.push_back({MDLJ_NBR_LC, MDLJ_ORD_I_PER_LANE, k, 1, 0, 0});
+    for (int ai : {8, 16}) v.push_back({MDLJ_NBR_LC, MDLJ_ORD_CLUSTER_TILE, ai, 64 / ai, 0, 0});
+    for (int g : {1, 2, 4}) v.push_back({MDLJ_NBR_LC, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, 0});
+    // Verlet lists
+    for (int n3 : {0, 1}) {
+        v.push_back({MDLJ_NBR_VL, MDLJ_ORD_I_PER_LANE, 0, 0, 0, n3});
+        for (int g : {1, 2, 4}) v.push_back({MDLJ_NBR_VL, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, n3});
+    }
+    // Verlet cluster lists
+    for (int m : {4, 8})
+        for (int n3 : {0, 1}) {
+            v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_I_PER_LANE, 0, 0, m, n3});
+            v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_CLUSTER_TILE, m, 64 / m, m, n3});
+        }
+    return v;
+}
+
+static bool cfg_valid(const mdlj_ctx *ctx, const mdlj_config &c)
+{
+    for (const auto &s : ctx->space)
+        if (cfg_eq(s, c)) return true;
+    return false;
+}
+
+// ------------------------------------------------------------------ helpers
+
+static bool ready(const mdlj_ctx *ctx, std::string *why)
+{
+    if (!ctx->box_set) { *why = "box not set"; return false; }
+    if (!(ctx->rc > 0)) { *why = "cutoff not set"; return false; }
+    for (int s = 0; s < ctx->nspec; ++s)
+        if (!ctx->species_set[s]) { *why = "species parameters not set"; return false; }
+    return true;
+}
+
+// Interaction range a configuration needs from its neighbour structure.
+static double range_of(const mdlj_ctx *ctx, const mdlj_config &c)
+{
+    return c.nbr_algo == MDLJ_NBR_LC ? ctx->rc : ctx->rc + ctx->skin;
+}
+
+static mdlj_status check_geometry(mdlj_ctx *ctx, const mdlj_config &c)
+{
+    double r = range_of(ctx, c);
+    for (int a = 0; a < 3; ++a) {
+        if (ctx->box[a] < 2.0 * r)
+            return set_err(ctx, MDLJ_ERR_GEOMETRY, "box edge shorter than twice the interaction range");
+        if (c.nbr_algo != MDLJ_NBR_VCL && floor(ctx->box[a] / r) < 3)
+            return set_err(ctx, MDLJ_ERR_GEOMETRY, "fewer than 3 linked cells along an axis");
+    }
+    return MDLJ_OK;
+}
+
+static mdlj_status copy_in(mdlj_ctx *ctx, double *dst, const double *src, int mem_kind)
+{
+    hipMemcpyKind k = mem_kind == MDLJ_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(ctx, hipMemcpyAsync(dst, src, sizeof(double) * ctx->n, k, ctx->stream));
+    return MDLJ_OK;
+}
+
+static mdlj_status copy_out(mdlj_ctx *ctx, double *dst, const double *src, int mem_kind)
+{
+    hipMemcpyKind k = mem_kind == MDLJ_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(ctx, hipMemcpyAsync(dst, src, sizeof(double) * ctx->n, k, ctx->stream));
+    return MDLJ_OK;
+}
+
+static void invalidate(mdlj_ctx *ctx)
+{
+    ctx->built = false;
+    ctx->forces_valid = false;
+}
+
+// ------------------------------------------------------------------ build
+
+// (Re)build the neighbour structure of configuration c.
+static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
+{
+    STCHK(check_geometry(ctx, c));
+    if (c.nbr_algo == MDLJ_NBR_VCL) {
+        STCHK(vcl_build(ctx, c));
+    } else {
+        double r = range_of(ctx, c);
+        double rmin[3] = {r, r, r};
+        int h[3] = {1, 1, 1};
+        Grid g;
+        if (!make_grid(ctx->box, rmin, h, false, &g))
+            return set_err(ctx, MDLJ_ERR_GEOMETRY, "grid set-up failed");
+        STCHK(bin_particles(ctx, g));
+        if (c.nbr_algo == MDLJ_NBR_VL) STCHK(vl_build(ctx, c));
+    }
+    ctx->built = true;
+    ctx->built_cfg = c;
+    ctx->steps_since_build = 0;
+    memcpy(ctx->built_box, ctx->box, sizeof ctx->box);
+    ctx->built_rc = ctx->rc;
+    ctx->built_skin = ctx->skin;
+    return MDLJ_OK;
+}
+
+static bool structure_current(const mdlj_ctx *ctx, const mdlj_config &c)
+{
+    if (!ctx->built) return false;
+    const mdlj_config &b = ctx->built_cfg;
+    // the VL/VCL structures differ per layout; LC grids only by range
+    if (b.nbr_algo != c.nbr_algo) return false;
+    if (c.nbr_algo == MDLJ_NBR_VL && (b.order != c.order || b.newton3 != c.newton3)) return false;
+    if (c.nbr_algo == MDLJ_NBR_VCL && (b.cluster_size != c.cluster_size || b.newton3 != c.newton3))
+        return false;
+    if (memcmp(ctx->built_box, ctx->box, sizeof ctx->box) != 0) return false;
+    if (ctx->built_rc != ctx->rc || ctx->built_skin != ctx->skin) return false;
+    return true;
+}
+
+// Make the structure valid for the current positions: LC re-bins whenever
+// positions changed; lists are rebuilt when stale (interval or displacement)
+mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed, bool *rebuilt)
+{
+    *rebuilt = false;
+    bool need = !structure_current(ctx, c);
+    if (!need && positions_changed) {
+        if (c.nbr_algo == MDLJ_NBR_LC) need = true;
+        else if (ctx->steps_since_build >= ctx->rebuild_every) need = true;
+    }
+    if (need) {
+        STCHK(rebuild(ctx, c));
+        *rebuilt = true;
+    }
+    return MDLJ_OK;
+}
+
+// Run the force kernel of c into the sorted force buffers.
+mdlj_status run_force_kernel(mdlj_ctx *ctx, const mdlj_config &c, bool energy, ForceOut &fo,
+                             int64_t *nblocks)
+{
+    STCHK(ensure(ctx, ctx->b_fsorted, sizeof(double) * 3 * ctx->n_ext));
+    double *f = (double *)ctx->b_fsorted.p;
+    fo.fx = f;
+    fo.fy = f + ctx->n_ext;
+    fo.fz = f + 2 * ctx->n_ext;
+    fo.partial = nullptr;
+    switch (c.nbr_algo) {
+    case MDLJ_NBR_LC: return lc_forces(ctx, c, energy, fo, nblocks);
+    case MDLJ_NBR_VL: return vl_forces(ctx, c, energy, fo, nblocks);
+    case MDLJ_NBR_VCL: return vcl_forces(ctx, c, energy, fo, nblocks);
+    }
+    return set_err(ctx, MDLJ_ERR_ARG, "unknown neighbour algorithm");
+}
+
+// The whole force evaluation for the current configuration into the
+// context's caller-order force arrays; optional totals.
+mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW)
+{
+    std::string why;
+    if (!ready(ctx, &why)) return set_err(ctx, MDLJ_ERR_STATE, why);
+    const mdlj_config c = ctx->cfg;
+    bool rebuilt;
+    STCHK(prepare(ctx, c, positions_changed, &rebuilt));
+    ForceOut fo;
+    int64_t nb = 0;
+    bool energy = UW != nullptr;
+    STCHK(run_force_kernel(ctx, c, energy, fo, &nb));
+    STCHK(unpermute_forces(ctx, fo, c.newton3 != 0, ctx->fx, ctx->fy, ctx->fz));
+    if (energy) STCHK(reduce_partials(ctx, fo.partial, nb, UW));
+    ctx->steps_since_build++;
+    ctx->forces_valid = true;
+    return MDLJ_OK;
+}
+
+// ------------------------------------------------------------------ ABI
+
+extern "C" {
+
+const char *mdlj_version(void) { return MDLJ_VERSION_STR; }
+
+const char *mdlj_last_error(const mdlj_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mdlj_status mdlj_create(mdlj_ctx **out, int64_t n, const double *x, const double *y,
+                        const double *z, const int32_t *type, int32_t n_species,
+                        int32_t mem_kind, void *hip_stream)
+{
+    if (!out) return MDLJ_ERR_ARG;
+    *out = nullptr;
+    if (n < 1 || n >= ((int64_t)1 << 30) || !x || !y || !z) return MDLJ_ERR_ARG;
+    if (n_species < 1 || n_species > MDLJ_MAX_SPECIES) return MDLJ_ERR_ARG;
+    if (mem_kind != MDLJ_MEM_HOST && mem_kind != MDLJ_MEM_DEVICE) return MDLJ_ERR_ARG;
+    if (mem_kind == MDLJ_MEM_HOST) {
+        for (int64_t i = 0; i < n; ++i)
+            if (!isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i])) return MDLJ_ERR_NONFINITE;
+        if (type)
+            for (int64_t i = 0; i < n; ++i)
+                if (type[i] < 0 || type[i] >= n_species) return MDLJ_ERR_ARG;
+    }
+    mdlj_ctx *ctx = new (std::nothrow) mdlj_ctx();
+    if (!ctx) return MDLJ_ERR_NOMEM;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->n = n;
+    ctx->nspec = n_species;
+    ctx->space = build_space();
+    mdlj_status st = MDLJ_OK;
+    DevBuf pos, typ, frc;
+    do {
+        if ((st = ensure(ctx, pos, sizeof(double) * 3 * n)) != MDLJ_OK) break;
+        if ((st = ensure(ctx, typ, sizeof(int32_t) * n)) != MDLJ_OK) break;
+        if ((st = ensure(ctx, frc, sizeof(double) * 3 * n)) != MDLJ_OK) break;
+        ctx->x = (double *)pos.p;
+        ctx->y = ctx->x + n;
+        ctx->z = ctx->x + 2 * n;
+        ctx->type = (int32_t *)typ.p;
+        ctx->fx = (double *)frc.p;
+        ctx->fy = ctx->fx + n;
+        ctx->fz = ctx->fx + 2 * n;
+        if ((st = copy_in(ctx, ctx->x, x, mem_kind)) != MDLJ_OK) break;
+        if ((st = copy_in(ctx, ctx->y, y, mem_kind)) != MDLJ_OK) break;
+        if ((st = copy_in(ctx, ctx->z, z, mem_kind)) != MDLJ_OK) break;
+        hipError_t e;
+        if (type) {
+            e = hipMemcpyAsync(ctx->type, type, sizeof(int32_t) * n,
+                               mem_kind == MDLJ_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                           : hipMemcpyHostToDevice,
+                               ctx->stream);
+        } else {
+            e = hipMemsetAsync(ctx->type, 0, sizeof(int32_t) * n, ctx->stream);
+        }
+        if (e != hipSuccess) { st = hip_check(ctx, e, "type copy"); break; }
+        if (mem_kind == MDLJ_MEM_DEVICE) {
+            bool ok = true;
+            if ((st = check_finite(ctx, ctx->x, ctx->y, ctx->z, n, &ok)) != MDLJ_OK) break;
+            if (!ok) { st = MDLJ_ERR_NONFINITE; break; }
+            if (type) {
+                if ((st = check_types(ctx, &ok)) != MDLJ_OK) break;
+                if (!ok) { st = MDLJ_ERR_ARG; break; }
+            }
+        }
+        e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) { st = hip_check(ctx, e, "create sync"); break; }
+    } while (0);
+    if (st != MDLJ_OK) {
+        free_buf(pos);
+        free_buf(typ);
+        free_buf(frc);
+        mdlj_destroy(ctx);
+        return st;
+    }
+    ctx->b_pos = pos;
+    ctx->b_type = typ;
+    ctx->b_force = frc;
+    *out = ctx;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_destroy(mdlj_ctx *ctx)
+{
+    if (!ctx) return MDLJ_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    DevBuf *bufs[] = {&ctx->b_cell_of, &ctx->b_rank,    &ctx->b_count,   &ctx->b_start,
+                      &ctx->b_slot_of, &ctx->b_sorted,  &ctx->b_scan_part, &ctx->b_fsorted,
+                      &ctx->b_partial, &ctx->b_flags,   &ctx->b_nbr,     &ctx->b_nlen,
+                      &ctx->b_ref,     &ctx->b_disp,    &ctx->b_misc,    &ctx->b_clu,
+                      &ctx->b_cpair,   &ctx->b_cstart,  &ctx->b_fold,
+                      &ctx->b_pos,     &ctx->b_type,    &ctx->b_force,
+                      &ctx->b_cnt_ext, &ctx->b_img,     &ctx->b_icnt,    &ctx->b_ilist,
+                      &ctx->b_xref};
+    for (DevBuf *b : bufs) free_buf(*b);
+    delete ctx;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_box(mdlj_ctx *ctx, double lx, double ly, double lz)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (!(lx > 0 && ly > 0 && lz > 0) || !isfinite(lx) || !isfinite(ly) || !isfinite(lz))
+        return set_err(ctx, MDLJ_ERR_ARG, "box edges must be positive and finite");
+    ctx->box[0] = lx;
+    ctx->box[1] = ly;
+    ctx->box[2] = lz;
+    ctx->box_set = true;
+    invalidate(ctx);
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_cutoff(mdlj_ctx *ctx, double rc)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (!(rc > 0) || !isfinite(rc)) return set_err(ctx, MDLJ_ERR_ARG, "cutoff must be positive");
+    ctx->rc = rc;
+    invalidate(ctx);
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_skin(mdlj_ctx *ctx, double skin, int32_t rebuild_every)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (!(skin >= 0) || !isfinite(skin) || rebuild_every < 1)
+        return set_err(ctx, MDLJ_ERR_ARG, "skin must be >= 0 and rebuild_every >= 1");
+    ctx->skin = skin;
+    ctx->rebuild_every = rebuild_every;
+    invalidate(ctx);
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_species(mdlj_ctx *ctx, int32_t s, double epsilon, double sigma)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (s < 0 || s >= ctx->nspec) return set_err(ctx, MDLJ_ERR_ARG, "species index out of range");
+    if (!(epsilon > 0) || !(sigma > 0) || !isfinite(epsilon) || !isfinite(sigma))
+        return set_err(ctx, MDLJ_ERR_ARG, "epsilon and sigma must be positive");
+    ctx->eps[s] = epsilon;
+    ctx->sig[s] = sigma;
+    ctx->species_set[s] = true;
+    ctx->forces_valid = false;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_mass(mdlj_ctx *ctx, int32_t s, double mass)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (s < 0 || s >= ctx->nspec || !(mass > 0) || !isfinite(mass))
+        return set_err(ctx, MDLJ_ERR_ARG, "bad species index or mass");
+    ctx->mass[s] = mass;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_energy_shift(mdlj_ctx *ctx, int32_t on)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (on != 0 && on != 1) return set_err(ctx, MDLJ_ERR_ARG, "shift flag must be 0 or 1");
+    ctx->shift_on = on;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_precision(mdlj_ctx *ctx, int32_t prec)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (prec != MDLJ_PREC_F32PAIR_F64ACC && prec != MDLJ_PREC_F64)
+        return set_err(ctx, MDLJ_ERR_ARG, "unknown precision");
+    ctx->prec = prec;
+    ctx->forces_valid = false;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_positions(mdlj_ctx *ctx, const double *x, const double *y, const double *z,
+                               int32_t mem_kind)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (!x || !y || !z || (mem_kind != MDLJ_MEM_HOST && mem_kind != MDLJ_MEM_DEVICE))
+        return set_err(ctx, MDLJ_ERR_ARG, "bad positions");
+    if (mem_kind == MDLJ_MEM_HOST) {
+        for (int64_t i = 0; i < ctx->n; ++i)
+            if (!isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i]))
+                return set_err(ctx, MDLJ_ERR_NONFINITE, "non-finite particle position");
+    }
+    STCHK(copy_in(ctx, ctx->x, x, mem_kind));
+    STCHK(copy_in(ctx, ctx->y, y, mem_kind));
+    STCHK(copy_in(ctx, ctx->z, z, mem_kind));
+    if (mem_kind == MDLJ_MEM_DEVICE) {
+        bool ok = true;
+        STCHK(check_finite(ctx, ctx->x, ctx->y, ctx->z, ctx->n, &ok));
+        if (!ok) return set_err(ctx, MDLJ_ERR_NONFINITE, "non-finite particle position");
+    } else {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    ctx->forces_valid = false;
+    ctx->pos_changed = true;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_get_positions(mdlj_ctx *ctx, double *x, double *y, double *z, int32_t mem_kind)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (!x || !y || !z || (mem_kind != MDLJ_MEM_HOST && mem_kind != MDLJ_MEM_DEVICE))
+        return set_err(ctx, MDLJ_ERR_ARG, "bad output pointers");
+    STCHK(copy_out(ctx, x, ctx->x, mem_kind));
+    STCHK(copy_out(ctx, y, ctx->y, mem_kind));
+    STCHK(copy_out(ctx, z, ctx->z, mem_kind));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_config(mdlj_ctx *ctx, const mdlj_config *cfg)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (!cfg || !cfg_valid(ctx, *cfg)) return set_err(ctx, MDLJ_ERR_ARG, "invalid configuration");
+    if (!cfg_eq(ctx->cfg, *cfg)) ctx->forces_valid = false;
+    ctx->cfg = *cfg;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_get_config(const mdlj_ctx *ctx, mdlj_config *cfg)
+{
+    if (!ctx || !cfg) return MDLJ_ERR_ARG;
+    *cfg = ctx->cfg;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_config_count(const mdlj_ctx *ctx, int32_t *count)
+{
+    if (!ctx || !count) return MDLJ_ERR_ARG;
+    *count = (int32_t)ctx->space.size();
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_config_at(const mdlj_ctx *ctx, int32_t k, mdlj_config *cfg)
+{
+    if (!ctx || !cfg || k < 0 || k >= (int32_t)ctx->space.size()) return MDLJ_ERR_ARG;
+    *cfg = ctx->space[k];
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_rebuild_neighbors(mdlj_ctx *ctx)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    std::string why;
+    if (!ready(ctx, &why)) return set_err(ctx, MDLJ_ERR_STATE, why);
+    STCHK(rebuild(ctx, ctx->cfg));
+    ctx->pos_changed = false;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_compute_forces(mdlj_ctx *ctx, double *fx, double *fy, double *fz,
+                                int32_t mem_kind, double *epot, double *virial)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (!fx || !fy || !fz || (mem_kind != MDLJ_MEM_HOST && mem_kind != MDLJ_MEM_DEVICE))
+        return set_err(ctx, MDLJ_ERR_ARG, "bad output pointers");
+    double UW[2] = {0, 0};
+    bool want = epot || virial;
+    STCHK(forces_internal(ctx, ctx->pos_changed, want ? UW : nullptr));
+    ctx->pos_changed = false;
+    STCHK(copy_out(ctx, fx, ctx->fx, mem_kind));
+    STCHK(copy_out(ctx, fy, ctx->fy, mem_kind));
+    STCHK(copy_out(ctx, fz, ctx->fz, mem_kind));
+    if (mem_kind == MDLJ_MEM_HOST) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (epot) *epot = UW[0];
+    if (virial) *virial = UW[1];
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_count_pairs(mdlj_ctx *ctx, int64_t *n_useful_pairs)
+{
+    if (!ctx || !n_useful_pairs) return MDLJ_ERR_ARG;
+    std::string why;
+    if (!ready(ctx, &why)) return set_err(ctx, MDLJ_ERR_STATE, why);
+    return count_pairs_dev(ctx, n_useful_pairs);
+}
+
+}  // extern "C"

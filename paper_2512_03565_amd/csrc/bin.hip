@@ -1,0 +1,541 @@
+// bin.hip -- counting-sort cell binning with periodic halo images.
+//
+// The linked-cell container (section 2.1.1: equal cells, a particle
+// interacts with its own and the neighbouring cells) is stored as one
+// sorted array of particle records.  Interior cells hold the particles of
+// the box; the h outer layers of cells hold periodic images (shifted by
+// +-L) of the interior cells they mirror, so force kernels read every
+// neighbour cell as plain memory and never apply a minimum image.
+//
+// Steps: wrap + cell index + per-cell rank (atomics) -> exclusive scan of
+// the extended cell counts -> scatter caller indices -> order each cell by
+// caller index (so results do not depend on atomic order) -> fill records
+// of interior and halo cells.
+#include "internal.h"
+
+namespace {
+
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+// x - L floor(x / L), every operation rounded on its own (no FMA), so the
+// cell decision is the same as a plain binary64 evaluation of the formula.
+__device__ __forceinline__ double wrap_coord(double x, double L)
+{
+#pragma clang fp contract(off)
+    double q = floor(x / L);
+    double m = L * q;
+    return x - m;
+}
+
+__device__ __forceinline__ int cell_coord(double xw, double inv, int n)
+{
+#pragma clang fp contract(off)
+    double s = xw * inv;
+    int c = (int)s;
+    c = c >= n ? n - 1 : c;
+    c = c < 0 ? 0 : c;
+    return c;
+}
+
+// Interior source cell of an extended cell (identity for interior cells).
+__device__ __forceinline__ int64_t source_cell(int64_t e, const Grid &g)
+{
+    int64_t src = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int c = (int)((e / g.stride[a]) % g.e[a]) - g.h[a];
+        int s = c % g.n[a];
+        s = s < 0 ? s + g.n[a] : s;
+        src += (int64_t)(s + g.h[a]) * g.stride[a];
+    }
+    return src;
+}
+
+__global__ void k_bin_count(int64_t n, double *__restrict__ x, double *__restrict__ y,
+                            double *__restrict__ z, Grid g, int32_t *__restrict__ cell_of,
+                            int32_t *__restrict__ rank, int32_t *__restrict__ count,
+                            int32_t *__restrict__ flags)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double p[3] = {x[i], y[i], z[i]};
+    if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) {
+        atomicOr(&flags[0], 1);
+        cell_of[i] = -1;
+        rank[i] = 0;
+        return;
+    }
+    int64_t e = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double xw = wrap_coord(p[a], g.L[a]);
+        int c = cell_coord(xw, g.inv[a], g.n[a]);
+        e += (int64_t)(c + g.h[a]) * g.stride[a];
+        p[a] = xw;
+    }
+    x[i] = p[0];
+    y[i] = p[1];
+    z[i] = p[2];
+    cell_of[i] = (int32_t)e;
+    rank[i] = atomicAdd(&count[e], 1);
+}
+
+// Extended-cell counts: a halo cell holds as many records as its source.
+__global__ void k_ext_counts(Grid g, const int32_t *__restrict__ count,
+                             int32_t *__restrict__ cnt_ext)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.ncell_ext) return;
+    cnt_ext[e] = count[source_cell(e, g)];
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(int64_t n,
+                                                            const int32_t *__restrict__ in,
+                                                            int32_t *__restrict__ part)
+{
+    __shared__ int32_t red[SCAN_BLOCK / MDLJ_WAVE];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t e = base + (int64_t)k * SCAN_BLOCK + threadIdx.x;
+        if (e < n) s += in[e];
+    }
+    for (int o = MDLJ_WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0) red[threadIdx.x / MDLJ_WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < SCAN_BLOCK / MDLJ_WAVE; ++w) t += red[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the per-tile sums in one workgroup; writes the total.
+__global__ __launch_bounds__(1024) void k_scan_parts(int64_t nparts, int32_t *__restrict__ part,
+                                                     int32_t *__restrict__ total)
+{
+    __shared__ int32_t sums[1024];
+    int64_t per = ceil_div(nparts, 1024);
+    int64_t b = threadIdx.x * per;
+    int64_t e = b + per < nparts ? b + per : nparts;
+    int32_t s = 0;
+    for (int64_t k = b; k < e; ++k) s += part[k];
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            int32_t v = sums[t];
+            sums[t] = run;
+            run += v;
+        }
+        *total = run;
+    }
+    __syncthreads();
+    int32_t run = sums[threadIdx.x];
+    for (int64_t k = b; k < e; ++k) {
+        int32_t v = part[k];
+        part[k] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(int64_t n,
+                                                          const int32_t *__restrict__ in,
+                                                          const int32_t *__restrict__ part,
+                                                          int32_t *__restrict__ out)
+{
+    __shared__ int32_t wsum[SCAN_BLOCK / MDLJ_WAVE];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t e = base + k;
+        v[k] = e < n ? in[e] : 0;
+        s += v[k];
+    }
+    int lane = threadIdx.x & (MDLJ_WAVE - 1);
+    int32_t inc = s;
+    for (int o = 1; o < MDLJ_WAVE; o <<= 1) {
+        int32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == MDLJ_WAVE - 1) wsum[threadIdx.x / MDLJ_WAVE] = inc;
+    __syncthreads();
+    int32_t woff = 0;
+    for (int w = 0; w < (int)(threadIdx.x / MDLJ_WAVE); ++w) woff += wsum[w];
+    int32_t run = part[blockIdx.x] + woff + inc - s;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t e = base + k;
+        if (e < n) out[e] = run;
+        run += v[k];
+    }
+}
+
+__global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
+                          const int32_t *__restrict__ rank, const int32_t *__restrict__ start,
+                          int32_t *__restrict__ sorted_orig)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t e = cell_of[i];
+    if (e < 0) return;
+    sorted_orig[start[e] + rank[i]] = (int32_t)i;
+}
+
+__device__ __forceinline__ bool is_interior(int64_t e, const Grid &g)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int c = (int)((e / g.stride[a]) % g.e[a]) - g.h[a];
+        if (c < 0 || c >= g.n[a]) return false;
+    }
+    return true;
+}
+
+// Order every interior cell by caller index (insertion sort; cells are small).
+__global__ void k_order_cells(Grid g, const int32_t *__restrict__ start,
+                              int32_t *__restrict__ sorted_orig)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.ncell_ext || !is_interior(e, g)) return;
+    int32_t b = start[e], en = start[e + 1];
+    for (int32_t k = b + 1; k < en; ++k) {
+        int32_t v = sorted_orig[k];
+        int32_t m = k - 1;
+        while (m >= b && sorted_orig[m] > v) {
+            sorted_orig[m + 1] = sorted_orig[m];
+            --m;
+        }
+        sorted_orig[m + 1] = v;
+    }
+}
+
+// One wavefront per extended cell: interior cells gather their records,
+// halo cells copy the records of their source cell shifted by +-L.
+__global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict__ start,
+                                              int32_t *__restrict__ sorted_orig,
+                                              const double *__restrict__ x,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ z,
+                                              const int32_t *__restrict__ type,
+                                              PosT *__restrict__ rec,
+                                              int32_t *__restrict__ slot_of,
+                                              char4 *__restrict__ img)
+{
+    int64_t e = (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
+    int lane = threadIdx.x & (MDLJ_WAVE - 1);
+    if (e >= g.ncell_ext) return;
+    int32_t b = start[e], en = start[e + 1];
+    double sh[3];
+    signed char code[3];
+    int64_t src = 0;
+    bool interior = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int c = (int)((e / g.stride[a]) % g.e[a]) - g.h[a];
+        int s = c;
+        sh[a] = 0.0;
+        code[a] = 0;
+        if (c < 0) { s = c + g.n[a]; sh[a] = -g.L[a]; code[a] = -1; interior = false; }
+        if (c >= g.n[a]) { s = c - g.n[a]; sh[a] = g.L[a]; code[a] = 1; interior = false; }
+        src += (int64_t)(s + g.h[a]) * g.stride[a];
+    }
+    int32_t sb = start[src];
+    for (int32_t k = b + lane; k < en; k += MDLJ_WAVE) {
+        int32_t i = interior ? sorted_orig[k] : sorted_orig[sb + (k - b)];
+        PosT r;
+        r.x = x[i] + sh[0];
+        r.y = y[i] + sh[1];
+        r.z = z[i] + sh[2];
+        r.t = type[i];
+        r.orig = i;
+        rec[k] = r;
+        img[k] = make_char4(code[0], code[1], code[2], 0);
+        if (interior) slot_of[i] = k;
+        else sorted_orig[k] = i;
+    }
+}
+
+__global__ void k_unpermute(int64_t n, const int32_t *__restrict__ slot_of,
+                            const double *__restrict__ fx, const double *__restrict__ fy,
+                            const double *__restrict__ fz, double *__restrict__ ox,
+                            double *__restrict__ oy, double *__restrict__ oz)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t s = slot_of[i];
+    ox[i] = fx[s];
+    oy[i] = fy[s];
+    oz[i] = fz[s];
+}
+
+// Halo slots carry forces applied to images (Newton-3 kernels); add them
+// onto the slot of the particle they copy.
+__global__ void k_fold(int64_t n_ext, const PosT *__restrict__ rec,
+                       const int32_t *__restrict__ slot_of, double *__restrict__ fx,
+                       double *__restrict__ fy, double *__restrict__ fz)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_ext) return;
+    int32_t s = slot_of[rec[k].orig];
+    if (s == k) return;
+    atomicAdd(&fx[s], fx[k]);
+    atomicAdd(&fy[s], fy[k]);
+    atomicAdd(&fz[s], fz[k]);
+}
+
+__global__ void k_zero3(int64_t n, double *__restrict__ a, double *__restrict__ b,
+                        double *__restrict__ c)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    a[i] = 0.0;
+    b[i] = 0.0;
+    c[i] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(int64_t nb,
+                                                         const double *__restrict__ part,
+                                                         double *__restrict__ out)
+{
+    __shared__ double su[256], sw[256];
+    double u = 0, w = 0;
+    for (int64_t k = threadIdx.x; k < nb; k += 256) {
+        u += part[2 * k];
+        w += part[2 * k + 1];
+    }
+    su[threadIdx.x] = u;
+    sw[threadIdx.x] = w;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            su[threadIdx.x] += su[threadIdx.x + o];
+            sw[threadIdx.x] += sw[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = su[0];
+        out[1] = sw[0];
+    }
+}
+
+__global__ void k_finite(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                         const double *__restrict__ z, int32_t *__restrict__ flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i])) atomicOr(flag, 1);
+}
+
+__global__ void k_types(int64_t n, const int32_t *__restrict__ t, int32_t ns,
+                        int32_t *__restrict__ flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (t[i] < 0 || t[i] >= ns) atomicOr(flag, 1);
+}
+
+// Compact list of the real slots in sorted order (interior cells only).
+__global__ void k_int_counts(Grid g, const int32_t *__restrict__ count, int32_t *__restrict__ icnt)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell_int) return;
+    int cx = (int)(c % g.n[0]);
+    int cy = (int)((c / g.n[0]) % g.n[1]);
+    int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    int64_t e = (int64_t)(cx + g.h[0]) * g.stride[0] + (int64_t)(cy + g.h[1]) * g.stride[1] +
+                (int64_t)(cz + g.h[2]) * g.stride[2];
+    icnt[c] = count[e];
+}
+
+__global__ void k_ilist(Grid g, const int32_t *__restrict__ start, const int32_t *__restrict__ ibase,
+                        int32_t *__restrict__ ilist)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell_int) return;
+    int cx = (int)(c % g.n[0]);
+    int cy = (int)((c / g.n[0]) % g.n[1]);
+    int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    int64_t e = (int64_t)(cx + g.h[0]) * g.stride[0] + (int64_t)(cy + g.h[1]) * g.stride[1] +
+                (int64_t)(cz + g.h[2]) * g.stride[2];
+    int32_t b = start[e], en = start[e + 1], o = ibase[c];
+    for (int32_t k = b; k < en; ++k) ilist[o + (k - b)] = k;
+}
+
+}  // namespace
+
+mdlj_status exclusive_scan(mdlj_ctx *ctx, const int32_t *in, int32_t *out, int64_t n)
+{
+    int64_t nparts = ceil_div(n, SCAN_TILE);
+    STCHK(ensure(ctx, ctx->b_scan_part, sizeof(int32_t) * (nparts > 0 ? nparts : 1)));
+    int32_t *part = (int32_t *)ctx->b_scan_part.p;
+    hipStream_t s = ctx->stream;
+    if (n > 0) k_scan_reduce<<<nparts, SCAN_BLOCK, 0, s>>>(n, in, part);
+    k_scan_parts<<<1, 1024, 0, s>>>(nparts, part, out + n);
+    if (n > 0) k_scan_down<<<nparts, SCAN_BLOCK, 0, s>>>(n, in, part, out);
+    HIPCHK(ctx, hipGetLastError());
+    return MDLJ_OK;
+}
+
+mdlj_status build_ilist(mdlj_ctx *ctx)
+{
+    const Grid &g = ctx->grid;
+    STCHK(ensure(ctx, ctx->b_icnt, sizeof(int32_t) * (g.ncell_int + 1) * 2));
+    STCHK(ensure(ctx, ctx->b_ilist, sizeof(int32_t) * ctx->n));
+    int32_t *icnt = (int32_t *)ctx->b_icnt.p;
+    int32_t *ibase = icnt + g.ncell_int + 1;
+    const int TB = 256;
+    k_int_counts<<<ceil_div(g.ncell_int, TB), TB, 0, ctx->stream>>>(g, (const int32_t *)ctx->b_count.p,
+                                                                    icnt);
+    STCHK(exclusive_scan(ctx, icnt, ibase, g.ncell_int));
+    k_ilist<<<ceil_div(g.ncell_int, TB), TB, 0, ctx->stream>>>(g, (const int32_t *)ctx->b_start.p,
+                                                               ibase, (int32_t *)ctx->b_ilist.p);
+    HIPCHK(ctx, hipGetLastError());
+    return MDLJ_OK;
+}
+
+mdlj_status check_types(mdlj_ctx *ctx, bool *ok)
+{
+    STCHK(ensure(ctx, ctx->b_flags, sizeof(int32_t) * 64));
+    int32_t *flag = (int32_t *)ctx->b_flags.p + 9;
+    HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+    k_types<<<ceil_div(ctx->n, 256), 256, 0, ctx->stream>>>(ctx->n, ctx->type, ctx->nspec, flag);
+    HIPCHK(ctx, hipGetLastError());
+    int32_t h = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *ok = (h == 0);
+    return MDLJ_OK;
+}
+
+bool make_grid(const double *L, const double *r_min, const int *h, bool z_fastest, Grid *g)
+{
+    for (int a = 0; a < 3; ++a) {
+        int n = (int)floor(L[a] / r_min[a]);
+        if (n < 1) return false;
+        g->n[a] = n;
+        g->h[a] = h[a];
+        g->e[a] = n + 2 * h[a];
+        g->L[a] = L[a];
+        g->inv[a] = (double)n / L[a];
+        g->edge[a] = L[a] / (double)n;
+    }
+    if (z_fastest) {
+        g->stride[2] = 1;
+        g->stride[0] = g->e[2];
+        g->stride[1] = (int64_t)g->e[2] * g->e[0];
+    } else {
+        g->stride[0] = 1;
+        g->stride[1] = g->e[0];
+        g->stride[2] = (int64_t)g->e[0] * g->e[1];
+    }
+    g->ncell_ext = (int64_t)g->e[0] * g->e[1] * g->e[2];
+    g->ncell_int = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    return true;
+}
+
+mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
+{
+    const int64_t n = ctx->n;
+    if (g.ncell_ext >= (int64_t)1 << 31) return set_err(ctx, MDLJ_ERR_GEOMETRY, "too many cells");
+    STCHK(ensure(ctx, ctx->b_cell_of, sizeof(int32_t) * n));
+    STCHK(ensure(ctx, ctx->b_rank, sizeof(int32_t) * n));
+    STCHK(ensure(ctx, ctx->b_count, sizeof(int32_t) * g.ncell_ext));
+    STCHK(ensure(ctx, ctx->b_start, sizeof(int32_t) * (g.ncell_ext + 1)));
+    STCHK(ensure(ctx, ctx->b_slot_of, sizeof(int32_t) * n));
+    STCHK(ensure(ctx, ctx->b_flags, sizeof(int32_t) * 64));
+    STCHK(ensure(ctx, ctx->b_cnt_ext, sizeof(int32_t) * g.ncell_ext));
+    int32_t *count = (int32_t *)ctx->b_count.p;
+    int32_t *start = (int32_t *)ctx->b_start.p;
+    int32_t *flags = (int32_t *)ctx->b_flags.p;
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, hipMemsetAsync(count, 0, sizeof(int32_t) * g.ncell_ext, s));
+    HIPCHK(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, s));
+    const int TB = 256;
+    k_bin_count<<<ceil_div(n, TB), TB, 0, s>>>(n, ctx->x, ctx->y, ctx->z, g,
+                                                 (int32_t *)ctx->b_cell_of.p,
+                                                 (int32_t *)ctx->b_rank.p, count, flags);
+    k_ext_counts<<<ceil_div(g.ncell_ext, TB), TB, 0, s>>>(g, count, (int32_t *)ctx->b_cnt_ext.p);
+    HIPCHK(ctx, hipGetLastError());
+    STCHK(exclusive_scan(ctx, (const int32_t *)ctx->b_cnt_ext.p, start, g.ncell_ext));
+    HIPCHK(ctx, hipGetLastError());
+    int32_t host[2] = {0, 0};
+    HIPCHK(ctx, hipMemcpyAsync(&host[0], flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(&host[1], start + g.ncell_ext, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (host[0]) return set_err(ctx, MDLJ_ERR_NONFINITE, "non-finite particle position");
+    const int64_t n_ext = host[1];
+    if (n_ext < n) return set_err(ctx, MDLJ_ERR_HIP, "binning lost particles");
+    STCHK(ensure(ctx, ctx->b_sorted, sizeof(PosT) * n_ext));
+    STCHK(ensure(ctx, ctx->b_misc, sizeof(int32_t) * n_ext));
+    STCHK(ensure(ctx, ctx->b_img, sizeof(char4) * n_ext));
+    int32_t *sorted_orig = (int32_t *)ctx->b_misc.p;
+    k_scatter<<<ceil_div(n, TB), TB, 0, s>>>(n, (int32_t *)ctx->b_cell_of.p,
+                                              (int32_t *)ctx->b_rank.p, start, sorted_orig);
+    k_order_cells<<<ceil_div(g.ncell_ext, TB), TB, 0, s>>>(g, start, sorted_orig);
+    k_fill<<<ceil_div(g.ncell_ext, TB / MDLJ_WAVE), TB, 0, s>>>(
+        g, start, sorted_orig, ctx->x, ctx->y, ctx->z, ctx->type, (PosT *)ctx->b_sorted.p,
+        (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->grid = g;
+    ctx->n_ext = n_ext;
+    return MDLJ_OK;
+}
+
+mdlj_status unpermute_forces(mdlj_ctx *ctx, const ForceOut &fo, bool fold, double *ox,
+                             double *oy, double *oz)
+{
+    hipStream_t s = ctx->stream;
+    const int TB = 256;
+    if (fold)
+        k_fold<<<ceil_div(ctx->n_ext, TB), TB, 0, s>>>(ctx->n_ext, (const PosT *)ctx->b_sorted.p,
+                                                        (const int32_t *)ctx->b_slot_of.p, fo.fx,
+                                                        fo.fy, fo.fz);
+    k_unpermute<<<ceil_div(ctx->n, TB), TB, 0, s>>>(ctx->n, (const int32_t *)ctx->b_slot_of.p,
+                                                     fo.fx, fo.fy, fo.fz, ox, oy, oz);
+    HIPCHK(ctx, hipGetLastError());
+    return MDLJ_OK;
+}
+
+mdlj_status zero_forces(mdlj_ctx *ctx, const ForceOut &fo, int64_t nslots)
+{
+    const int TB = 256;
+    k_zero3<<<ceil_div(nslots, TB), TB, 0, ctx->stream>>>(nslots, fo.fx, fo.fy, fo.fz);
+    HIPCHK(ctx, hipGetLastError());
+    return MDLJ_OK;
+}
+
+mdlj_status reduce_partials(mdlj_ctx *ctx, const double *partial, int64_t nblocks,
+                            double *UW_host)
+{
+    double *out = (double *)ctx->b_flags.p + 16;  // bytes 128..143 of the flag block
+    k_reduce_partials<<<1, 256, 0, ctx->stream>>>(nblocks, partial, out);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipMemcpyAsync(UW_host, out, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MDLJ_OK;
+}
+
+mdlj_status check_finite(mdlj_ctx *ctx, const double *x, const double *y, const double *z,
+                         int64_t n, bool *ok)
+{
+    STCHK(ensure(ctx, ctx->b_flags, sizeof(int32_t) * 64));
+    int32_t *flag = (int32_t *)ctx->b_flags.p + 8;
+    HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+    k_finite<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(n, x, y, z, flag);
+    HIPCHK(ctx, hipGetLastError());
+    int32_t h = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *ok = (h == 0);
+    return MDLJ_OK;
+}

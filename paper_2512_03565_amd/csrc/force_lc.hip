@@ -1,0 +1,292 @@
+// force_lc.hip -- force kernels over linked cells (section 2.1.1) with the
+// interaction orders of section 4.1, mapped onto 64-lane wavefronts.
+//
+// Cells have edge >= rc, so a particle's partners lie in the 3x3x3 block
+// of cells around its own (halo cells included).  Cells are numbered x
+// fastest, so the three cells cx-1..cx+1 of one (dy, dz) row are one
+// contiguous run of sorted records: the candidate set of a cell is nine
+// contiguous runs.  Every pair is evaluated from both sides (no Newton-3),
+// which needs no atomics and no colouring of the domain.
+//
+// Orders:
+//   k_lc_ipl   VectorLength/1 (i-per-lane): each lane owns one i of an
+//              i-tile of K consecutive cells along x; the j-candidates of
+//              the tile (nine runs of K+2 cells) are staged 64 at a time in
+//              LDS and every lane reads the same j (LDS broadcast).  No
+//              reduction: each lane stores its own i (section 4.1.2).
+//   k_lc_tile  a_i x a_j lane grid, a_i * a_j = 64: a_i i's of one cell
+//              per step, a_j lanes per i striding over the concatenated
+//              nine runs; the a_j partial forces of an i are summed over
+//              their lanes at the end.  a_i = 1 is 1/VectorLength
+//              (wave-per-i), a_i = 2, 4 its split variants, a_i = 8, 16
+//              the cluster tiles (2/(VL/2)-, (VL/2)/2-like).
+#include "pair.h"
+
+namespace {
+
+template <typename T, bool E, bool MS>
+__global__ __launch_bounds__(64) void k_lc_ipl(const PosT *__restrict__ rec,
+                                               const int32_t *__restrict__ start, Grid g, int K,
+                                               int tiles_x, LJTable<T> tab, ForceOut fo,
+                                               int remap)
+{
+    __shared__ PosT js[MDLJ_WAVE];
+    __shared__ LdsTable<T> lt;
+    const int lane = threadIdx.x;
+    if (MS) lds_table_load(lt, tab, lane, MDLJ_WAVE);
+    const int64_t nb = gridDim.x;
+    const int64_t t = remap ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
+    const int tx = (int)(t % tiles_x);
+    const int64_t rr = t / tiles_x;
+    const int cy = (int)(rr % g.n[1]);
+    const int cz = (int)(rr / g.n[1]);
+    const int cx0 = tx * K;
+    const int ncx = min(K, g.n[0] - cx0);
+    const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
+                       cx0 + g.h[0];
+    const int ib = start[ei], ie = start[ei + ncx];
+    double bu = 0.0, bw = 0.0;
+    __syncthreads();
+    for (int i0 = ib; i0 < ie; i0 += MDLJ_WAVE) {
+        const int i = i0 + lane;
+        const bool act = i < ie;
+        const PosT pi = rec[act ? i : ib];
+        Acc a;
+        acc_zero(a);
+        for (int r = 0; r < 9; ++r) {
+            const int dy = r % 3 - 1, dz = r / 3 - 1;
+            const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
+                               (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx0 - 1 + g.h[0];
+            const int jb = start[ej], je = start[ej + ncx + 2];
+            for (int j0 = jb; j0 < je; j0 += MDLJ_WAVE) {
+                const int jn = min(MDLJ_WAVE, je - j0);
+                __syncthreads();
+                if (lane < jn) js[lane] = rec[j0 + lane];
+                __syncthreads();
+                for (int jj = 0; jj < jn; ++jj) {
+                    const PosT pj = js[jj];
+                    const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
+                    T fxp, fyp, fzp;
+                    lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, act && (j0 + jj) != i, p,
+                                  tab.rc2, a, fxp, fyp, fzp);
+                }
+            }
+        }
+        if (act) {
+            fo.fx[i] = a.fx;
+            fo.fy[i] = a.fy;
+            fo.fz[i] = a.fz;
+        }
+        if (E) {
+            bu += a.u;
+            bw += a.w;
+        }
+    }
+    if (E) wave_partial(bu, bw, 0.5, fo.partial, blockIdx.x);
+}
+
+template <typename T, bool E, bool MS, int AI>
+__global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
+                                                const int32_t *__restrict__ start, Grid g,
+                                                LJTable<T> tab, ForceOut fo, int remap)
+{
+    constexpr int AJ = MDLJ_WAVE / AI;
+    __shared__ int seg_b[9];
+    __shared__ int seg_c[10];
+    __shared__ LdsTable<T> lt;
+    const int lane = threadIdx.x;
+    if (MS) lds_table_load(lt, tab, lane, MDLJ_WAVE);
+    const int64_t nb = gridDim.x;
+    const int64_t c = remap ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
+    const int cx = (int)(c % g.n[0]);
+    const int cy = (int)((c / g.n[0]) % g.n[1]);
+    const int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
+                       cx + g.h[0];
+    const int ib = start[ei], ie = start[ei + 1];
+    if (lane < 9) {
+        const int dy = lane % 3 - 1, dz = lane / 3 - 1;
+        const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
+                           (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx - 1 + g.h[0];
+        seg_b[lane] = start[ej];
+        seg_c[lane + 1] = start[ej + 3] - start[ej];
+    }
+    __syncthreads();
+    if (lane == 0) {
+        seg_c[0] = 0;
+        for (int r = 0; r < 9; ++r) seg_c[r + 1] += seg_c[r];
+    }
+    __syncthreads();
+    const int C = seg_c[9];
+    const int ii = lane / AJ, jl = lane % AJ;
+    double bu = 0.0, bw = 0.0;
+    for (int i0 = ib; i0 < ie; i0 += AI) {
+        const int i = i0 + ii;
+        const bool act = i < ie;
+        const PosT pi = rec[act ? i : ib];
+        Acc a;
+        acc_zero(a);
+        int r = 0;
+        for (int k = jl; k < C; k += AJ) {
+            while (k >= seg_c[r + 1]) ++r;
+            const int j = seg_b[r] + (k - seg_c[r]);
+            const PosT pj = rec[j];
+            const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
+            T fxp, fyp, fzp;
+            lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, act && j != i, p, tab.rc2, a, fxp,
+                          fyp, fzp);
+        }
+        a.fx = seg_sum(a.fx, AJ);
+        a.fy = seg_sum(a.fy, AJ);
+        a.fz = seg_sum(a.fz, AJ);
+        if (act && jl == 0) {
+            fo.fx[i] = a.fx;
+            fo.fy[i] = a.fy;
+            fo.fz[i] = a.fz;
+        }
+        if (E) {
+            bu += a.u;
+            bw += a.w;
+        }
+    }
+    if (E) wave_partial(bu, bw, 0.5, fo.partial, blockIdx.x);
+}
+
+// Unordered pairs {i, j} with r < rc, each counted once (from the particle
+// with the smaller caller index), in FP64.
+__global__ __launch_bounds__(64) void k_lc_count(const PosT *__restrict__ rec,
+                                                 const int32_t *__restrict__ start, Grid g,
+                                                 double rc2,
+                                                 unsigned long long *__restrict__ out)
+{
+    __shared__ int seg_b[9];
+    __shared__ int seg_c[10];
+    const int lane = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int cx = (int)(c % g.n[0]);
+    const int cy = (int)((c / g.n[0]) % g.n[1]);
+    const int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
+                       cx + g.h[0];
+    const int ib = start[ei], ie = start[ei + 1];
+    if (lane < 9) {
+        const int dy = lane % 3 - 1, dz = lane / 3 - 1;
+        const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
+                           (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx - 1 + g.h[0];
+        seg_b[lane] = start[ej];
+        seg_c[lane + 1] = start[ej + 3] - start[ej];
+    }
+    __syncthreads();
+    if (lane == 0) {
+        seg_c[0] = 0;
+        for (int r = 0; r < 9; ++r) seg_c[r + 1] += seg_c[r];
+    }
+    __syncthreads();
+    const int C = seg_c[9];
+    unsigned long long cnt = 0;
+    for (int i = ib; i < ie; ++i) {
+        const PosT pi = rec[i];
+        int r = 0;
+        for (int k = lane; k < C; k += MDLJ_WAVE) {
+            while (k >= seg_c[r + 1]) ++r;
+            const PosT pj = rec[seg_b[r] + (k - seg_c[r])];
+            if (pj.orig <= pi.orig) continue;
+            const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+            if (dx * dx + dy * dy + dz * dz < rc2) ++cnt;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0 && cnt) atomicAdd(out, cnt);
+}
+
+template <typename T, bool E, bool MS>
+void launch_lc(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, ForceOut &fo,
+               int64_t *nblocks, int remap)
+{
+    const Grid &g = ctx->grid;
+    const PosT *rec = (const PosT *)ctx->b_sorted.p;
+    const int32_t *start = (const int32_t *)ctx->b_start.p;
+    hipStream_t s = ctx->stream;
+    if (cfg.order == MDLJ_ORD_I_PER_LANE) {
+        const int K = cfg.tile_i;
+        const int tiles_x = (int)ceil_div(g.n[0], K);
+        const int64_t nb = (int64_t)tiles_x * g.n[1] * g.n[2];
+        *nblocks = nb;
+        k_lc_ipl<T, E, MS><<<nb, 64, 0, s>>>(rec, start, g, K, tiles_x, tab, fo, remap);
+        return;
+    }
+    const int64_t nb = g.ncell_int;
+    *nblocks = nb;
+    switch (cfg.tile_i) {
+    case 1: k_lc_tile<T, E, MS, 1><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
+    case 2: k_lc_tile<T, E, MS, 2><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
+    case 4: k_lc_tile<T, E, MS, 4><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
+    case 8: k_lc_tile<T, E, MS, 8><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
+    case 16: k_lc_tile<T, E, MS, 16><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
+    default: *nblocks = -1;
+    }
+}
+
+template <typename T>
+mdlj_status lc_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
+                        int64_t *nblocks)
+{
+    LJTable<T> tab;
+    fill_table<T>(ctx, &tab);
+    const bool ms = ctx->nspec > 1;
+    const int remap = 1;
+    int64_t nb = 0;
+    if (energy) {
+        // partial buffer sized by the launch: one (U, W) per workgroup
+        const Grid &g = ctx->grid;
+        int64_t maxb = g.ncell_int;
+        STCHK(ensure(ctx, ctx->b_partial, sizeof(double) * 2 * maxb));
+        fo.partial = (double *)ctx->b_partial.p;
+        if (ms) launch_lc<T, true, true>(ctx, cfg, tab, fo, &nb, remap);
+        else launch_lc<T, true, false>(ctx, cfg, tab, fo, &nb, remap);
+    } else {
+        if (ms) launch_lc<T, false, true>(ctx, cfg, tab, fo, &nb, remap);
+        else launch_lc<T, false, false>(ctx, cfg, tab, fo, &nb, remap);
+    }
+    if (nb < 0) return set_err(ctx, MDLJ_ERR_ARG, "unsupported linked-cell tile shape");
+    HIPCHK(ctx, hipGetLastError());
+    *nblocks = nb;
+    return MDLJ_OK;
+}
+
+}  // namespace
+
+mdlj_status lc_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
+                      int64_t *nblocks)
+{
+    if (ctx->grid.h[0] != 1 || ctx->grid.stride[0] != 1)
+        return set_err(ctx, MDLJ_ERR_STATE, "linked-cell grid not built");
+    if (ctx->prec == MDLJ_PREC_F64) return lc_forces_t<double>(ctx, cfg, energy, fo, nblocks);
+    return lc_forces_t<float>(ctx, cfg, energy, fo, nblocks);
+}
+
+mdlj_status count_pairs_dev(mdlj_ctx *ctx, int64_t *out)
+{
+    // bin at the cutoff (as linked cells do) and count from the smaller index
+    double r = ctx->rc;
+    for (int a = 0; a < 3; ++a)
+        if (ctx->box[a] < 2.0 * r || floor(ctx->box[a] / r) < 3)
+            return set_err(ctx, MDLJ_ERR_GEOMETRY, "box too small for linked cells");
+    double rmin[3] = {r, r, r};
+    int h[3] = {1, 1, 1};
+    Grid g;
+    if (!make_grid(ctx->box, rmin, h, false, &g)) return set_err(ctx, MDLJ_ERR_GEOMETRY, "grid");
+    STCHK(bin_particles(ctx, g));
+    ctx->built = false;  // the current structure was replaced
+    STCHK(ensure(ctx, ctx->b_partial, sizeof(unsigned long long)));
+    unsigned long long *d = (unsigned long long *)ctx->b_partial.p;
+    HIPCHK(ctx, hipMemsetAsync(d, 0, sizeof(unsigned long long), ctx->stream));
+    k_lc_count<<<g.ncell_int, 64, 0, ctx->stream>>>((const PosT *)ctx->b_sorted.p,
+                                                   (const int32_t *)ctx->b_start.p, g, r * r, d);
+    HIPCHK(ctx, hipGetLastError());
+    unsigned long long h_cnt = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&h_cnt, d, sizeof h_cnt, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *out = (int64_t)h_cnt;
+    return MDLJ_OK;
+}

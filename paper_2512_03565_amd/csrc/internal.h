@@ -1,0 +1,174 @@
+// internal.h -- shared declarations of libmdlj (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mdlj.h"
+
+#define MDLJ_MAX_SPECIES 8
+#define MDLJ_WAVE 64
+
+// Sorted particle record: FP64 position, species and the caller index of
+// the particle (for a halo image: of the particle it copies).  32 bytes, so
+// a j-load is two 16-byte loads.
+struct __attribute__((aligned(32))) PosT {
+    double x, y, z;
+    int32_t t;
+    int32_t orig;
+};
+
+// Uniform grid over the box plus h halo layers per side.  Cell coordinate
+// c in [-h, n + h) maps to the extended index sum_a (c_a + h_a) * stride_a.
+// Halo cells hold periodic images of interior cells (shifted by +-L).
+struct Grid {
+    int n[3];
+    int h[3];
+    int e[3];
+    double L[3];
+    double inv[3];   // n / L, for the cell index
+    double edge[3];  // L / n
+    int64_t stride[3];
+    int64_t ncell_ext;
+    int64_t ncell_int;
+};
+
+// Pair-law table in the arithmetic type of the pair loop.  For pair type
+// index k = ti * ns + tj: sig2 = sigma^2, eps24 = 24 eps, eps4 = 4 eps,
+// shift = energy shift; rc2 = cutoff^2.
+template <typename T>
+struct LJTable {
+    T sig2[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
+    T eps24[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
+    T eps4[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
+    T shift[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
+    T rc2;
+    int ns;
+};
+
+// Output of a force kernel in sorted order: FP64 forces per slot and, when
+// energies are requested, one (U, W) pair per workgroup.
+struct ForceOut {
+    double *fx, *fy, *fz;
+    double *partial;  // [2 * nblocks] or nullptr
+};
+
+// Device buffers that grow on demand.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct mdlj_ctx {
+    hipStream_t stream = nullptr;
+    int64_t n = 0;
+    int nspec = 1;
+    double eps[MDLJ_MAX_SPECIES] = {0};
+    double sig[MDLJ_MAX_SPECIES] = {0};
+    double mass[MDLJ_MAX_SPECIES] = {1, 1, 1, 1, 1, 1, 1, 1};
+    bool species_set[MDLJ_MAX_SPECIES] = {false};
+    double box[3] = {0, 0, 0};
+    bool box_set = false;
+    double rc = 0;
+    double skin = 0;
+    int rebuild_every = 10;
+    int shift_on = 1;
+    int prec = MDLJ_PREC_F32PAIR_F64ACC;
+    mdlj_config cfg = {MDLJ_NBR_LC, MDLJ_ORD_I_PER_LANE, 1, 0, 0, 0};
+    std::string err;
+
+    // caller-order particle state (device)
+    double *x = nullptr, *y = nullptr, *z = nullptr;  // wrapped positions
+    int32_t *type = nullptr;
+    double *fx = nullptr, *fy = nullptr, *fz = nullptr;  // last forces, caller order
+    bool forces_valid = false;
+    bool pos_changed = true;      // positions changed since the last force call
+
+    // neighbour structure state
+    bool built = false;           // structure matches cfg/positions
+    mdlj_config built_cfg = {-1, -1, -1, -1, -1, -1};
+    int steps_since_build = 0;
+    double built_box[3] = {0, 0, 0};
+    double built_rc = -1, built_skin = -1;
+    Grid grid{};
+    int64_t n_ext = 0;            // real + halo slots
+    int64_t nbr_cap = 0;          // Verlet list capacity per particle
+    int64_t vl_max = 0;           // longest list of the last build
+
+    // named device buffers
+    DevBuf b_pos, b_type, b_force;  // caller-order state above
+    DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
+        b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
+        b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref;
+
+    // tuner state
+    std::vector<mdlj_config> space;
+    std::vector<double> tune_us;
+    // learned tuner
+    std::vector<float> mlp_w;
+    int mlp_k = 0;
+    double mlp_threshold = 0.6;
+    bool mlp_loaded = false;
+
+    // reusable host scratch
+    std::vector<double> h_partial;
+};
+
+// --- helpers implemented in api.cpp --------------------------------------
+mdlj_status set_err(mdlj_ctx *ctx, mdlj_status st, const std::string &msg);
+mdlj_status hip_check(mdlj_ctx *ctx, hipError_t e, const char *what);
+mdlj_status ensure(mdlj_ctx *ctx, DevBuf &b, size_t bytes);
+
+#define HIPCHK(ctx, call)                                      \
+    do {                                                       \
+        hipError_t _e = (call);                                \
+        if (_e != hipSuccess) return hip_check(ctx, _e, #call); \
+    } while (0)
+
+#define STCHK(call)                       \
+    do {                                  \
+        mdlj_status _s = (call);          \
+        if (_s != MDLJ_OK) return _s;     \
+    } while (0)
+
+// --- binning (bin.hip) ----------------------------------------------------
+// Bins the caller-order positions into g (wrapping them in place), writes
+// the sorted real + halo records and slot_of[i] (slot of caller particle i).
+mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g);
+// Sorted FP64 forces (slots [0, n_ext)) back to caller order; when fold is
+// set, halo slots are first added onto the slot of the particle they copy.
+mdlj_status unpermute_forces(mdlj_ctx *ctx, const ForceOut &fo, bool fold, double *ox,
+                             double *oy, double *oz);
+mdlj_status zero_forces(mdlj_ctx *ctx, const ForceOut &fo, int64_t nslots);
+// Sum of per-block (U, W) partials.
+mdlj_status reduce_partials(mdlj_ctx *ctx, const double *partial, int64_t nblocks,
+                            double *UW_host);
+mdlj_status check_types(mdlj_ctx *ctx, bool *ok);
+// Exclusive scan of n int32 counts; out[n] receives the total.
+mdlj_status exclusive_scan(mdlj_ctx *ctx, const int32_t *in, int32_t *out, int64_t n);
+// Compact list (length n) of the slots of real particles in sorted order.
+mdlj_status build_ilist(mdlj_ctx *ctx);
+mdlj_status check_finite(mdlj_ctx *ctx, const double *x, const double *y, const double *z,
+                         int64_t n, bool *ok);
+
+// --- force kernels ----------------------------------------------------------
+mdlj_status lc_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
+                      int64_t *nblocks);
+mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg);
+mdlj_status vl_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
+                      int64_t *nblocks);
+mdlj_status vcl_build(mdlj_ctx *ctx, const mdlj_config &cfg);
+mdlj_status vcl_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
+                       int64_t *nblocks);
+mdlj_status count_pairs_dev(mdlj_ctx *ctx, int64_t *out);
+
+// grid set-up shared by the containers: edge >= r_min per axis, h halo layers
+bool make_grid(const double *L, const double *r_min, const int *h, bool z_fastest, Grid *g);
+
+template <typename T>
+void fill_table(const mdlj_ctx *ctx, LJTable<T> *t);
+
+__host__ __device__ static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -1,0 +1,140 @@
+// pair.h -- the Lennard-Jones 12-6 pair interaction used by every force
+// kernel, in the pair arithmetic type T (float or double), accumulating
+// into FP64 per-lane sums.
+//
+// The pair force is F_ij = 24 eps s6 (2 s6 - 1) / r^2 * d, s6 = (sig^2/r^2)^3,
+// d = x_i - x_j, for r^2 < rc^2 (cutoff, section 2.1); pair energy
+// 4 eps s6 (s6 - 1) - shift and pair virial r.F = 24 eps s6 (2 s6 - 1).
+// The separation d is always formed in FP64 from FP64 positions and then
+// rounded once to T, so the FP32 path keeps |d| to half an FP32 ulp even in
+// large boxes; every later step runs in T.
+#pragma once
+
+#include "internal.h"
+
+template <typename T>
+__device__ __forceinline__ T rcp_t(T x);
+template <>
+__device__ __forceinline__ float rcp_t<float>(float x)
+{
+    return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ __forceinline__ double rcp_t<double>(double x)
+{
+    return 1.0 / x;
+}
+
+struct Acc {
+    double fx, fy, fz, u, w;
+};
+
+__device__ __forceinline__ void acc_zero(Acc &a) { a.fx = a.fy = a.fz = a.u = a.w = 0.0; }
+
+template <typename T>
+struct PairP {
+    T sig2, eps24, eps4, shift;
+};
+
+// Species table staged in LDS for multi-species kernels.
+template <typename T>
+struct LdsTable {
+    T sig2[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
+    T eps24[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
+    T eps4[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
+    T shift[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
+};
+
+template <typename T>
+__device__ __forceinline__ void lds_table_load(LdsTable<T> &s, const LJTable<T> &t, int tid,
+                                               int nthreads)
+{
+    for (int k = tid; k < t.ns * t.ns; k += nthreads) {
+        s.sig2[k] = t.sig2[k];
+        s.eps24[k] = t.eps24[k];
+        s.eps4[k] = t.eps4[k];
+        s.shift[k] = t.shift[k];
+    }
+}
+
+// Parameters of the (ti, tj) pair: from kernel arguments for one species,
+// from the LDS table otherwise.
+template <typename T, bool MS>
+__device__ __forceinline__ PairP<T> pair_params(const LJTable<T> &t, const LdsTable<T> &s, int ti,
+                                                int tj)
+{
+    PairP<T> p;
+    if (MS) {
+        int k = ti * t.ns + tj;
+        p.sig2 = s.sig2[k];
+        p.eps24 = s.eps24[k];
+        p.eps4 = s.eps4[k];
+        p.shift = s.shift[k];
+    } else {
+        p.sig2 = t.sig2[0];
+        p.eps24 = t.eps24[0];
+        p.eps4 = t.eps4[0];
+        p.shift = t.shift[0];
+    }
+    return p;
+}
+
+// One pair.  Returns the force on i in (fxp, fyp, fzp) (zero when the pair
+// is masked or outside the cutoff) and adds force, energy and virial to a.
+template <typename T, bool E>
+__device__ __forceinline__ void lj_pair(double pxi, double pyi, double pzi, double pxj,
+                                        double pyj, double pzj, bool valid, const PairP<T> &p,
+                                        T rc2, Acc &a, T &fxp, T &fyp, T &fzp)
+{
+    const T dx = (T)(pxi - pxj);
+    const T dy = (T)(pyi - pyj);
+    const T dz = (T)(pzi - pzj);
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    const bool in = valid && (r2 < rc2);
+    const T ir2 = in ? rcp_t<T>(r2) : T(0);
+    const T sr2 = p.sig2 * ir2;
+    const T s6 = sr2 * sr2 * sr2;
+    const T rf = p.eps24 * s6 * (T(2) * s6 - T(1));
+    const T fs = rf * ir2;
+    fxp = fs * dx;
+    fyp = fs * dy;
+    fzp = fs * dz;
+    a.fx += (double)fxp;
+    a.fy += (double)fyp;
+    a.fz += (double)fzp;
+    if (E) {
+        const T u = in ? p.eps4 * s6 * (s6 - T(1)) - p.shift : T(0);
+        a.u += (double)u;
+        a.w += (double)rf;
+    }
+}
+
+// Sum of v over the `width` consecutive lanes of a segment (width a power
+// of two <= 64), result in every lane of the segment.
+__device__ __forceinline__ double seg_sum(double v, int width)
+{
+    for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, MDLJ_WAVE);
+    return v;
+}
+
+// Workgroups are handed to the 8 XCDs round-robin; remap the block index so
+// each XCD works on one contiguous run of tiles (neighbouring tiles share
+// j-data, which then stays in one XCD's L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    const int64_t per = nb >> 3, rem = nb & 7;
+    const int64_t x = b & 7, k = b >> 3;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+// Energy/virial of the workgroup (one wavefront) into partial[2 * blk].
+__device__ __forceinline__ void wave_partial(double u, double w, double scale, double *partial,
+                                             int64_t blk)
+{
+    u = seg_sum(u, MDLJ_WAVE);
+    w = seg_sum(w, MDLJ_WAVE);
+    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0) {
+        partial[2 * blk] = scale * u;
+        partial[2 * blk + 1] = scale * w;
+    }
+}

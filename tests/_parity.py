@@ -1,0 +1,64 @@
+"""Parity metrics between the HIP path and the FP64 oracle.
+
+Force error norm (per particle, normalised so that particles whose net
+force nearly cancels are not over-weighted):
+
+    err_F = max_i ||F_i - F_i^ref|| / max(||F_i^ref||, F_rms^ref)
+
+Pairs whose squared distance sits within a few ulps of rc^2 may be counted
+inside the cutoff by one arithmetic and outside by the other; both answers
+are correct for that arithmetic.  For the particles of such pairs the
+allowed deviation is the summed magnitude of those pair forces (and
+energies/virials for the totals), computed by the oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+F32_BAND = 4 * 2.0 ** -24
+F64_BAND = 4 * 2.0 ** -53
+
+
+def frms(f):
+    return float(np.sqrt((f * f).sum(1).mean())) if len(f) else 0.0
+
+
+def boundary_slack(orc, pos, box, rc, eps, sig, types, shift, band):
+    """Per-particle force slack and total (U, W) slack from pairs within the
+    ambiguous band |r^2/rc^2 - 1| <= band."""
+    n = len(pos)
+    slack = np.zeros(n)
+    su = sw = 0.0
+    namb = 0
+    pi, pj, r2 = orc.pairs_within(pos, box, rc * np.sqrt(1.0 + 2 * band))
+    sel = np.abs(r2 / (rc * rc) - 1.0) <= band
+    eps = np.atleast_1d(eps)
+    sig = np.atleast_1d(sig)
+    for a, b, q in zip(pi[sel], pj[sel], r2[sel]):
+        ta = 0 if types is None else int(types[a])
+        tb = 0 if types is None else int(types[b])
+        e_ab, s_ab = orc.mix(eps[ta], sig[ta], eps[tb], sig[tb])
+        f, u, w = orc.lj_pair(q, e_ab, s_ab, rc, shift)
+        mag = abs(f) * np.sqrt(q) * (1 + 1e-6)
+        slack[a] += mag
+        slack[b] += mag
+        su += abs(u) * (1 + 1e-6)
+        sw += abs(w) * (1 + 1e-6)
+        namb += 1
+    return slack, su, sw, namb
+
+
+def force_error(f, ref, slack=None, idx=None, scale=None):
+    """err_F over the particles idx (all if None); scale overrides F_rms."""
+    d = np.linalg.norm(np.asarray(f) - np.asarray(ref), axis=1)
+    if slack is not None:
+        d = np.maximum(0.0, d - slack)
+    nr = np.linalg.norm(ref, axis=1)
+    s = frms(ref) if scale is None else scale
+    if len(d) == 0:
+        return 0.0
+    return float((d / np.maximum(nr, s)).max())
+
+
+def total_error(val, ref, slack=0.0):
+    return max(0.0, abs(val - ref) - slack) / max(abs(ref), 1e-300)
