@@ -205,18 +205,62 @@ mdlj_status mdlj_step_vv(mdlj_ctx *ctx, double *vx, double *vy, double *vz, doub
                          int32_t nsteps);
 mdlj_status mdlj_set_mass(mdlj_ctx *ctx, int32_t s, double mass);
 
+/* Kernel timing with HIP events on the context's stream.  on = 1 enables
+ * and resets the totals; while enabled every force evaluation synchronises
+ * after its force kernel.  get_timing returns the summed force-kernel and
+ * rebuild (binning + list build, or the per-step re-binning of linked
+ * cells) microseconds and how many of each were timed.  Outputs may be
+ * NULL. */
+mdlj_status mdlj_set_timing(mdlj_ctx *ctx, int32_t on);
+mdlj_status mdlj_get_timing(const mdlj_ctx *ctx, double *force_us, double *build_us,
+                            int64_t *n_force, int64_t *n_build);
+
 /* Eight scene features the learned tuner reads (log10 N, density,
  * rc / sigma_max, species count, expected neighbours within rc, cell
  * occupancy coefficient of variation, empty-cell fraction, max/mean cell
  * occupancy), computed on the device from the current positions. */
 mdlj_status mdlj_features(mdlj_ctx *ctx, float *features8);
 
-/* Learned tuner network (8 -> 64 -> 64 -> K).  load/save use a flat
- * little-endian float32 file; train runs `epochs` epochs of Adam on the
- * device over (features, best-config label) pairs given in host memory. */
+/*
+ * Learned tuner (data-driven tuning, section 6): a network 8 -> 64 -> 64 ->
+ * K (ReLU, softmax over the K configurations of config_at order), FP32,
+ * trained and evaluated on the device by the library's own kernels.
+ * Parameters are one flat float array W1[64][8] b1[64] W2[64][64] b2[64]
+ * W3[K][64] b3[K] (row-major [out][in]); inputs are z-scored with a stored
+ * mean and deviation per feature (set_norm; init sets 0 and 1).
+ *   init        He-normal weights from `seed`, zero biases, K classes (1..256).
+ *   set_norm    per-feature mean and standard deviation (> 0), 8 each.
+ *   get/set_params  copy the flat parameter array (count must match K).
+ *   predict     softmax probabilities [n][K] for n raw feature rows (host).
+ *   loss_grad   mean cross-entropy over n rows (used as network input as
+ *               given, no z-scoring) and its gradient [n_params] (host).
+ *   train       `epochs` passes of Adam (lr, beta 0.9/0.999, eps 1e-8) over
+ *               full minibatches of `batch` rows in a seeded shuffled order;
+ *               rows are raw features, z-scored with the stored values;
+ *               *final_loss = mean loss of the last epoch.
+ *   load/save   file "MDLJMLP1", int32 K, 8, 64, 64, float mean[8], std[8],
+ *               params (little-endian); MDLJ_ERR_NOTFOUND if unreadable.
+ *   set_threshold  confidence (largest probability) below which LEARNED
+ *               tuning falls back to full search; default 0.6.
+ *   stats       confidence of the last LEARNED decision and the number of
+ *               fallbacks so far.
+ * All feature/label/probability arrays are host memory.
+ */
+mdlj_status mdlj_mlp_init(mdlj_ctx *ctx, int32_t k, uint64_t seed);
+mdlj_status mdlj_mlp_set_norm(mdlj_ctx *ctx, const float *mean8, const float *std8);
+mdlj_status mdlj_mlp_get_params(const mdlj_ctx *ctx, float *w, int64_t cap, int64_t *count,
+                                int32_t *k);
+mdlj_status mdlj_mlp_set_params(mdlj_ctx *ctx, const float *w, int64_t count, int32_t k);
+mdlj_status mdlj_mlp_predict(mdlj_ctx *ctx, const float *x, int32_t n, float *probs);
+mdlj_status mdlj_mlp_loss_grad(mdlj_ctx *ctx, const float *x, const int32_t *labels, int32_t n,
+                               float *grad, float *loss);
+mdlj_status mdlj_mlp_train(mdlj_ctx *ctx, const float *x, const int32_t *labels, int32_t n,
+                           int32_t epochs, int32_t batch, double lr, uint64_t seed,
+                           double *final_loss);
 mdlj_status mdlj_mlp_load(mdlj_ctx *ctx, const char *path);
 mdlj_status mdlj_mlp_save(const mdlj_ctx *ctx, const char *path);
 mdlj_status mdlj_mlp_set_threshold(mdlj_ctx *ctx, double threshold);
+mdlj_status mdlj_mlp_stats(const mdlj_ctx *ctx, double *last_confidence, int64_t *fallbacks);
 
 /* Human-readable message of the last failing call on ctx ("" if none). */
 const char *mdlj_last_error(const mdlj_ctx *ctx);

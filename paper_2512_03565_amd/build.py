@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdlj.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["api.cpp", "bin.hip", "force_lc.hip", "pending.cpp"]
+SOURCES = ["api.cpp", "bin.hip", "force_lc.hip", "vl.hip", "vcl.hip", "integrate.hip", "tune.cpp", "mlp.hip"]
 ARCH = os.environ.get("MDLJ_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",

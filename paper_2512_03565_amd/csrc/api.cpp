@@ -187,6 +187,7 @@ static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
         STCHK(bin_particles(ctx, g));
         if (c.nbr_algo == MDLJ_NBR_VL) STCHK(vl_build(ctx, c));
     }
+    if (c.nbr_algo != MDLJ_NBR_LC) STCHK(save_reference(ctx));
     ctx->built = true;
     ctx->built_cfg = c;
     ctx->steps_since_build = 0;
@@ -217,8 +218,17 @@ mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed,
     *rebuilt = false;
     bool need = !structure_current(ctx, c);
     if (!need && positions_changed) {
-        if (c.nbr_algo == MDLJ_NBR_LC) need = true;
-        else if (ctx->steps_since_build >= ctx->rebuild_every) need = true;
+        if (c.nbr_algo == MDLJ_NBR_LC) {
+            need = true;
+        } else if (ctx->steps_since_build >= ctx->rebuild_every) {
+            need = true;
+        } else {
+            // lists stay exact while every particle moved less than skin/2
+            bool far = false;
+            STCHK(moved_too_far(ctx, &far));
+            if (far) need = true;
+            else STCHK(refresh_records(ctx));
+        }
     }
     if (need) {
         STCHK(rebuild(ctx, c));
@@ -245,6 +255,13 @@ mdlj_status run_force_kernel(mdlj_ctx *ctx, const mdlj_config &c, bool energy, F
     return set_err(ctx, MDLJ_ERR_ARG, "unknown neighbour algorithm");
 }
 
+// Newton-3 kernels over halo images leave forces on the images; cluster
+// lists use shift codes instead of images and need no fold.
+bool needs_fold(const mdlj_config &c)
+{
+    return c.newton3 != 0 && c.nbr_algo != MDLJ_NBR_VCL;
+}
+
 // The whole force evaluation for the current configuration into the
 // context's caller-order force arrays; optional totals.
 mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW)
@@ -253,12 +270,29 @@ mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW)
     if (!ready(ctx, &why)) return set_err(ctx, MDLJ_ERR_STATE, why);
     const mdlj_config c = ctx->cfg;
     bool rebuilt;
+    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     STCHK(prepare(ctx, c, positions_changed, &rebuilt));
     ForceOut fo;
     int64_t nb = 0;
     bool energy = UW != nullptr;
+    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
     STCHK(run_force_kernel(ctx, c, energy, fo, &nb));
-    STCHK(unpermute_forces(ctx, fo, c.newton3 != 0, ctx->fx, ctx->fy, ctx->fz));
+    if (ctx->timing) {
+        HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev[2]));
+        float tb = 0, tf = 0;
+        HIPCHK(ctx, hipEventElapsedTime(&tb, ctx->ev[0], ctx->ev[1]));
+        HIPCHK(ctx, hipEventElapsedTime(&tf, ctx->ev[1], ctx->ev[2]));
+        ctx->last_force_us = 1e3 * tf;
+        ctx->last_build_us = rebuilt ? 1e3 * tb : 0.0;
+        ctx->t_force_us += 1e3 * tf;
+        ctx->t_nforce++;
+        if (rebuilt) {
+            ctx->t_build_us += 1e3 * tb;
+            ctx->t_nbuild++;
+        }
+    }
+    STCHK(unpermute_forces(ctx, fo, needs_fold(c), ctx->fx, ctx->fy, ctx->fz));
     if (energy) STCHK(reduce_partials(ctx, fo.partial, nb, UW));
     ctx->steps_since_build++;
     ctx->forces_valid = true;
@@ -351,6 +385,8 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
 {
     if (!ctx) return MDLJ_OK;
     (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
     DevBuf *bufs[] = {&ctx->b_cell_of, &ctx->b_rank,    &ctx->b_count,   &ctx->b_start,
                       &ctx->b_slot_of, &ctx->b_sorted,  &ctx->b_scan_part, &ctx->b_fsorted,
                       &ctx->b_partial, &ctx->b_flags,   &ctx->b_nbr,     &ctx->b_nlen,
@@ -358,7 +394,7 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
                       &ctx->b_cpair,   &ctx->b_cstart,  &ctx->b_fold,
                       &ctx->b_pos,     &ctx->b_type,    &ctx->b_force,
                       &ctx->b_cnt_ext, &ctx->b_img,     &ctx->b_icnt,    &ctx->b_ilist,
-                      &ctx->b_xref};
+                      &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat};
     for (DevBuf *b : bufs) free_buf(*b);
     delete ctx;
     return MDLJ_OK;
@@ -532,6 +568,39 @@ mdlj_status mdlj_compute_forces(mdlj_ctx *ctx, double *fx, double *fy, double *f
     if (epot) *epot = UW[0];
     if (virial) *virial = UW[1];
     return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_timing(mdlj_ctx *ctx, int32_t on)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (on && !ctx->ev[0])
+        for (hipEvent_t &e : ctx->ev) HIPCHK(ctx, hipEventCreate(&e));
+    ctx->timing = on != 0;
+    ctx->t_force_us = ctx->t_build_us = 0;
+    ctx->t_nforce = ctx->t_nbuild = 0;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_get_timing(const mdlj_ctx *ctx, double *force_us, double *build_us,
+                            int64_t *n_force, int64_t *n_build)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (force_us) *force_us = ctx->t_force_us;
+    if (build_us) *build_us = ctx->t_build_us;
+    if (n_force) *n_force = ctx->t_nforce;
+    if (n_build) *n_build = ctx->t_nbuild;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_step_vv(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt,
+                         int32_t nsteps)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (!vx || !vy || !vz || nsteps < 0 || !(dt > 0) || !isfinite(dt))
+        return set_err(ctx, MDLJ_ERR_ARG, "bad velocities, time step or step count");
+    std::string why;
+    if (!ready(ctx, &why)) return set_err(ctx, MDLJ_ERR_STATE, why);
+    return vv_steps(ctx, vx, vy, vz, dt, nsteps);
 }
 
 mdlj_status mdlj_count_pairs(mdlj_ctx *ctx, int64_t *n_useful_pairs)

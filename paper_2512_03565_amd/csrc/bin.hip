@@ -283,7 +283,9 @@ __global__ void k_fold(int64_t n_ext, const PosT *__restrict__ rec,
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_ext) return;
-    int32_t s = slot_of[rec[k].orig];
+    const int32_t o = rec[k].orig;
+    if (o < 0) return;
+    int32_t s = slot_of[o];
     if (s == k) return;
     atomicAdd(&fx[s], fx[k]);
     atomicAdd(&fy[s], fy[k]);

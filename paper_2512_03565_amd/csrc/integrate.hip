@@ -1,0 +1,147 @@
+// integrate.hip -- velocity Verlet (the integrator the paper's background
+// names for turning forces into motion, section 2.1) and the upkeep of the
+// sorted records between neighbour-list rebuilds.
+//
+// Verlet and cluster lists stay valid while no particle has moved more
+// than skin/2 since they were built (section 2.1.1).  Between rebuilds the
+// sorted records keep their slots; only their coordinates are refreshed
+// from the caller-order positions, halo images with the same +-L shift as
+// at build time.  Positions are left unwrapped until the next rebuild.
+#include "internal.h"
+
+namespace {
+
+struct InvMass {
+    double v[MDLJ_MAX_SPECIES];
+};
+
+// v += F dt / (2m); x += v dt
+__global__ void k_kick_drift(int64_t n, double *__restrict__ x, double *__restrict__ y,
+                             double *__restrict__ z, double *__restrict__ vx,
+                             double *__restrict__ vy, double *__restrict__ vz,
+                             const double *__restrict__ fx, const double *__restrict__ fy,
+                             const double *__restrict__ fz, const int32_t *__restrict__ type,
+                             InvMass im, double dt)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = 0.5 * dt * im.v[type[i]];
+    const double ux = vx[i] + h * fx[i];
+    const double uy = vy[i] + h * fy[i];
+    const double uz = vz[i] + h * fz[i];
+    vx[i] = ux;
+    vy[i] = uy;
+    vz[i] = uz;
+    x[i] += dt * ux;
+    y[i] += dt * uy;
+    z[i] += dt * uz;
+}
+
+// v += F dt / (2m)
+__global__ void k_kick(int64_t n, double *__restrict__ vx, double *__restrict__ vy,
+                       double *__restrict__ vz, const double *__restrict__ fx,
+                       const double *__restrict__ fy, const double *__restrict__ fz,
+                       const int32_t *__restrict__ type, InvMass im, double dt)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = 0.5 * dt * im.v[type[i]];
+    vx[i] += h * fx[i];
+    vy[i] += h * fy[i];
+    vz[i] += h * fz[i];
+}
+
+// Sorted records from current positions: rec[k] = x[orig] + image * L.
+// Padding records (orig < 0) are left as they are.
+__global__ void k_refresh(int64_t n_ext, PosT *__restrict__ rec, const char4 *__restrict__ img,
+                          const double *__restrict__ x, const double *__restrict__ y,
+                          const double *__restrict__ z, double lx, double ly, double lz)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_ext) return;
+    const int32_t o = rec[k].orig;
+    if (o < 0) return;
+    const char4 c = img[k];
+    rec[k].x = x[o] + (double)c.x * lx;
+    rec[k].y = y[o] + (double)c.y * ly;
+    rec[k].z = z[o] + (double)c.z * lz;
+}
+
+// flag := 1 if any particle moved more than sqrt(thr2) since the reference
+__global__ void k_displacement(int64_t n, const double *__restrict__ x,
+                               const double *__restrict__ y, const double *__restrict__ z,
+                               const double *__restrict__ xr, double thr2,
+                               int32_t *__restrict__ flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dx = x[i] - xr[i], dy = y[i] - xr[n + i], dz = z[i] - xr[2 * n + i];
+    if (!(dx * dx + dy * dy + dz * dz <= thr2)) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+mdlj_status save_reference(mdlj_ctx *ctx)
+{
+    const int64_t n = ctx->n;
+    STCHK(ensure(ctx, ctx->b_xref, sizeof(double) * 3 * n));
+    double *xr = (double *)ctx->b_xref.p;
+    HIPCHK(ctx, hipMemcpyAsync(xr, ctx->x, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(xr + n, ctx->y, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(xr + 2 * n, ctx->z, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    return MDLJ_OK;
+}
+
+mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far)
+{
+    const int64_t n = ctx->n;
+    int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
+    HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+    const double h = 0.5 * ctx->skin;
+    k_displacement<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z,
+                                                             (const double *)ctx->b_xref.p, h * h,
+                                                             flag);
+    HIPCHK(ctx, hipGetLastError());
+    int32_t hf = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&hf, flag, sizeof hf, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *too_far = hf != 0;
+    return MDLJ_OK;
+}
+
+mdlj_status refresh_records(mdlj_ctx *ctx)
+{
+    k_refresh<<<ceil_div(ctx->n_ext, 256), 256, 0, ctx->stream>>>(
+        ctx->n_ext, (PosT *)ctx->b_sorted.p, (const char4 *)ctx->b_img.p, ctx->x, ctx->y, ctx->z,
+        ctx->box[0], ctx->box[1], ctx->box[2]);
+    HIPCHK(ctx, hipGetLastError());
+    return MDLJ_OK;
+}
+
+static InvMass inv_mass(const mdlj_ctx *ctx)
+{
+    InvMass im;
+    for (int s = 0; s < MDLJ_MAX_SPECIES; ++s) im.v[s] = 1.0 / ctx->mass[s];
+    return im;
+}
+
+mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt, int nsteps)
+{
+    const int64_t n = ctx->n;
+    const InvMass im = inv_mass(ctx);
+    const int TB = 256;
+    if (!ctx->forces_valid) STCHK(forces_internal(ctx, ctx->pos_changed, nullptr));
+    ctx->pos_changed = false;
+    for (int s = 0; s < nsteps; ++s) {
+        k_kick_drift<<<ceil_div(n, TB), TB, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z, vx, vy, vz,
+                                                              ctx->fx, ctx->fy, ctx->fz, ctx->type,
+                                                              im, dt);
+        HIPCHK(ctx, hipGetLastError());
+        STCHK(forces_internal(ctx, true, nullptr));
+        k_kick<<<ceil_div(n, TB), TB, 0, ctx->stream>>>(n, vx, vy, vz, ctx->fx, ctx->fy, ctx->fz,
+                                                        ctx->type, im, dt);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    return MDLJ_OK;
+}

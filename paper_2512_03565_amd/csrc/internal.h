@@ -97,24 +97,37 @@ struct mdlj_ctx {
     int64_t n_ext = 0;            // real + halo slots
     int64_t nbr_cap = 0;          // Verlet list capacity per particle
     int64_t vl_max = 0;           // longest list of the last build
+    int64_t vcl_cap = 0;          // cluster-pair list capacity per cluster
 
     // named device buffers
     DevBuf b_pos, b_type, b_force;  // caller-order state above
     DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
-        b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref;
+        b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat;
 
     // tuner state
     std::vector<mdlj_config> space;
     std::vector<double> tune_us;
     // learned tuner
-    std::vector<float> mlp_w;
+    std::vector<float> mlp_w, mlp_m, mlp_v;
+    float mlp_mean[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    float mlp_std[8] = {1, 1, 1, 1, 1, 1, 1, 1};
     int mlp_k = 0;
+    int mlp_adam_t = 0;
     double mlp_threshold = 0.6;
+    double mlp_last_conf = 0.0;
+    int64_t mlp_fallbacks = 0;
     bool mlp_loaded = false;
 
     // reusable host scratch
     std::vector<double> h_partial;
+
+    // kernel timing (HIP events on the context's stream)
+    bool timing = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    double t_force_us = 0, t_build_us = 0;
+    int64_t t_nforce = 0, t_nbuild = 0;
+    double last_force_us = 0, last_build_us = 0;
 };
 
 // --- helpers implemented in api.cpp --------------------------------------
@@ -153,6 +166,27 @@ mdlj_status exclusive_scan(mdlj_ctx *ctx, const int32_t *in, int32_t *out, int64
 mdlj_status build_ilist(mdlj_ctx *ctx);
 mdlj_status check_finite(mdlj_ctx *ctx, const double *x, const double *y, const double *z,
                          int64_t n, bool *ok);
+
+// --- integrator and record upkeep (integrate.hip) ---------------------------
+mdlj_status save_reference(mdlj_ctx *ctx);
+mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far);
+mdlj_status refresh_records(mdlj_ctx *ctx);
+mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt, int nsteps);
+
+// --- force evaluation (api.cpp) ---------------------------------------------
+// Bring the neighbour structure of c up to date for the current positions.
+mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed, bool *rebuilt);
+mdlj_status run_force_kernel(mdlj_ctx *ctx, const mdlj_config &c, bool energy, ForceOut &fo,
+                             int64_t *nblocks);
+// Full evaluation with the current configuration into ctx->fx/fy/fz
+// (caller order); UW (host, may be null) receives U and W.
+mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW);
+bool needs_fold(const mdlj_config &c);
+
+// --- tuning (tune.cpp, mlp.hip) ---------------------------------------------
+mdlj_status tune_exhaustive(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *best_us);
+mdlj_status tune_measure_current(mdlj_ctx *ctx, int samples, double *us);
+mdlj_status tune_learned(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *us);
 
 // --- force kernels ----------------------------------------------------------
 mdlj_status lc_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,

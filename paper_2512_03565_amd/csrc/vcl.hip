@@ -1,0 +1,520 @@
+// vcl.hip -- Verlet cluster lists (section 2.1.1, after Pall & Hess): the
+// particles are grouped into clusters of a fixed size M (4 or 8, cf. the
+// cluster-size study of section 5), and every cluster keeps a list of the
+// clusters whose bounding boxes lie within rc + skin, rebuilt every few
+// steps.  Neighbour lists are thereby multiples of M long (section 5).
+//
+// Clusters: the box is cut into xy columns of edge ~(M/rho)^(1/3) and thin
+// z slabs; binning sorts each column by slab, and each column is chunked
+// into clusters of M consecutive particles.  The last cluster of a column
+// is padded with dummy records placed far outside the box (distinct
+// positions, so dummy pairs fall outside the cutoff).
+//
+// Periodic images are handled per cluster pair: a list entry packs J (low
+// 26 bits) and an image code (high bits), the code naming the lattice shift (sx, sy, sz) in {-1,0,1}^3 that
+// is added to J's coordinates.  With Newton-3 an entry is kept only for
+// I < J, or I == J with a shift that is zero or lexicographically positive,
+// so each particle pair is computed once (section 4.1.3).
+//
+// Kernels:
+//   k_vcl_tile  cluster tile: 64 lanes = M i's of cluster I x (64/M) j's,
+//               i.e. one J (M = 8, 8x8) or four consecutive list entries
+//               (M = 4, 4x16) per step; i-forces summed over the j lanes at
+//               the end, j-forces (Newton-3) over the i lanes every step.
+//   k_vcl_ipl   i-per-lane: a lane owns one i; the M lanes of a cluster walk
+//               its list and read the M j's of each J in turn, so the j is
+//               the same for all lanes of the cluster (a broadcast load).
+#include "pair.h"
+
+namespace {
+
+constexpr int CODE_SHIFT = 26;
+constexpr int32_t J_MASK = (1 << CODE_SHIFT) - 1;
+constexpr double DUMMY_BASE = 1.0e7;
+constexpr double DUMMY_STEP = 64.0;
+
+__host__ __device__ inline int shift_code(int sx, int sy, int sz)
+{
+    return (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1);
+}
+
+struct ClusterGeom {
+    int M;
+    int ncx, ncy, nz;   // columns in x and y, slabs in z
+    double L[3];
+    double slab;        // slab height
+    int64_t nclu;
+    int hx, hy;         // columns to search on each side
+    double R2;          // (rc + skin)^2
+};
+
+// Per column: number of clusters.
+__global__ void k_col_counts(Grid g, const int32_t *__restrict__ start, int M,
+                             int32_t *__restrict__ ccount)
+{
+    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= (int64_t)g.n[0] * g.n[1]) return;
+    int cx = (int)(col % g.n[0]), cy = (int)(col / g.n[0]);
+    int64_t e0 = (int64_t)cx * g.stride[0] + (int64_t)cy * g.stride[1];
+    int32_t cnt = start[e0 + g.n[2]] - start[e0];
+    ccount[col] = (cnt + M - 1) / M;
+}
+
+// Per column (one wavefront): copy records into clusters, pad, bounding
+// boxes, slab range, column of each cluster and the particle -> slot map.
+__global__ __launch_bounds__(64) void k_make_clusters(
+    Grid g, const int32_t *__restrict__ start, const int32_t *__restrict__ cbase, int M,
+    const PosT *__restrict__ rec, PosT *__restrict__ crec, int32_t *__restrict__ slot_of,
+    double *__restrict__ bb, int32_t *__restrict__ slabr, int32_t *__restrict__ ccol)
+{
+    const int64_t col = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int cx = (int)(col % g.n[0]), cy = (int)(col / g.n[0]);
+    const int64_t e0 = (int64_t)cx * g.stride[0] + (int64_t)cy * g.stride[1];
+    const int32_t b = start[e0], en = start[e0 + g.n[2]];
+    const int32_t q0 = cbase[col], q1 = cbase[col + 1];
+    for (int32_t q = q0; q < q1; ++q) {
+        for (int m = lane; m < M; m += MDLJ_WAVE) {
+            const int32_t src = b + (q - q0) * M + m;
+            const int64_t dst = (int64_t)q * M + m;
+            if (src < en) {
+                const PosT r = rec[src];
+                crec[dst] = r;
+                slot_of[r.orig] = (int32_t)dst;
+            } else {
+                PosT d;
+                d.x = d.y = d.z = DUMMY_BASE + DUMMY_STEP * (double)dst;
+                d.t = 0;
+                d.orig = -1;
+                crec[dst] = d;
+            }
+        }
+    }
+    // bounding boxes and slab ranges: one lane per cluster
+    for (int32_t q = q0 + lane; q < q1; q += MDLJ_WAVE) {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        const int32_t s0 = b + (q - q0) * M;
+        const int32_t s1 = min(s0 + M, en);
+        for (int32_t k = s0; k < s1; ++k) {
+            const PosT r = rec[k];
+            lo[0] = fmin(lo[0], r.x); hi[0] = fmax(hi[0], r.x);
+            lo[1] = fmin(lo[1], r.y); hi[1] = fmax(hi[1], r.y);
+            lo[2] = fmin(lo[2], r.z); hi[2] = fmax(hi[2], r.z);
+        }
+        for (int a = 0; a < 3; ++a) {
+            bb[6 * (int64_t)q + a] = lo[a];
+            bb[6 * (int64_t)q + 3 + a] = hi[a];
+        }
+        // slab of the first and last member (records are sorted by slab)
+        int slab_first = (int)(rec[s0].z * g.inv[2]);
+        int slab_last = (int)(rec[s1 - 1].z * g.inv[2]);
+        slab_first = max(0, min(g.n[2] - 1, slab_first));
+        slab_last = max(0, min(g.n[2] - 1, slab_last));
+        slabr[2 * (int64_t)q] = slab_first;
+        slabr[2 * (int64_t)q + 1] = slab_last;
+        ccol[q] = (int32_t)col;
+    }
+}
+
+__device__ __forceinline__ double gap(double alo, double ahi, double blo, double bhi)
+{
+    const double d1 = blo - ahi, d2 = alo - bhi;
+    const double d = d1 > d2 ? d1 : d2;
+    return d > 0.0 ? d : 0.0;
+}
+
+// One thread per cluster I: all (J, shift) with bounding-box distance
+// < rc + skin, into row I of the list (row-major, capacity cap).
+__global__ void k_pair_search(ClusterGeom cg, const double *__restrict__ bb,
+                              const int32_t *__restrict__ slabr,
+                              const int32_t *__restrict__ ccol,
+                              const int32_t *__restrict__ cbase, int half, int32_t cap,
+                              int32_t *__restrict__ list, int32_t *__restrict__ len,
+                              int32_t *__restrict__ maxlen)
+{
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= cg.nclu) return;
+    double ilo[3], ihi[3];
+    for (int a = 0; a < 3; ++a) {
+        ilo[a] = bb[6 * I + a];
+        ihi[a] = bb[6 * I + 3 + a];
+    }
+    const int col = ccol[I];
+    const int cx = col % cg.ncx, cy = col / cg.ncx;
+    const double R = sqrt(cg.R2);
+    int32_t cnt = 0;
+    for (int dy = -cg.hy; dy <= cg.hy; ++dy) {
+        int ny = cy + dy;
+        int sy = 0;
+        while (ny < 0) { ny += cg.ncy; --sy; }
+        while (ny >= cg.ncy) { ny -= cg.ncy; ++sy; }
+        if (sy < -1 || sy > 1) continue;
+        for (int dx = -cg.hx; dx <= cg.hx; ++dx) {
+            int nx = cx + dx;
+            int sx = 0;
+            while (nx < 0) { nx += cg.ncx; --sx; }
+            while (nx >= cg.ncx) { nx -= cg.ncx; ++sx; }
+            if (sx < -1 || sx > 1) continue;
+            const int ncol = nx + cg.ncx * ny;
+            const int32_t q0 = cbase[ncol], q1 = cbase[ncol + 1];
+            if (q0 == q1) continue;
+            for (int sz = -1; sz <= 1; ++sz) {
+                const double shz = sz * cg.L[2];
+                const double wlo = ilo[2] - R - shz, whi = ihi[2] + R - shz;
+                if (whi < 0.0 || wlo > cg.L[2]) continue;
+                // first cluster whose last slab reaches the window (monotone key)
+                int32_t lo = q0, hi = q1;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if ((slabr[2 * (int64_t)mid + 1] + 1) * cg.slab < wlo) lo = mid + 1;
+                    else hi = mid;
+                }
+                for (int32_t q = lo; q < q1; ++q) {
+                    if (slabr[2 * (int64_t)q] * cg.slab > whi) break;
+                    const double shx = sx * cg.L[0], shy = sy * cg.L[1];
+                    const double gx = gap(ilo[0], ihi[0], bb[6 * (int64_t)q] + shx, bb[6 * (int64_t)q + 3] + shx);
+                    const double gy = gap(ilo[1], ihi[1], bb[6 * (int64_t)q + 1] + shy, bb[6 * (int64_t)q + 4] + shy);
+                    const double gz = gap(ilo[2], ihi[2], bb[6 * (int64_t)q + 2] + shz, bb[6 * (int64_t)q + 5] + shz);
+                    if (gx * gx + gy * gy + gz * gz >= cg.R2) continue;
+                    if (half) {
+                        if (q < I) continue;
+                        if (q == I) {
+                            // keep the zero shift and one of each +-shift pair
+                            const int code = shift_code(sx, sy, sz);
+                            if (code < 13) continue;
+                        }
+                    }
+                    if (cnt < cap)
+                        list[I * cap + cnt] = (int32_t)q | (shift_code(sx, sy, sz) << CODE_SHIFT);
+                    ++cnt;
+                }
+            }
+        }
+    }
+    len[I] = cnt;
+    atomicMax(maxlen, cnt);
+}
+
+__device__ __forceinline__ void decode(int32_t e, const double *L, int32_t &J, double &sx,
+                                       double &sy, double &sz)
+{
+    J = e & J_MASK;
+    const int code = (int)((uint32_t)e >> CODE_SHIFT);
+    sx = (double)(code % 3 - 1) * L[0];
+    sy = (double)((code / 3) % 3 - 1) * L[1];
+    sz = (double)(code / 9 - 1) * L[2];
+}
+
+struct BoxL {
+    double L[3];
+};
+
+// Cluster tile: M x (64/M) lanes; one wavefront per cluster I.
+template <typename T, bool E, bool MS, bool N3, int M>
+__global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
+                                                  const int32_t *__restrict__ list,
+                                                  const int32_t *__restrict__ len, int64_t nclu,
+                                                  int32_t cap, BoxL bl, LJTable<T> tab,
+                                                  ForceOut fo, int remap)
+{
+    constexpr int AJ = MDLJ_WAVE / M;    // j lanes per i
+    constexpr int JPS = AJ / M;          // list entries per step (1 for M=8, 4 for M=4)
+    __shared__ LdsTable<T> lt;
+    if (MS) {
+        lds_table_load(lt, tab, threadIdx.x, blockDim.x);
+        __syncthreads();
+    }
+    const int64_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t I = b * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
+    const int lane = threadIdx.x & (MDLJ_WAVE - 1);
+    const int a = lane / AJ;             // i within the cluster
+    const int bj = lane % AJ;            // j lane
+    const int eo = bj / M;               // which list entry of the step
+    const int m = bj % M;                // j within its cluster
+    Acc acc;
+    acc_zero(acc);
+    const bool live = I < nclu;
+    const int64_t islot = live ? I * M + a : 0;
+    const PosT pi = crec[islot];
+    const int32_t Ln = live ? len[I] : 0;
+    for (int32_t k0 = 0; k0 < Ln; k0 += JPS) {
+        const int32_t k = k0 + eo;
+        const bool ok = k < Ln;
+        int32_t J = 0;
+        double sx = 0, sy = 0, sz = 0;
+        if (ok) decode(list[I * cap + k], bl.L, J, sx, sy, sz);
+        const int64_t jslot = (int64_t)J * M + m;
+        const PosT pj = crec[jslot];
+        // self cluster without shift: skip the diagonal, and with Newton-3
+        // the lower triangle
+        const bool self0 = ok && J == I && sx == 0.0 && sy == 0.0 && sz == 0.0;
+        const bool valid = ok && !(self0 && (N3 ? m <= a : m == a));
+        const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
+        T fxp, fyp, fzp;
+        lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x + sx, pj.y + sy, pj.z + sz, valid, p, tab.rc2, acc, fxp,
+                      fyp, fzp);
+        if (N3) {
+            // -F on j summed over the M i-lanes that share it
+            double gx = -(double)fxp, gy = -(double)fyp, gz = -(double)fzp;
+            for (int o = AJ; o < MDLJ_WAVE; o <<= 1) {
+                gx += __shfl_xor(gx, o, MDLJ_WAVE);
+                gy += __shfl_xor(gy, o, MDLJ_WAVE);
+                gz += __shfl_xor(gz, o, MDLJ_WAVE);
+            }
+            if (a == 0 && ok) {
+                atomicAdd(&fo.fx[jslot], gx);
+                atomicAdd(&fo.fy[jslot], gy);
+                atomicAdd(&fo.fz[jslot], gz);
+            }
+        }
+    }
+    acc.fx = seg_sum(acc.fx, AJ);
+    acc.fy = seg_sum(acc.fy, AJ);
+    acc.fz = seg_sum(acc.fz, AJ);
+    if (live && bj == 0) {
+        if (N3) {
+            atomicAdd(&fo.fx[islot], acc.fx);
+            atomicAdd(&fo.fy[islot], acc.fy);
+            atomicAdd(&fo.fz[islot], acc.fz);
+        } else {
+            fo.fx[islot] = acc.fx;
+            fo.fy[islot] = acc.fy;
+            fo.fz[islot] = acc.fz;
+        }
+    }
+    if (E)
+        wave_partial(acc.u, acc.w, N3 ? 1.0 : 0.5, fo.partial,
+                     (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE);
+}
+
+// i-per-lane: 64/M clusters per wavefront, M lanes each.
+template <typename T, bool E, bool MS, bool N3, int M>
+__global__ __launch_bounds__(256) void k_vcl_ipl(const PosT *__restrict__ crec,
+                                                 const int32_t *__restrict__ list,
+                                                 const int32_t *__restrict__ len, int64_t nclu,
+                                                 int32_t cap, BoxL bl, LJTable<T> tab,
+                                                 ForceOut fo, int remap)
+{
+    __shared__ LdsTable<T> lt;
+    if (MS) {
+        lds_table_load(lt, tab, threadIdx.x, blockDim.x);
+        __syncthreads();
+    }
+    const int64_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t g = b * blockDim.x + threadIdx.x;  // global lane
+    const int64_t I = g / M;
+    const int a = (int)(g % M);
+    const bool live = I < nclu;
+    const int64_t islot = live ? I * M + a : 0;
+    const PosT pi = crec[islot];
+    const int32_t Ln = live ? len[I] : 0;
+    Acc acc;
+    acc_zero(acc);
+    for (int32_t k = 0; k < Ln; ++k) {
+        int32_t J;
+        double sx, sy, sz;
+        decode(list[I * cap + k], bl.L, J, sx, sy, sz);
+        const bool self0 = J == I && sx == 0.0 && sy == 0.0 && sz == 0.0;
+        for (int mm = 0; mm < M; ++mm) {
+            const int64_t jslot = (int64_t)J * M + mm;
+            const PosT pj = crec[jslot];
+            const bool valid = !(self0 && (N3 ? mm <= a : mm == a));
+            const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
+            T fxp, fyp, fzp;
+            lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x + sx, pj.y + sy, pj.z + sz, valid, p, tab.rc2,
+                          acc, fxp, fyp, fzp);
+            if (N3) {
+                double gx = -(double)fxp, gy = -(double)fyp, gz = -(double)fzp;
+                // sum over the M lanes of this cluster (they share j)
+                for (int o = 1; o < M; o <<= 1) {
+                    gx += __shfl_xor(gx, o, M);
+                    gy += __shfl_xor(gy, o, M);
+                    gz += __shfl_xor(gz, o, M);
+                }
+                if (a == 0) {
+                    atomicAdd(&fo.fx[jslot], gx);
+                    atomicAdd(&fo.fy[jslot], gy);
+                    atomicAdd(&fo.fz[jslot], gz);
+                }
+            }
+        }
+    }
+    if (live) {
+        if (N3) {
+            atomicAdd(&fo.fx[islot], acc.fx);
+            atomicAdd(&fo.fy[islot], acc.fy);
+            atomicAdd(&fo.fz[islot], acc.fz);
+        } else {
+            fo.fx[islot] = acc.fx;
+            fo.fy[islot] = acc.fy;
+            fo.fz[islot] = acc.fz;
+        }
+    }
+    if (E)
+        wave_partial(acc.u, acc.w, N3 ? 1.0 : 0.5, fo.partial,
+                     (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE);
+}
+
+template <typename T, bool E, bool MS, bool N3, int M>
+int64_t launch_vcl_m(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, ForceOut &fo,
+                     int remap)
+{
+    const int64_t nclu = ctx->n_ext / M;
+    const PosT *crec = (const PosT *)ctx->b_sorted.p;
+    const int32_t *list = (const int32_t *)ctx->b_nbr.p;
+    const int32_t *len = (const int32_t *)ctx->b_nlen.p;
+    const int32_t cap = (int32_t)ctx->nbr_cap;
+    BoxL bl = {{ctx->box[0], ctx->box[1], ctx->box[2]}};
+    hipStream_t s = ctx->stream;
+    const int TB = 256;
+    if (cfg.order == MDLJ_ORD_CLUSTER_TILE) {
+        const int64_t nb = ceil_div(nclu, TB / MDLJ_WAVE);
+        k_vcl_tile<T, E, MS, N3, M><<<nb, TB, 0, s>>>(crec, list, len, nclu, cap, bl, tab, fo, remap);
+        return nb * (TB / MDLJ_WAVE);
+    }
+    const int64_t nb = ceil_div(nclu * M, TB);
+    k_vcl_ipl<T, E, MS, N3, M><<<nb, TB, 0, s>>>(crec, list, len, nclu, cap, bl, tab, fo, remap);
+    return nb * (TB / MDLJ_WAVE);
+}
+
+template <typename T, bool E, bool MS>
+int64_t launch_vcl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, ForceOut &fo,
+                   int remap)
+{
+    const bool n3 = cfg.newton3 != 0;
+    if (cfg.cluster_size == 4)
+        return n3 ? launch_vcl_m<T, E, MS, true, 4>(ctx, cfg, tab, fo, remap)
+                  : launch_vcl_m<T, E, MS, false, 4>(ctx, cfg, tab, fo, remap);
+    if (cfg.cluster_size == 8)
+        return n3 ? launch_vcl_m<T, E, MS, true, 8>(ctx, cfg, tab, fo, remap)
+                  : launch_vcl_m<T, E, MS, false, 8>(ctx, cfg, tab, fo, remap);
+    return -1;
+}
+
+template <typename T>
+mdlj_status vcl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
+                         int64_t *nblocks)
+{
+    LJTable<T> tab;
+    fill_table<T>(ctx, &tab);
+    const bool ms = ctx->nspec > 1;
+    const int remap = 1;
+    if (cfg.newton3) STCHK(zero_forces(ctx, fo, ctx->n_ext));
+    int64_t nw;
+    if (energy) {
+        const int64_t maxw = ctx->n_ext + 64;
+        STCHK(ensure(ctx, ctx->b_partial, sizeof(double) * 2 * maxw));
+        fo.partial = (double *)ctx->b_partial.p;
+        nw = ms ? launch_vcl<T, true, true>(ctx, cfg, tab, fo, remap)
+                : launch_vcl<T, true, false>(ctx, cfg, tab, fo, remap);
+    } else {
+        nw = ms ? launch_vcl<T, false, true>(ctx, cfg, tab, fo, remap)
+                : launch_vcl<T, false, false>(ctx, cfg, tab, fo, remap);
+    }
+    if (nw < 0) return set_err(ctx, MDLJ_ERR_ARG, "unsupported cluster size");
+    HIPCHK(ctx, hipGetLastError());
+    *nblocks = nw;
+    return MDLJ_OK;
+}
+
+}  // namespace
+
+mdlj_status vcl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
+{
+    const int M = cfg.cluster_size;
+    if (M != 4 && M != 8) return set_err(ctx, MDLJ_ERR_ARG, "cluster size must be 4 or 8");
+    const double R = ctx->rc + ctx->skin;
+    const double vol = ctx->box[0] * ctx->box[1] * ctx->box[2];
+    const double rho = (double)ctx->n / vol;
+    // columns of roughly cubic clusters; slabs thin enough that a slab-sorted
+    // column is nearly z-sorted
+    double edge = cbrt((double)M / rho);
+    const double slab = fmin(0.5, 0.25 * edge);
+    double rmin[3] = {edge, edge, slab};
+    int h[3] = {0, 0, 0};
+    Grid g;
+    if (!make_grid(ctx->box, rmin, h, true, &g)) return set_err(ctx, MDLJ_ERR_GEOMETRY, "grid");
+    for (int a = 0; a < 3; ++a)
+        if (ctx->box[a] < 2.0 * R)
+            return set_err(ctx, MDLJ_ERR_GEOMETRY, "box edge shorter than twice rc + skin");
+    STCHK(bin_particles(ctx, g));
+    const int64_t ncol = (int64_t)g.n[0] * g.n[1];
+    STCHK(ensure(ctx, ctx->b_icnt, sizeof(int32_t) * (ncol + 1) * 2));
+    int32_t *ccount = (int32_t *)ctx->b_icnt.p;
+    int32_t *cbase = ccount + ncol + 1;
+    hipStream_t s = ctx->stream;
+    k_col_counts<<<ceil_div(ncol, 256), 256, 0, s>>>(g, (const int32_t *)ctx->b_start.p, M, ccount);
+    HIPCHK(ctx, hipGetLastError());
+    STCHK(exclusive_scan(ctx, ccount, cbase, ncol));
+    int32_t hnclu = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&hnclu, cbase + ncol, sizeof hnclu, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    const int64_t nclu = hnclu;
+    const int64_t nslot = nclu * M;
+    if (nslot >= ((int64_t)1 << CODE_SHIFT)) return set_err(ctx, MDLJ_ERR_OVERFLOW, "too many clusters");
+    // cluster records replace the binned records
+    STCHK(ensure(ctx, ctx->b_clu, sizeof(PosT) * (nslot > 0 ? nslot : 1)));
+    STCHK(ensure(ctx, ctx->b_cstart, sizeof(double) * 6 * (nclu > 0 ? nclu : 1)));
+    STCHK(ensure(ctx, ctx->b_cpair, sizeof(int32_t) * 3 * (nclu > 0 ? nclu : 1)));
+    int32_t *slabr = (int32_t *)ctx->b_cpair.p;
+    int32_t *ccol = slabr + 2 * nclu;
+    k_make_clusters<<<ncol, 64, 0, s>>>(g, (const int32_t *)ctx->b_start.p, cbase, M,
+                                        (const PosT *)ctx->b_sorted.p, (PosT *)ctx->b_clu.p,
+                                        (int32_t *)ctx->b_slot_of.p, (double *)ctx->b_cstart.p,
+                                        slabr, ccol);
+    HIPCHK(ctx, hipGetLastError());
+    // swap: the force path reads b_sorted as the record array
+    std::swap(ctx->b_sorted, ctx->b_clu);
+    ctx->n_ext = nslot;
+    STCHK(ensure(ctx, ctx->b_img, sizeof(char4) * (nslot > 0 ? nslot : 1)));
+    HIPCHK(ctx, hipMemsetAsync(ctx->b_img.p, 0, sizeof(char4) * (nslot > 0 ? nslot : 1), s));
+
+    ClusterGeom cg;
+    cg.M = M;
+    cg.ncx = g.n[0];
+    cg.ncy = g.n[1];
+    cg.nz = g.n[2];
+    for (int a = 0; a < 3; ++a) cg.L[a] = ctx->box[a];
+    cg.slab = g.edge[2];
+    cg.nclu = nclu;
+    cg.hx = (int)ceil(R / g.edge[0]);
+    cg.hy = (int)ceil(R / g.edge[1]);
+    // never visit a column twice with the same shift
+    cg.hx = std::min(cg.hx, (g.n[0] - 1) / 2 + 1);
+    cg.hy = std::min(cg.hy, (g.n[1] - 1) / 2 + 1);
+    cg.R2 = R * R;
+    const double est_pairs = rho * 4.18879020478639 * pow(R + edge, 3) / M;
+    int64_t cap = (int64_t)((cfg.newton3 ? 0.6 : 1.2) * est_pairs) + 16;
+    if (ctx->vcl_cap > cap && ctx->built_cfg.newton3 == cfg.newton3 &&
+        ctx->built_cfg.cluster_size == M)
+        cap = ctx->vcl_cap;
+    STCHK(ensure(ctx, ctx->b_nlen, sizeof(int32_t) * (nclu > 0 ? nclu : 1)));
+    int32_t *maxlen = (int32_t *)ctx->b_flags.p + 12;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        STCHK(ensure(ctx, ctx->b_nbr, sizeof(int32_t) * (nclu > 0 ? nclu : 1) * cap));
+        HIPCHK(ctx, hipMemsetAsync(maxlen, 0, sizeof(int32_t), s));
+        if (nclu > 0)
+            k_pair_search<<<ceil_div(nclu, 128), 128, 0, s>>>(
+                cg, (const double *)ctx->b_cstart.p, slabr, ccol, cbase, cfg.newton3 ? 1 : 0,
+                (int32_t)cap, (int32_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen);
+        HIPCHK(ctx, hipGetLastError());
+        int32_t hmax = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&hmax, maxlen, sizeof hmax, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        ctx->vl_max = hmax;
+        if (hmax <= cap) {
+            ctx->vcl_cap = cap;
+            ctx->nbr_cap = cap;
+            return MDLJ_OK;
+        }
+        cap = (int64_t)(hmax * 1.1) + 8;
+    }
+    return set_err(ctx, MDLJ_ERR_OVERFLOW, "cluster list capacity could not be grown");
+}
+
+mdlj_status vcl_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
+                       int64_t *nblocks)
+{
+    if (ctx->prec == MDLJ_PREC_F64) return vcl_forces_t<double>(ctx, cfg, energy, fo, nblocks);
+    return vcl_forces_t<float>(ctx, cfg, energy, fo, nblocks);
+}

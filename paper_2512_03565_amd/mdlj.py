@@ -62,6 +62,12 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2512_03565_amd/build.py "
                       "(there is no CPU fallback)")
 
+# torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+# Loading torch first makes libmdlj bind to that runtime, so the process
+# holds one HIP runtime and torch streams and tensors are valid handles for
+# the library.  Loading libmdlj first would pull in a second runtime.
+import torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 _vp = C.c_void_p
 _d = C.POINTER(C.c_double)
@@ -93,6 +99,8 @@ _SIGS = {
     "mdlj_mlp_load": [_ctxp, C.c_char_p],
     "mdlj_mlp_save": [_ctxp, C.c_char_p],
     "mdlj_mlp_set_threshold": [_ctxp, C.c_double],
+    "mdlj_set_timing": [_ctxp, C.c_int32],
+    "mdlj_get_timing": [_ctxp, _d, _d, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(lib, _name)
@@ -288,6 +296,17 @@ class System:
             raise ValueError("velocities must be device tensors")
         check(lib.mdlj_step_vv(self.ctx, ptrs[0][0], ptrs[1][0], ptrs[2][0], float(dt),
                                int(nsteps)), self.ctx)
+
+    def set_timing(self, on=True):
+        check(lib.mdlj_set_timing(self.ctx, int(bool(on))), self.ctx)
+
+    def get_timing(self):
+        """(force_us_total, build_us_total, n_force, n_build) since set_timing."""
+        f, b = C.c_double(), C.c_double()
+        nf, nb = C.c_int64(), C.c_int64()
+        check(lib.mdlj_get_timing(self.ctx, C.byref(f), C.byref(b), C.byref(nf), C.byref(nb)),
+              self.ctx)
+        return f.value, b.value, nf.value, nb.value
 
     def features(self):
         f = (C.c_float * 8)()

@@ -1,0 +1,113 @@
+"""GPU parity of the Verlet-list kernels, the list upkeep between rebuilds
+(refresh while every particle moved < skin/2, early rebuild otherwise) and
+the velocity-Verlet integrator, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_2512_03565_amd import scenes
+from tests import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-5, 1: 1e-12}
+
+
+@pytest.fixture(scope="module")
+def m():
+    from paper_2512_03565_amd import mdlj
+    return mdlj
+
+
+def vl_configs(m):
+    out = []
+    for n3 in (0, 1):
+        out.append((m.NBR_VL, m.ORD_I_PER_LANE, 0, 0, 0, n3))
+        out += [(m.NBR_VL, m.ORD_WAVE_PER_I, g, 64 // g, 0, n3) for g in (1, 2, 4)]
+    return out
+
+
+def check(m, orc, s, configs, label, precs=(0, 1), skin=0.3):
+    pos, box, rc = s["pos"], s["box"], s["rc"]
+    types = s["types"] if len(s["eps"]) > 1 else None
+    ref = orc.forces(pos, box, rc, s["eps"], s["sig"], types)
+    with m.System(pos, box, rc, s["eps"], s["sig"], types=types, skin=skin) as sysm:
+        for prec in precs:
+            sysm.set_precision(prec)
+            band = P.F32_BAND if prec == 0 else P.F64_BAND
+            slack, su, sw, namb = P.boundary_slack(orc, pos, box, rc, s["eps"], s["sig"], types,
+                                                   True, band)
+            for cfg in configs:
+                print(f"[vl parity] {label} prec={prec} cfg={cfg}", flush=True)
+                sysm.set_config(cfg)
+                f, U, W = sysm.forces()
+                e = P.force_error(f, ref["f"], slack)
+                assert e <= TOL[prec], (cfg, prec, e, namb)
+                assert P.total_error(U, ref["U"], su) <= TOL[prec], (cfg, prec, U, ref["U"])
+                assert P.total_error(W, ref["W"], sw) <= TOL[prec], (cfg, prec, W, ref["W"])
+
+
+def test_vl_config1(m, orc):
+    check(m, orc, scenes.config1(), vl_configs(m), "cfg1")
+
+
+def test_vl_two_species(m, orc):
+    check(m, orc, scenes.config4(ncell=12), vl_configs(m), "2-species")
+
+
+def test_vl_config2_100k(m, orc):
+    check(m, orc, scenes.config2(), vl_configs(m), "cfg2")
+
+
+def test_vl_zero_skin_equals_cutoff_lists(m, orc):
+    check(m, orc, scenes.config1(), vl_configs(m)[:2], "skin0", skin=0.0)
+
+
+def test_vl_refresh_and_early_rebuild(m, orc):
+    s = scenes.config2()
+    pos, box, rc = s["pos"], s["box"], s["rc"]
+    rng = np.random.default_rng(31)
+    with m.System(pos, box, rc, skin=0.3, rebuild_every=1000, precision=1) as sysm:
+        for cfg in ((m.NBR_VL, m.ORD_I_PER_LANE, 0, 0, 0, 0),
+                    (m.NBR_VL, m.ORD_WAVE_PER_I, 2, 32, 0, 1)):
+            sysm.set_config(cfg)
+            sysm.set_positions(pos)
+            sysm.set_timing(True)
+            sysm.forces()
+            # small moves (< skin/2): records are refreshed, the lists kept
+            moved = pos + rng.uniform(-0.08, 0.08, pos.shape)
+            sysm.set_positions(moved)
+            f, U, W = sysm.forces()
+            _, _, nf, nb = sysm.get_timing()
+            assert (nf, nb) == (2, 1), (cfg, nf, nb)
+            ref = orc.forces(moved, box, rc)
+            assert P.force_error(f, ref["f"]) <= 1e-12, cfg
+            # one particle moves by 0.2 > skin/2: the lists must be rebuilt
+            moved2 = moved.copy()
+            moved2[123] = pos[123] + np.array([0.2, 0.0, 0.0])
+            sysm.set_positions(moved2)
+            f, U, W = sysm.forces()
+            _, _, nf, nb = sysm.get_timing()
+            assert (nf, nb) == (3, 2), (cfg, nf, nb)
+            ref = orc.forces(moved2, box, rc)
+            assert P.force_error(f, ref["f"]) <= 1e-12, cfg
+
+
+@pytest.mark.parametrize("cfg", [(0, 0, 1, 1, 0, 0), (0, 2, 2, 32, 0, 0), (1, 0, 0, 0, 0, 0),
+                                 (1, 2, 1, 64, 0, 1)])
+def test_velocity_verlet_trajectory_matches_oracle(m, orc, cfg):
+    import torch
+    s = scenes.config1()
+    p_ref, v_ref, f_ref, ep, ek = orc.vv(s["pos"], s["vel"], s["box"], s["rc"], s["dt"], 10)
+    with m.System(s["pos"], s["box"], s["rc"], skin=0.3, rebuild_every=4, precision=1) as sysm:
+        sysm.set_config(cfg)
+        vel = [torch.tensor(np.ascontiguousarray(s["vel"][:, k]), device="cuda") for k in range(3)]
+        sysm.step_vv(vel, s["dt"], 10)
+        f, U, W = sysm.forces()
+        pos = sysm.get_positions()
+    v = torch.stack(vel, 1).cpu().numpy()
+    d = pos - p_ref
+    d -= s["box"] * np.rint(d / s["box"])
+    assert np.abs(d).max() < 1e-10, cfg
+    assert np.abs(v - v_ref).max() < 1e-9, cfg
+    assert P.force_error(f, f_ref) < 1e-9, cfg
+    assert U == pytest.approx(ep[-1], rel=1e-10)
