@@ -64,6 +64,7 @@ void fill_table(const mdlj_ctx *ctx, LJTable<T> *t)
     int ns = ctx->nspec;
     t->ns = ns;
     t->rc2 = (T)(ctx->rc * ctx->rc);
+    t->rc2d = ctx->rc * ctx->rc;
     for (int a = 0; a < ns; ++a)
         for (int b = 0; b < ns; ++b) {
             // Lorentz-Berthelot mixing
@@ -102,7 +103,7 @@ static std::vector<mdlj_config> build_space()
     // Verlet lists
     for (int n3 : {0, 1}) {
         v.push_back({MDLJ_NBR_VL, MDLJ_ORD_I_PER_LANE, 0, 0, 0, n3});
-        for (int g : {1, 2, 4}) v.push_back({MDLJ_NBR_VL, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, n3});
+        for (int g : {1, 2, 4, 8}) v.push_back({MDLJ_NBR_VL, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, n3});
     }
     // Verlet cluster lists
     for (int m : {4, 8})

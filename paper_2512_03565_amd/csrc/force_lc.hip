@@ -24,6 +24,9 @@
 
 namespace {
 
+// candidates per trip of the tile loops
+constexpr int UNROLL = 4;
+
 template <typename T, bool E, bool MS>
 __global__ __launch_bounds__(64) void k_lc_ipl(const PosT *__restrict__ rec,
                                                const int32_t *__restrict__ start, Grid g, int K,
@@ -32,6 +35,7 @@ __global__ __launch_bounds__(64) void k_lc_ipl(const PosT *__restrict__ rec,
 {
     __shared__ PosT js[MDLJ_WAVE];
     __shared__ LdsTable<T> lt;
+    const double rc2 = tab.rc2d;
     const int lane = threadIdx.x;
     if (MS) lds_table_load(lt, tab, lane, MDLJ_WAVE);
     const int64_t nb = gridDim.x;
@@ -66,9 +70,9 @@ __global__ __launch_bounds__(64) void k_lc_ipl(const PosT *__restrict__ rec,
                 for (int jj = 0; jj < jn; ++jj) {
                     const PosT pj = js[jj];
                     const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
-                    T fxp, fyp, fzp;
+                    double fxp, fyp, fzp;
                     lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, act && (j0 + jj) != i, p,
-                                  tab.rc2, a, fxp, fyp, fzp);
+                                  rc2, a, fxp, fyp, fzp);
                 }
             }
         }
@@ -94,6 +98,7 @@ __global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
     __shared__ int seg_b[9];
     __shared__ int seg_c[10];
     __shared__ LdsTable<T> lt;
+    const double rc2 = tab.rc2d;
     const int lane = threadIdx.x;
     if (MS) lds_table_load(lt, tab, lane, MDLJ_WAVE);
     const int64_t nb = gridDim.x;
@@ -127,14 +132,28 @@ __global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
         Acc a;
         acc_zero(a);
         int r = 0;
-        for (int k = jl; k < C; k += AJ) {
-            while (k >= seg_c[r + 1]) ++r;
-            const int j = seg_b[r] + (k - seg_c[r]);
-            const PosT pj = rec[j];
-            const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
-            T fxp, fyp, fzp;
-            lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, act && j != i, p, tab.rc2, a, fxp,
-                          fyp, fzp);
+        // U candidates per trip: their record loads are in flight together
+        for (int k0 = jl; k0 < C; k0 += UNROLL * AJ) {
+            int jj[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const int k = k0 + u * AJ;
+                jj[u] = -1;
+                if (k < C) {
+                    while (k >= seg_c[r + 1]) ++r;
+                    jj[u] = seg_b[r] + (k - seg_c[r]);
+                }
+            }
+            PosT pj[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) pj[u] = rec[jj[u] >= 0 ? jj[u] : ib];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj[u].t);
+                double fxp, fyp, fzp;
+                lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x, pj[u].y, pj[u].z,
+                              act && jj[u] >= 0 && jj[u] != i, p, rc2, a, fxp, fyp, fzp);
+            }
         }
         a.fx = seg_sum(a.fx, AJ);
         a.fy = seg_sum(a.fy, AJ);

@@ -46,6 +46,7 @@ struct LJTable {
     T eps4[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
     T shift[MDLJ_MAX_SPECIES * MDLJ_MAX_SPECIES];
     T rc2;
+    double rc2d;  // cutoff^2 in FP64: the in/out decision is taken on FP64 r^2
     int ns;
 };
 

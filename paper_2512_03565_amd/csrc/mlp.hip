@@ -185,6 +185,7 @@ __global__ void k_feat_count(int64_t n, const double *__restrict__ x, const doub
                              const double *__restrict__ z, int nx, int ny, int nz, double lx,
                              double ly, double lz, int32_t *__restrict__ cnt)
 {
+#pragma clang fp contract(off)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double p[3] = {x[i], y[i], z[i]};
@@ -192,8 +193,11 @@ __global__ void k_feat_count(int64_t n, const double *__restrict__ x, const doub
     const int nn[3] = {nx, ny, nz};
     int c[3];
     for (int a = 0; a < 3; ++a) {
-        double w = p[a] - L[a] * floor(p[a] / L[a]);
-        int k = (int)(w * (double)nn[a] / L[a]);
+        const double q = floor(p[a] / L[a]);
+        const double m = L[a] * q;
+        const double w = p[a] - m;
+        const double inv = (double)nn[a] / L[a];
+        int k = (int)(w * inv);
         c[a] = k < 0 ? 0 : (k >= nn[a] ? nn[a] - 1 : k);
     }
     atomicAdd(&cnt[c[0] + (int64_t)nx * (c[1] + (int64_t)ny * c[2])], 1);

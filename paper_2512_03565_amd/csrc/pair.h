@@ -5,9 +5,9 @@
 // The pair force is F_ij = 24 eps s6 (2 s6 - 1) / r^2 * d, s6 = (sig^2/r^2)^3,
 // d = x_i - x_j, for r^2 < rc^2 (cutoff, section 2.1); pair energy
 // 4 eps s6 (s6 - 1) - shift and pair virial r.F = 24 eps s6 (2 s6 - 1).
-// The separation d is always formed in FP64 from FP64 positions and then
-// rounded once to T, so the FP32 path keeps |d| to half an FP32 ulp even in
-// large boxes; every later step runs in T.
+// The separation d and r^2 are formed in FP64 from FP64 positions, so the
+// FP32 path keeps full accuracy of d even in large boxes; the pair law
+// itself (reciprocal, powers, force factor, energy) runs in T.
 #pragma once
 
 #include "internal.h"
@@ -79,33 +79,39 @@ __device__ __forceinline__ PairP<T> pair_params(const LJTable<T> &t, const LdsTa
     return p;
 }
 
-// One pair.  Returns the force on i in (fxp, fyp, fzp) (zero when the pair
-// is masked or outside the cutoff) and adds force, energy and virial to a.
+// One pair.  The separation d and r^2 are formed in FP64 (exact inputs, so
+// |d| carries no more than binary64 rounding); the cutoff decision is taken
+// on the FP64 r^2.  The pair law (reciprocal, s6, force factor, energy) runs
+// in T.  The force factor is widened once and the force accumulated as
+// F += fs * d with FP64 fused multiply-adds, which on this hardware issue
+// at the FP32 rate.  Returns the force on i in (fxp, fyp, fzp) (zero when
+// masked or outside the cutoff).
 template <typename T, bool E>
 __device__ __forceinline__ void lj_pair(double pxi, double pyi, double pzi, double pxj,
                                         double pyj, double pzj, bool valid, const PairP<T> &p,
-                                        T rc2, Acc &a, T &fxp, T &fyp, T &fzp)
+                                        double rc2, Acc &a, double &fxp, double &fyp, double &fzp)
 {
-    const T dx = (T)(pxi - pxj);
-    const T dy = (T)(pyi - pyj);
-    const T dz = (T)(pzi - pzj);
-    const T r2 = dx * dx + dy * dy + dz * dz;
-    const bool in = valid && (r2 < rc2);
-    const T ir2 = in ? rcp_t<T>(r2) : T(0);
+    const double dx = pxi - pxj;
+    const double dy = pyi - pyj;
+    const double dz = pzi - pzj;
+    const double r2d = dx * dx + dy * dy + dz * dz;
+    const bool in = valid && (r2d < rc2);
+    const T r2 = (T)r2d;
+    const T ir2 = rcp_t<T>(r2);
     const T sr2 = p.sig2 * ir2;
     const T s6 = sr2 * sr2 * sr2;
     const T rf = p.eps24 * s6 * (T(2) * s6 - T(1));
-    const T fs = rf * ir2;
+    const double fs = in ? (double)(rf * ir2) : 0.0;
     fxp = fs * dx;
     fyp = fs * dy;
     fzp = fs * dz;
-    a.fx += (double)fxp;
-    a.fy += (double)fyp;
-    a.fz += (double)fzp;
+    a.fx += fxp;
+    a.fy += fyp;
+    a.fz += fzp;
     if (E) {
-        const T u = in ? p.eps4 * s6 * (s6 - T(1)) - p.shift : T(0);
-        a.u += (double)u;
-        a.w += (double)rf;
+        const T u = p.eps4 * s6 * (s6 - T(1)) - p.shift;
+        a.u += in ? (double)u : 0.0;
+        a.w += in ? (double)rf : 0.0;
     }
 }
 

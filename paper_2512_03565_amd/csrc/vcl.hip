@@ -32,6 +32,8 @@ constexpr int CODE_SHIFT = 26;
 constexpr int32_t J_MASK = (1 << CODE_SHIFT) - 1;
 constexpr double DUMMY_BASE = 1.0e7;
 constexpr double DUMMY_STEP = 64.0;
+// list steps per trip of the force loops
+constexpr int UNROLL = 4;
 
 __host__ __device__ inline int shift_code(int sx, int sy, int sz)
 {
@@ -220,6 +222,7 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
     constexpr int AJ = MDLJ_WAVE / M;    // j lanes per i
     constexpr int JPS = AJ / M;          // list entries per step (1 for M=8, 4 for M=4)
     __shared__ LdsTable<T> lt;
+    const double rc2 = tab.rc2d;
     if (MS) {
         lds_table_load(lt, tab, threadIdx.x, blockDim.x);
         __syncthreads();
@@ -237,34 +240,48 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
     const int64_t islot = live ? I * M + a : 0;
     const PosT pi = crec[islot];
     const int32_t Ln = live ? len[I] : 0;
-    for (int32_t k0 = 0; k0 < Ln; k0 += JPS) {
-        const int32_t k = k0 + eo;
-        const bool ok = k < Ln;
-        int32_t J = 0;
-        double sx = 0, sy = 0, sz = 0;
-        if (ok) decode(list[I * cap + k], bl.L, J, sx, sy, sz);
-        const int64_t jslot = (int64_t)J * M + m;
-        const PosT pj = crec[jslot];
-        // self cluster without shift: skip the diagonal, and with Newton-3
-        // the lower triangle
-        const bool self0 = ok && J == I && sx == 0.0 && sy == 0.0 && sz == 0.0;
-        const bool valid = ok && !(self0 && (N3 ? m <= a : m == a));
-        const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
-        T fxp, fyp, fzp;
-        lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x + sx, pj.y + sy, pj.z + sz, valid, p, tab.rc2, acc, fxp,
-                      fyp, fzp);
-        if (N3) {
-            // -F on j summed over the M i-lanes that share it
-            double gx = -(double)fxp, gy = -(double)fyp, gz = -(double)fzp;
-            for (int o = AJ; o < MDLJ_WAVE; o <<= 1) {
-                gx += __shfl_xor(gx, o, MDLJ_WAVE);
-                gy += __shfl_xor(gy, o, MDLJ_WAVE);
-                gz += __shfl_xor(gz, o, MDLJ_WAVE);
-            }
-            if (a == 0 && ok) {
-                atomicAdd(&fo.fx[jslot], gx);
-                atomicAdd(&fo.fy[jslot], gy);
-                atomicAdd(&fo.fz[jslot], gz);
+    for (int32_t k00 = 0; k00 < Ln; k00 += JPS * UNROLL) {
+        // U steps per trip: their list and record loads are in flight together
+        int32_t J[UNROLL];
+        double sx[UNROLL], sy[UNROLL], sz[UNROLL];
+        bool ok[UNROLL];
+        PosT pj[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int32_t k = k00 + u * JPS + eo;
+            ok[u] = k < Ln;
+            J[u] = 0;
+            sx[u] = sy[u] = sz[u] = 0.0;
+            if (ok[u]) decode(list[I * cap + k], bl.L, J[u], sx[u], sy[u], sz[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) pj[u] = crec[(int64_t)J[u] * M + m];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            // all lanes take part in the shuffles below; masked lanes add zero
+            if (k00 + u * JPS >= Ln) break;
+            const int64_t jslot = (int64_t)J[u] * M + m;
+            // self cluster without shift: skip the diagonal, and with Newton-3
+            // the lower triangle
+            const bool self0 = ok[u] && J[u] == I && sx[u] == 0.0 && sy[u] == 0.0 && sz[u] == 0.0;
+            const bool valid = ok[u] && !(self0 && (N3 ? m <= a : m == a));
+            const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj[u].t);
+            double fxp, fyp, fzp;
+            lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x + sx[u], pj[u].y + sy[u], pj[u].z + sz[u], valid,
+                          p, rc2, acc, fxp, fyp, fzp);
+            if (N3) {
+                // -F on j summed over the M i-lanes that share it
+                double gx = -fxp, gy = -fyp, gz = -fzp;
+                for (int o = AJ; o < MDLJ_WAVE; o <<= 1) {
+                    gx += __shfl_xor(gx, o, MDLJ_WAVE);
+                    gy += __shfl_xor(gy, o, MDLJ_WAVE);
+                    gz += __shfl_xor(gz, o, MDLJ_WAVE);
+                }
+                if (a == 0 && ok[u]) {
+                    atomicAdd(&fo.fx[jslot], gx);
+                    atomicAdd(&fo.fy[jslot], gy);
+                    atomicAdd(&fo.fz[jslot], gz);
+                }
             }
         }
     }
@@ -296,6 +313,7 @@ __global__ __launch_bounds__(256) void k_vcl_ipl(const PosT *__restrict__ crec,
                                                  ForceOut fo, int remap)
 {
     __shared__ LdsTable<T> lt;
+    const double rc2 = tab.rc2d;
     if (MS) {
         lds_table_load(lt, tab, threadIdx.x, blockDim.x);
         __syncthreads();
@@ -320,11 +338,11 @@ __global__ __launch_bounds__(256) void k_vcl_ipl(const PosT *__restrict__ crec,
             const PosT pj = crec[jslot];
             const bool valid = !(self0 && (N3 ? mm <= a : mm == a));
             const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
-            T fxp, fyp, fzp;
-            lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x + sx, pj.y + sy, pj.z + sz, valid, p, tab.rc2,
+            double fxp, fyp, fzp;
+            lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x + sx, pj.y + sy, pj.z + sz, valid, p, rc2,
                           acc, fxp, fyp, fzp);
             if (N3) {
-                double gx = -(double)fxp, gy = -(double)fyp, gz = -(double)fzp;
+                double gx = -fxp, gy = -fyp, gz = -fzp;
                 // sum over the M lanes of this cluster (they share j)
                 for (int o = 1; o < M; o <<= 1) {
                     gx += __shfl_xor(gx, o, M);

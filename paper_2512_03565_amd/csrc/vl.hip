@@ -17,66 +17,49 @@
 
 namespace {
 
-__global__ __launch_bounds__(64) void k_vl_build(const PosT *__restrict__ rec,
-                                                 const int32_t *__restrict__ start,
-                                                 const int32_t *__restrict__ ibase, Grid g,
-                                                 double rl2, int half, int64_t sk, int64_t st,
-                                                 int32_t cap, int32_t *__restrict__ nbr,
-                                                 int32_t *__restrict__ len,
-                                                 int32_t *__restrict__ maxlen)
+// candidates per trip of the force loops
+constexpr int UNROLL = 4;
+
+// One lane per particle: walk the nine rows of three cells around its cell
+// and append every partner within rc + skin.  Lanes of a wavefront are
+// consecutive sorted particles (one or two cells), so their j-reads overlap.
+__global__ __launch_bounds__(256) void k_vl_build(const PosT *__restrict__ rec,
+                                                  const int32_t *__restrict__ start,
+                                                  const int32_t *__restrict__ ilist,
+                                                  const int32_t *__restrict__ cell_of, Grid g,
+                                                  int64_t n, double rl2, int half, int64_t sk,
+                                                  int64_t st, int32_t cap,
+                                                  int32_t *__restrict__ nbr,
+                                                  int32_t *__restrict__ len,
+                                                  int32_t *__restrict__ maxlen)
 {
-    __shared__ int seg_b[9];
-    __shared__ int seg_c[10];
-    const int lane = threadIdx.x;
-    const int64_t c = blockIdx.x;
-    const int cx = (int)(c % g.n[0]);
-    const int cy = (int)((c / g.n[0]) % g.n[1]);
-    const int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
-    const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
-                       cx + g.h[0];
-    const int ib = start[ei], ie = start[ei + 1];
-    if (lane < 9) {
-        const int dy = lane % 3 - 1, dz = lane / 3 - 1;
-        const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
-                           (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx - 1 + g.h[0];
-        seg_b[lane] = start[ej];
-        seg_c[lane + 1] = start[ej + 3] - start[ej];
-    }
-    __syncthreads();
-    if (lane == 0) {
-        seg_c[0] = 0;
-        for (int r = 0; r < 9; ++r) seg_c[r + 1] += seg_c[r];
-    }
-    __syncthreads();
-    const int C = seg_c[9];
-    const unsigned long long below = (1ull << lane) - 1ull;
-    int32_t cmax = 0;
-    for (int i = ib; i < ie; ++i) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t cnt = 0;
+    if (t < n) {
+        const int32_t i = ilist[t];
         const PosT pi = rec[i];
-        const int64_t t = ibase[c] + (i - ib);
-        int32_t cnt = 0;
-        int r = 0;
-        for (int kk = 0; kk < C; kk += MDLJ_WAVE) {
-            const int k = kk + lane;
-            bool in = false;
-            int j = 0;
-            if (k < C) {
-                while (k >= seg_c[r + 1]) ++r;
-                j = seg_b[r] + (k - seg_c[r]);
+        const int64_t e = cell_of[pi.orig];
+        int32_t *out = nbr + t * st;
+        for (int r = 0; r < 9; ++r) {
+            const int dy = r % 3 - 1, dz = r / 3 - 1;
+            const int64_t ej = e + dy * g.stride[1] + dz * g.stride[2] - 1;
+            const int32_t jb = start[ej], je = start[ej + 3];
+            for (int32_t j = jb; j < je; ++j) {
                 const PosT pj = rec[j];
-                const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                in = (j != i) && (dx * dx + dy * dy + dz * dz < rl2) &&
-                     (!half || pj.orig > pi.orig);
+                const double dx = pi.x - pj.x, dyy = pi.y - pj.y, dzz = pi.z - pj.z;
+                const bool in = (j != i) && (dx * dx + dyy * dyy + dzz * dzz < rl2) &&
+                                (!half || pj.orig > pi.orig);
+                if (in) {
+                    if (cnt < cap) out[(int64_t)cnt * sk] = j;
+                    ++cnt;
+                }
             }
-            const unsigned long long m = __ballot(in);
-            const int32_t pos = cnt + __popcll(m & below);
-            if (in && pos < cap) nbr[(int64_t)pos * sk + t * st] = j;
-            cnt += __popcll(m);
         }
-        if (lane == 0) len[t] = cnt;
-        cmax = cnt > cmax ? cnt : cmax;
+        len[t] = cnt;
     }
-    if (lane == 0 && cmax > 0) atomicMax(maxlen, cmax);
+    // longest list of the wavefront, one atomic per wavefront
+    for (int o = 32; o > 0; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o));
+    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0 && cnt > 0) atomicMax(maxlen, cnt);
 }
 
 // i-per-lane over ELL lists.
@@ -88,6 +71,7 @@ __global__ __launch_bounds__(256) void k_vl_ipl(const PosT *__restrict__ rec,
                                                 LJTable<T> tab, ForceOut fo, int remap)
 {
     __shared__ LdsTable<T> lt;
+    const double rc2 = tab.rc2d;
     if (MS) {
         lds_table_load(lt, tab, threadIdx.x, blockDim.x);
         __syncthreads();
@@ -100,16 +84,26 @@ __global__ __launch_bounds__(256) void k_vl_ipl(const PosT *__restrict__ rec,
         const int32_t i = ilist[t];
         const PosT pi = rec[i];
         const int32_t L = len[t];
-        for (int32_t k = 0; k < L; ++k) {
-            const int32_t j = nbr[(int64_t)k * n + t];
-            const PosT pj = rec[j];
-            const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
-            T fxp, fyp, fzp;
-            lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, true, p, tab.rc2, a, fxp, fyp, fzp);
-            if (N3) {
-                atomicAdd(&fo.fx[j], -(double)fxp);
-                atomicAdd(&fo.fy[j], -(double)fyp);
-                atomicAdd(&fo.fz[j], -(double)fzp);
+        // U candidates per trip: their index and record loads are in flight together
+        for (int32_t k0 = 0; k0 < L; k0 += UNROLL) {
+            int32_t jj[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+                jj[u] = k0 + u < L ? nbr[(int64_t)(k0 + u) * n + t] : -1;
+            PosT pj[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) pj[u] = rec[jj[u] >= 0 ? jj[u] : i];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj[u].t);
+                double fxp, fyp, fzp;
+                lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x, pj[u].y, pj[u].z, jj[u] >= 0, p, rc2, a,
+                              fxp, fyp, fzp);
+                if (N3 && jj[u] >= 0) {
+                    atomicAdd(&fo.fx[jj[u]], -fxp);
+                    atomicAdd(&fo.fy[jj[u]], -fyp);
+                    atomicAdd(&fo.fz[jj[u]], -fzp);
+                }
             }
         }
         if (N3) {
@@ -138,6 +132,7 @@ __global__ __launch_bounds__(256) void k_vl_wpi(const PosT *__restrict__ rec,
 {
     constexpr int SEG = MDLJ_WAVE / G;
     __shared__ LdsTable<T> lt;
+    const double rc2 = tab.rc2d;
     if (MS) {
         lds_table_load(lt, tab, threadIdx.x, blockDim.x);
         __syncthreads();
@@ -155,16 +150,24 @@ __global__ __launch_bounds__(256) void k_vl_wpi(const PosT *__restrict__ rec,
         const PosT pi = rec[i];
         const int32_t L = len[t];
         const int32_t *row = nbr + t * cap;
-        for (int32_t k = l; k < L; k += SEG) {
-            const int32_t j = row[k];
-            const PosT pj = rec[j];
-            const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj.t);
-            T fxp, fyp, fzp;
-            lj_pair<T, E>(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, true, p, tab.rc2, a, fxp, fyp, fzp);
-            if (N3) {
-                atomicAdd(&fo.fx[j], -(double)fxp);
-                atomicAdd(&fo.fy[j], -(double)fyp);
-                atomicAdd(&fo.fz[j], -(double)fzp);
+        for (int32_t k0 = l; k0 < L; k0 += UNROLL * SEG) {
+            int32_t jj[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) jj[u] = k0 + u * SEG < L ? row[k0 + u * SEG] : -1;
+            PosT pj[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) pj[u] = rec[jj[u] >= 0 ? jj[u] : i];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj[u].t);
+                double fxp, fyp, fzp;
+                lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x, pj[u].y, pj[u].z, jj[u] >= 0, p, rc2, a,
+                              fxp, fyp, fzp);
+                if (N3 && jj[u] >= 0) {
+                    atomicAdd(&fo.fx[jj[u]], -fxp);
+                    atomicAdd(&fo.fy[jj[u]], -fyp);
+                    atomicAdd(&fo.fz[jj[u]], -fzp);
+                }
             }
         }
     }
@@ -210,6 +213,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
     case 1: k_vl_wpi<T, E, MS, N3, 1><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, tab, fo, remap); break;
     case 2: k_vl_wpi<T, E, MS, N3, 2><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, tab, fo, remap); break;
     case 4: k_vl_wpi<T, E, MS, N3, 4><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, tab, fo, remap); break;
+    case 8: k_vl_wpi<T, E, MS, N3, 8><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, tab, fo, remap); break;
     default: return -1;
     }
     return nb * (TB / MDLJ_WAVE);
@@ -271,10 +275,11 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         HIPCHK(ctx, hipMemsetAsync(maxlen, 0, sizeof(int32_t), ctx->stream));
         const int64_t sk = rowmajor ? 1 : n;
         const int64_t st = rowmajor ? cap : 1;
-        k_vl_build<<<g.ncell_int, 64, 0, ctx->stream>>>(
+        k_vl_build<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
             (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
-            (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1, g, rl * rl, cfg.newton3 ? 1 : 0, sk,
-            st, (int32_t)cap, (int32_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen);
+            (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, g, n, rl * rl,
+            cfg.newton3 ? 1 : 0, sk, st, (int32_t)cap, (int32_t *)ctx->b_nbr.p,
+            (int32_t *)ctx->b_nlen.p, maxlen);
         HIPCHK(ctx, hipGetLastError());
         int32_t hmax = 0;
         HIPCHK(ctx, hipMemcpyAsync(&hmax, maxlen, sizeof hmax, hipMemcpyDeviceToHost, ctx->stream));

@@ -100,6 +100,17 @@ _SIGS = {
     "mdlj_mlp_save": [_ctxp, C.c_char_p],
     "mdlj_mlp_set_threshold": [_ctxp, C.c_double],
     "mdlj_set_timing": [_ctxp, C.c_int32],
+    "mdlj_mlp_init": [_ctxp, C.c_int32, C.c_uint64],
+    "mdlj_mlp_set_norm": [_ctxp, C.POINTER(C.c_float), C.POINTER(C.c_float)],
+    "mdlj_mlp_get_params": [_ctxp, C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_int64),
+                            C.POINTER(C.c_int32)],
+    "mdlj_mlp_set_params": [_ctxp, C.POINTER(C.c_float), C.c_int64, C.c_int32],
+    "mdlj_mlp_predict": [_ctxp, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_float)],
+    "mdlj_mlp_loss_grad": [_ctxp, C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32,
+                           C.POINTER(C.c_float), C.POINTER(C.c_float)],
+    "mdlj_mlp_train": [_ctxp, C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                       C.c_int32, C.c_double, C.c_uint64, C.POINTER(C.c_double)],
+    "mdlj_mlp_stats": [_ctxp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "mdlj_get_timing": [_ctxp, _d, _d, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
 }
 for _name, _args in _SIGS.items():
@@ -137,6 +148,10 @@ def _ptr(a):
             return C.c_void_p(a.data_ptr()), MEM_DEVICE
         return C.c_void_p(a.data_ptr()), MEM_HOST
     return a.ctypes.data_as(C.c_void_p), MEM_HOST
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
 def _stream_handle(stream):
@@ -307,6 +322,69 @@ class System:
         check(lib.mdlj_get_timing(self.ctx, C.byref(f), C.byref(b), C.byref(nf), C.byref(nb)),
               self.ctx)
         return f.value, b.value, nf.value, nb.value
+
+    # --- learned tuner network -------------------------------------------
+    def mlp_init(self, k, seed=0):
+        check(lib.mdlj_mlp_init(self.ctx, int(k), int(seed)), self.ctx)
+
+    def mlp_set_norm(self, mean, std):
+        mean = np.ascontiguousarray(mean, np.float32)
+        std = np.ascontiguousarray(std, np.float32)
+        check(lib.mdlj_mlp_set_norm(self.ctx, _fp(mean), _fp(std)), self.ctx)
+
+    def mlp_params(self):
+        n = C.c_int64()
+        k = C.c_int32()
+        check(lib.mdlj_mlp_get_params(self.ctx, None, 0, C.byref(n), C.byref(k)), self.ctx)
+        w = np.empty(n.value, np.float32)
+        check(lib.mdlj_mlp_get_params(self.ctx, _fp(w), n.value, C.byref(n), C.byref(k)),
+              self.ctx)
+        return w, k.value
+
+    def mlp_set_params(self, w, k):
+        w = np.ascontiguousarray(w, np.float32)
+        check(lib.mdlj_mlp_set_params(self.ctx, _fp(w), w.size, int(k)), self.ctx)
+
+    def mlp_predict(self, X):
+        X = np.ascontiguousarray(np.atleast_2d(X), np.float32)
+        _, k = self.mlp_params()
+        out = np.empty((len(X), k), np.float32)
+        check(lib.mdlj_mlp_predict(self.ctx, _fp(X), len(X), _fp(out)), self.ctx)
+        return out
+
+    def mlp_loss_grad(self, X, y):
+        X = np.ascontiguousarray(np.atleast_2d(X), np.float32)
+        y = np.ascontiguousarray(y, np.int32)
+        w, _ = self.mlp_params()
+        g = np.empty_like(w)
+        loss = C.c_float()
+        check(lib.mdlj_mlp_loss_grad(self.ctx, _fp(X), y.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     len(X), _fp(g), C.byref(loss)), self.ctx)
+        return loss.value, g
+
+    def mlp_train(self, X, y, epochs, batch=64, lr=1e-3, seed=0):
+        X = np.ascontiguousarray(np.atleast_2d(X), np.float32)
+        y = np.ascontiguousarray(y, np.int32)
+        loss = C.c_double()
+        check(lib.mdlj_mlp_train(self.ctx, _fp(X), y.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 len(X), int(epochs), int(batch), float(lr), int(seed),
+                                 C.byref(loss)), self.ctx)
+        return loss.value
+
+    def mlp_load(self, path):
+        check(lib.mdlj_mlp_load(self.ctx, str(path).encode()), self.ctx)
+
+    def mlp_save(self, path):
+        check(lib.mdlj_mlp_save(self.ctx, str(path).encode()), self.ctx)
+
+    def mlp_set_threshold(self, t):
+        check(lib.mdlj_mlp_set_threshold(self.ctx, float(t)), self.ctx)
+
+    def mlp_stats(self):
+        c = C.c_double()
+        f = C.c_int64()
+        check(lib.mdlj_mlp_stats(self.ctx, C.byref(c), C.byref(f)), self.ctx)
+        return c.value, f.value
 
     def features(self):
         f = (C.c_float * 8)()

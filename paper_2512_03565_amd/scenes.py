@@ -152,6 +152,40 @@ def droplet_scene(n_total, r_drop, rho_drop, rho_vap, dmin, seed):
     return np.concatenate([drop, vap]), box
 
 
+def lattice_droplet(n, rho_drop, frac_drop=0.2, rho_vap=0.05, jitter=0.05, seed=0):
+    """About n particles: a sphere holding frac_drop of them at density
+    rho_drop (jittered FCC cut to the sphere) in vapour at rho_vap (a simple
+    cubic lattice of spacing rho_vap^(-1/3) jittered by a quarter spacing,
+    points inside the sphere or within 1.0 of its surface removed), in a
+    periodic cube.  Minimum spacing stays above ~0.8 sigma."""
+    rng = np.random.default_rng(seed)
+    n_drop = int(frac_drop * n)
+    n_vap = n - n_drop
+    v_drop = n_drop / rho_drop
+    r_drop = (3.0 * v_drop / (4.0 * math.pi)) ** (1.0 / 3.0)
+    L = (v_drop + n_vap / rho_vap) ** (1.0 / 3.0)
+    L = max(L, 2.0 * r_drop + 8.0)
+    box = np.array([L, L, L])
+    c = box / 2
+    a = (4.0 / rho_drop) ** (1.0 / 3.0)
+    m = int(math.ceil(2 * r_drop / a)) + 1
+    g = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"),
+                 -1).reshape(-1, 3).astype(np.float64)
+    d = ((g[:, None, :] + FCC_BASIS[None]) * a).reshape(-1, 3)
+    d = d - d.mean(0)
+    d = d[(d * d).sum(1) < r_drop * r_drop] + c
+    d = d + rng.uniform(-jitter, jitter, d.shape)
+    sp = rho_vap ** (-1.0 / 3.0)
+    k = max(1, int(L / sp))
+    sp = L / k
+    g = np.stack(np.meshgrid(np.arange(k), np.arange(k), np.arange(k), indexing="ij"),
+                 -1).reshape(-1, 3).astype(np.float64)
+    v = (g + 0.5) * sp + rng.uniform(-0.25 * sp, 0.25 * sp, g.shape)
+    rr = np.sqrt(((v - c) ** 2).sum(1))
+    v = v[rr > r_drop + 1.0]
+    return _wrap(np.concatenate([d, v]), box), box
+
+
 def _scene(pos, box, **kw):
     s = dict(pos=np.ascontiguousarray(pos, np.float64), box=np.asarray(box, np.float64))
     s.update(kw)
@@ -207,6 +241,36 @@ def config3(seed=1003, n_total=1_000_000, r_drop=40.0):
     pos, box = droplet_scene(n_total, r_drop, 0.8, 0.05, 0.9, seed)
     return _scene(pos, box, rc=3.0, skin=0.3, rebuild_every=10, T=0.9, dt=0.002,
                   name=f"{len(pos)} droplet r{r_drop}")
+
+
+def tuning_scene(index, n_min=1e4, n_max=4e6):
+    """Scene `index` of the learned-tuner sweep (seed 50000 + index): N
+    log-uniform in [n_min, n_max], density uniform in [0.05, 1.0], cutoff
+    uniform in [2.5, 3.5] sigma_max, one or two species, homogeneous (jittered
+    FCC) or droplet (20% of N at that density in vapour at 0.05)."""
+    seed = 50000 + index
+    rng = np.random.default_rng(seed)
+    n = int(round(10 ** rng.uniform(math.log10(n_min), math.log10(n_max))))
+    rho = float(rng.uniform(0.05, 1.0))
+    rc_fac = float(rng.uniform(2.5, 3.5))
+    nspec = int(rng.integers(1, 3))
+    droplet = bool(rng.integers(0, 2))
+    if droplet and rho > 0.1:
+        pos, box = lattice_droplet(n, rho, seed=seed + 1)
+    else:
+        m = max(2, int(round((n / 4.0) ** (1.0 / 3.0))))
+        nz = max(2, int(round(n / (4.0 * m * m))))
+        pos, box = fcc_lattice(m, m, nz, rho, 0.05, seed + 1)
+        droplet = False
+    sig = [1.0, 1.2][:nspec]
+    eps = [1.0, 0.8][:nspec]
+    types = random_species(len(pos), nspec, seed + 2)
+    rc = rc_fac * max(sig)
+    return _scene(pos, box, types=types, eps=eps, sig=sig, mass=[1.0] * nspec, rc=rc, skin=0.3,
+                  rebuild_every=10, T=1.0, dt=0.002,
+                  name=f"tune{index} n={len(pos)} rho={rho:.3f} rc={rc:.2f} "
+                       f"ns={nspec} {'droplet' if droplet else 'homog'}",
+                  rho=rho, droplet=droplet)
 
 
 def homogeneous_scene(n, rho, rc, nspec, seed):

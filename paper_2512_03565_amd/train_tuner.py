@@ -1,0 +1,112 @@
+"""Train the learned tuner on sweep timings and score it on held-out scenes.
+
+Reads one or more sweep .npz files (``sweep.py``), labels every scene with
+its fastest configuration, z-scores the features on the training scenes,
+trains the network on the GPU with the library's own kernels and evaluates
+the held-out scenes:
+
+  regret(scene) = t(chosen) / t(fastest) with both times from the sweep,
+  chosen = the network's argmax when its confidence >= threshold, else full
+  search (which picks the fastest, regret 1, but pays for timing every
+  configuration).
+
+Writes the network file and a JSON summary.
+
+    python -m paper_2512_03565_amd.train_tuner sweep_a.npz sweep_b.npz \
+        --out paper_2512_03565_amd/data/tuner_mlp.bin
+"""
+import argparse
+import json
+import sys
+
+import numpy as np
+
+
+def load(paths):
+    F, T, M = [], [], []
+    names = None
+    for p in paths:
+        d = np.load(p, allow_pickle=False)
+        F.append(d["features"])
+        T.append(d["table_us"])
+        M.append(d["meta"])
+        nm = list(d["names"])
+        if names is not None and nm != names:
+            raise ValueError("sweeps were taken with different configuration spaces")
+        names = nm
+    meta = np.concatenate(M)
+    order = np.argsort(meta[:, 0])  # by scene index
+    return (np.concatenate(F)[order], np.concatenate(T)[order], meta[order], names)
+
+
+def evaluate(probs, table, threshold):
+    best = np.min(table, axis=1)
+    pick = probs.argmax(1)
+    conf = probs.max(1)
+    t_pick = table[np.arange(len(table)), pick]
+    fallback = (conf < threshold) | ~np.isfinite(t_pick)
+    ratio = np.where(fallback, 1.0, t_pick / best)
+    return {
+        "geomean_ratio": float(np.exp(np.log(ratio).mean())),
+        "mean_ratio": float(ratio.mean()),
+        "max_ratio": float(ratio.max()),
+        "fallback_rate": float(fallback.mean()),
+        "top1_accuracy": float((pick == table.argmin(1)).mean()),
+        "within_5pct": float((ratio <= 1.05).mean()),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("sweeps", nargs="+")
+    ap.add_argument("--train", type=int, default=1600, help="first N scenes train, rest test")
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=20251203)
+    ap.add_argument("--threshold", type=float, default=0.6)
+    ap.add_argument("--out", default="tuner_mlp.bin")
+    ap.add_argument("--summary", default=None)
+    a = ap.parse_args(argv)
+
+    import torch  # noqa: F401  (one HIP runtime: torch's)
+    from paper_2512_03565_amd import mdlj, scenes
+
+    F, T, meta, names = load(a.sweeps)
+    ok = np.isfinite(T).any(1)
+    F, T, meta = F[ok], T[ok], meta[ok]
+    y = T.argmin(1).astype(np.int32)
+    ntr = min(a.train, len(F) - 1)
+    Ftr, ytr = F[:ntr], y[:ntr]
+    mean = Ftr.mean(0)
+    std = Ftr.std(0)
+    std[std < 1e-6] = 1.0
+    s = scenes.config1()
+    with mdlj.System(s["pos"], s["box"], s["rc"]) as sysm:
+        if len(sysm.configs()) != T.shape[1]:
+            raise ValueError("sweep table width differs from the library's configuration space")
+        sysm.mlp_init(T.shape[1], seed=a.seed)
+        sysm.mlp_set_norm(mean, std)
+        loss = sysm.mlp_train(Ftr, ytr, a.epochs, a.batch, a.lr, a.seed + 1)
+        sysm.mlp_set_threshold(a.threshold)
+        sysm.mlp_save(a.out)
+        p_tr = sysm.mlp_predict(Ftr)
+        p_te = sysm.mlp_predict(F[ntr:])
+    fixed = names.index("LC/i-per-lane/k1")
+    res = {
+        "scenes": int(len(F)), "train": int(ntr), "test": int(len(F) - ntr),
+        "configs": names, "final_loss": loss, "threshold": a.threshold,
+        "train_eval": evaluate(p_tr, T[:ntr], a.threshold),
+        "test_eval": evaluate(p_te, T[ntr:], a.threshold),
+        "test_fixed_geomean_ratio": float(np.exp(np.log(T[ntr:, fixed] / T[ntr:].min(1)).mean())),
+        "label_histogram": {names[k]: int(c) for k, c in zip(*np.unique(y, return_counts=True))},
+    }
+    print(json.dumps(res["test_eval"]), flush=True)
+    if a.summary:
+        with open(a.summary, "w") as f:
+            json.dump(res, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

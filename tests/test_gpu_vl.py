@@ -22,7 +22,7 @@ def vl_configs(m):
     out = []
     for n3 in (0, 1):
         out.append((m.NBR_VL, m.ORD_I_PER_LANE, 0, 0, 0, n3))
-        out += [(m.NBR_VL, m.ORD_WAVE_PER_I, g, 64 // g, 0, n3) for g in (1, 2, 4)]
+        out += [(m.NBR_VL, m.ORD_WAVE_PER_I, g, 64 // g, 0, n3) for g in (1, 2, 4, 8)]
     return out
 
 
