@@ -54,14 +54,13 @@ def parse():
 
 def run_mode(m, torch, sysm, vel, dt, steps, warmup, pairs):
     """Warm up, then time `steps` MD steps; returns dict of measurements."""
-    for _ in range(warmup):
-        sysm.step_vv(vel, dt, 1)
+    if warmup:
+        sysm.step_vv(vel, dt, warmup)
     torch.cuda.synchronize()
     sysm.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        sysm.step_vv(vel, dt, 1)
+    sysm.step_vv(vel, dt, steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     force_us, build_us, nf, nb = sysm.get_timing()

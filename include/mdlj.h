@@ -86,10 +86,15 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2 };
  *   CLUSTER_TILE tile_i x tile_j = 64 lanes of one wavefront, tile_i i's and
  *                tile_j j's per step (LC: 16x4, 8x8; VCL: cluster_size x
  *                64/cluster_size).
- *   WAVE_PER_I   tile_i = g, the i-particles per wavefront (1, 2, 4); each
- *                gets 64/g lanes.
+ *   WAVE_PER_I   tile_i = g, the i-particles per wavefront (LC: 1, 2, 4;
+ *                VL: 1, 2, 4, 8); each gets 64/g lanes.
  * cluster_size is 4 or 8 for VCL, 0 otherwise.  newton3 = 1 computes each
  * pair once and applies F_ji = -F_ij with atomics (section 4.1.3).
+ * staged = 1 (LC cluster-tile / wave-per-i, VL wave-per-i, full lists): a
+ * workgroup owns one cell and first copies the particles of its 27-cell
+ * neighbourhood into LDS with coalesced loads; j-particles are then read
+ * from LDS (the Verlet list holds 16-bit LDS-local indices).  staged = 0
+ * reads every j-particle from global memory.
  */
 typedef struct {
     int32_t nbr_algo;
@@ -98,6 +103,7 @@ typedef struct {
     int32_t tile_j;
     int32_t cluster_size;
     int32_t newton3;
+    int32_t staged;
 } mdlj_config;
 
 /*
@@ -195,6 +201,25 @@ mdlj_status mdlj_tune(mdlj_ctx *ctx, int32_t mode, int32_t samples, mdlj_config 
 mdlj_status mdlj_tune_results(const mdlj_ctx *ctx, double *us, int32_t cap, int32_t *count);
 
 /*
+ * Decision rules of the tuner, as pure host functions (no context, no
+ * device work), usable by drivers that time configurations themselves.
+ *   tune_select: samples is row-major [k][s] (microseconds; +inf or NaN for
+ *     a configuration that cannot run).  mode 0 reduces each row to its mean
+ *     with the first sample dropped as warm-up (all samples when s == 1),
+ *     mode 1 to its minimum (section 2.3.2 allows either).  values[k]
+ *     receives the reduced values; *chosen the index of the smallest finite
+ *     one, the lower index on ties, or -1 if none is finite.
+ *   retune_needed: *needed = 1 when the density (feature 1) or the
+ *     cell-occupancy spread (feature 5) of mdlj_features changed by more
+ *     than `threshold` relative to `before8` (the optimum moves with the
+ *     particle distribution, section 5).
+ */
+mdlj_status mdlj_tune_select(const double *samples, int32_t k, int32_t s, int32_t mode,
+                             double *values, int32_t *chosen);
+mdlj_status mdlj_retune_needed(const float *before8, const float *now8, double threshold,
+                               int32_t *needed);
+
+/*
  * nsteps velocity-Verlet steps (mass per species, default 1; time step dt):
  * v += F dt/2m; x += v dt; wrap; F = F(x); v += F dt/2m.  vx, vy, vz are
  * device float64 arrays in caller order, updated in place.  The forces of
@@ -206,13 +231,14 @@ mdlj_status mdlj_step_vv(mdlj_ctx *ctx, double *vx, double *vy, double *vz, doub
 mdlj_status mdlj_set_mass(mdlj_ctx *ctx, int32_t s, double mass);
 
 /* Kernel timing with HIP events on the context's stream.  on = 1 enables
- * and resets the totals; while enabled every force evaluation synchronises
- * after its force kernel.  get_timing returns the summed force-kernel and
- * rebuild (binning + list build, or the per-step re-binning of linked
- * cells) microseconds and how many of each were timed.  Outputs may be
- * NULL. */
+ * and resets the totals.  Events are recorded around the neighbour upkeep
+ * and the force kernel of every force evaluation and read only when
+ * get_timing is called (which synchronises the stream).  get_timing returns
+ * the summed force-kernel and rebuild (binning + list build, or the
+ * per-step re-binning of linked cells) microseconds and how many of each
+ * were timed.  Outputs may be NULL. */
 mdlj_status mdlj_set_timing(mdlj_ctx *ctx, int32_t on);
-mdlj_status mdlj_get_timing(const mdlj_ctx *ctx, double *force_us, double *build_us,
+mdlj_status mdlj_get_timing(mdlj_ctx *ctx, double *force_us, double *build_us,
                             int64_t *n_force, int64_t *n_build);
 
 /* Eight scene features the learned tuner reads (log10 N, density,

@@ -87,7 +87,8 @@ template void fill_table<double>(const mdlj_ctx *, LJTable<double> *);
 static bool cfg_eq(const mdlj_config &a, const mdlj_config &b)
 {
     return a.nbr_algo == b.nbr_algo && a.order == b.order && a.tile_i == b.tile_i &&
-           a.tile_j == b.tile_j && a.cluster_size == b.cluster_size && a.newton3 == b.newton3;
+           a.tile_j == b.tile_j && a.cluster_size == b.cluster_size && a.newton3 == b.newton3 &&
+           a.staged == b.staged;
 }
 
 // The search space: neighbour algorithm x interaction order x tile shape x
@@ -97,19 +98,25 @@ static std::vector<mdlj_config> build_space()
 {
     std::vector<mdlj_config> v;
     // linked cells (rebinned every step; full shell, no Newton-3)
-    for (int k : {1, 2, 4}) v.push_back({MDLJ_NBR_LC, MDLJ_ORD_I_PER_LANE, k, 1, 0, 0});
-    for (int ai : {8, 16}) v.push_back({MDLJ_NBR_LC, MDLJ_ORD_CLUSTER_TILE, ai, 64 / ai, 0, 0});
-    for (int g : {1, 2, 4}) v.push_back({MDLJ_NBR_LC, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, 0});
+    for (int k : {1, 2, 4}) v.push_back({MDLJ_NBR_LC, MDLJ_ORD_I_PER_LANE, k, 1, 0, 0, 0});
+    for (int st : {0, 1}) {
+        for (int ai : {8, 16})
+            v.push_back({MDLJ_NBR_LC, MDLJ_ORD_CLUSTER_TILE, ai, 64 / ai, 0, 0, st});
+        for (int g : {1, 2, 4})
+            v.push_back({MDLJ_NBR_LC, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, 0, st});
+    }
     // Verlet lists
     for (int n3 : {0, 1}) {
-        v.push_back({MDLJ_NBR_VL, MDLJ_ORD_I_PER_LANE, 0, 0, 0, n3});
-        for (int g : {1, 2, 4, 8}) v.push_back({MDLJ_NBR_VL, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, n3});
+        v.push_back({MDLJ_NBR_VL, MDLJ_ORD_I_PER_LANE, 0, 0, 0, n3, 0});
+        for (int g : {1, 2, 4, 8})
+            v.push_back({MDLJ_NBR_VL, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, n3, 0});
     }
+    for (int g : {2, 4, 8}) v.push_back({MDLJ_NBR_VL, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, 0, 1});
     // Verlet cluster lists
     for (int m : {4, 8})
         for (int n3 : {0, 1}) {
-            v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_I_PER_LANE, 0, 0, m, n3});
-            v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_CLUSTER_TILE, m, 64 / m, m, n3});
+            v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_I_PER_LANE, 0, 0, m, n3, 0});
+            v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_CLUSTER_TILE, m, 64 / m, m, n3, 0});
         }
     return v;
 }
@@ -204,7 +211,9 @@ static bool structure_current(const mdlj_ctx *ctx, const mdlj_config &c)
     const mdlj_config &b = ctx->built_cfg;
     // the VL/VCL structures differ per layout; LC grids only by range
     if (b.nbr_algo != c.nbr_algo) return false;
-    if (c.nbr_algo == MDLJ_NBR_VL && (b.order != c.order || b.newton3 != c.newton3)) return false;
+    if (c.nbr_algo == MDLJ_NBR_VL &&
+        (b.order != c.order || b.newton3 != c.newton3 || b.staged != c.staged))
+        return false;
     if (c.nbr_algo == MDLJ_NBR_VCL && (b.cluster_size != c.cluster_size || b.newton3 != c.newton3))
         return false;
     if (memcmp(ctx->built_box, ctx->box, sizeof ctx->box) != 0) return false;
@@ -213,10 +222,14 @@ static bool structure_current(const mdlj_ctx *ctx, const mdlj_config &c)
 }
 
 // Make the structure valid for the current positions: LC re-bins whenever
-// positions changed; lists are rebuilt when stale (interval or displacement)
-mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed, bool *rebuilt)
+// positions changed; lists are rebuilt when stale (interval reached).  When
+// the lists are reused, the skin/2 displacement check is only enqueued
+// (*check_pending); its result is read after the force kernel is queued.
+mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed, bool *rebuilt,
+                    bool *check_pending)
 {
     *rebuilt = false;
+    *check_pending = false;
     bool need = !structure_current(ctx, c);
     if (!need && positions_changed) {
         if (c.nbr_algo == MDLJ_NBR_LC) {
@@ -225,16 +238,64 @@ mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed,
             need = true;
         } else {
             // lists stay exact while every particle moved less than skin/2
-            bool far = false;
-            STCHK(moved_too_far(ctx, &far));
-            if (far) need = true;
-            else STCHK(refresh_records(ctx));
+            STCHK(launch_displacement_check(ctx));
+            STCHK(refresh_records(ctx));
+            *check_pending = true;
         }
     }
     if (need) {
         STCHK(rebuild(ctx, c));
         *rebuilt = true;
     }
+    return MDLJ_OK;
+}
+
+mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed, bool *rebuilt)
+{
+    bool pending = false;
+    STCHK(prepare(ctx, c, positions_changed, rebuilt, &pending));
+    if (pending) {
+        bool far = false;
+        STCHK(check_result(ctx, &far));
+        if (far) {
+            STCHK(rebuild(ctx, c));
+            *rebuilt = true;
+        }
+    }
+    return MDLJ_OK;
+}
+
+static mdlj_status take_event(mdlj_ctx *ctx, hipEvent_t *e)
+{
+    if (ctx->ev_pool.empty()) {
+        HIPCHK(ctx, hipEventCreate(e));
+    } else {
+        *e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+    }
+    return MDLJ_OK;
+}
+
+mdlj_status collect_timing(mdlj_ctx *ctx)
+{
+    if (ctx->ev_pending.empty()) return MDLJ_OK;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (const auto &t : ctx->ev_pending) {
+        float tb = 0, tf = 0;
+        HIPCHK(ctx, hipEventElapsedTime(&tb, t.e0, t.e1));
+        HIPCHK(ctx, hipEventElapsedTime(&tf, t.e1, t.e2));
+        ctx->last_force_us = 1e3 * tf;
+        ctx->t_force_us += 1e3 * tf;
+        ctx->t_nforce++;
+        if (t.rebuilt) {
+            ctx->t_build_us += 1e3 * tb;
+            ctx->t_nbuild++;
+        }
+        ctx->ev_pool.push_back(t.e0);
+        ctx->ev_pool.push_back(t.e1);
+        ctx->ev_pool.push_back(t.e2);
+    }
+    ctx->ev_pending.clear();
     return MDLJ_OK;
 }
 
@@ -265,38 +326,50 @@ bool needs_fold(const mdlj_config &c)
 
 // The whole force evaluation for the current configuration into the
 // context's caller-order force arrays; optional totals.
-mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW)
+mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW, ForceOut *fo_out,
+                            bool to_caller)
 {
     std::string why;
     if (!ready(ctx, &why)) return set_err(ctx, MDLJ_ERR_STATE, why);
     const mdlj_config c = ctx->cfg;
-    bool rebuilt;
-    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
-    STCHK(prepare(ctx, c, positions_changed, &rebuilt));
+    bool rebuilt = false, pending = false;
+    mdlj_ctx::Timed tm = {nullptr, nullptr, nullptr, false};
+    if (ctx->timing) {
+        STCHK(take_event(ctx, &tm.e0));
+        STCHK(take_event(ctx, &tm.e1));
+        STCHK(take_event(ctx, &tm.e2));
+        HIPCHK(ctx, hipEventRecord(tm.e0, ctx->stream));
+    }
+    STCHK(prepare(ctx, c, positions_changed, &rebuilt, &pending));
     ForceOut fo;
     int64_t nb = 0;
-    bool energy = UW != nullptr;
-    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    const bool energy = UW != nullptr;
+    if (ctx->timing) HIPCHK(ctx, hipEventRecord(tm.e1, ctx->stream));
     STCHK(run_force_kernel(ctx, c, energy, fo, &nb));
-    if (ctx->timing) {
-        HIPCHK(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
-        HIPCHK(ctx, hipEventSynchronize(ctx->ev[2]));
-        float tb = 0, tf = 0;
-        HIPCHK(ctx, hipEventElapsedTime(&tb, ctx->ev[0], ctx->ev[1]));
-        HIPCHK(ctx, hipEventElapsedTime(&tf, ctx->ev[1], ctx->ev[2]));
-        ctx->last_force_us = 1e3 * tf;
-        ctx->last_build_us = rebuilt ? 1e3 * tb : 0.0;
-        ctx->t_force_us += 1e3 * tf;
-        ctx->t_nforce++;
-        if (rebuilt) {
-            ctx->t_build_us += 1e3 * tb;
-            ctx->t_nbuild++;
+    if (ctx->timing) HIPCHK(ctx, hipEventRecord(tm.e2, ctx->stream));
+    if (pending) {
+        // the host waits for the check while the force kernel runs; on a
+        // violation the lists are rebuilt and the forces computed again
+        bool far = false;
+        STCHK(check_result(ctx, &far));
+        if (far) {
+            STCHK(rebuild(ctx, c));
+            rebuilt = true;
+            if (ctx->timing) HIPCHK(ctx, hipEventRecord(tm.e1, ctx->stream));
+            STCHK(run_force_kernel(ctx, c, energy, fo, &nb));
+            if (ctx->timing) HIPCHK(ctx, hipEventRecord(tm.e2, ctx->stream));
         }
     }
-    STCHK(unpermute_forces(ctx, fo, needs_fold(c), ctx->fx, ctx->fy, ctx->fz));
+    if (ctx->timing) {
+        tm.rebuilt = rebuilt;
+        ctx->ev_pending.push_back(tm);
+    }
+    if (needs_fold(c)) STCHK(fold_forces(ctx, fo));
+    if (to_caller) STCHK(unpermute_forces(ctx, fo, ctx->fx, ctx->fy, ctx->fz));
     if (energy) STCHK(reduce_partials(ctx, fo.partial, nb, UW));
     ctx->steps_since_build++;
-    ctx->forces_valid = true;
+    ctx->forces_valid = to_caller;
+    if (fo_out) *fo_out = fo;
     return MDLJ_OK;
 }
 
@@ -386,8 +459,14 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
 {
     if (!ctx) return MDLJ_OK;
     (void)hipStreamSynchronize(ctx->stream);
-    for (hipEvent_t &e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
+    for (const auto &t : ctx->ev_pending) {
+        ctx->ev_pool.push_back(t.e0);
+        ctx->ev_pool.push_back(t.e1);
+        ctx->ev_pool.push_back(t.e2);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->ev_flag) (void)hipEventDestroy(ctx->ev_flag);
+    if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
     DevBuf *bufs[] = {&ctx->b_cell_of, &ctx->b_rank,    &ctx->b_count,   &ctx->b_start,
                       &ctx->b_slot_of, &ctx->b_sorted,  &ctx->b_scan_part, &ctx->b_fsorted,
                       &ctx->b_partial, &ctx->b_flags,   &ctx->b_nbr,     &ctx->b_nlen,
@@ -574,18 +653,18 @@ mdlj_status mdlj_compute_forces(mdlj_ctx *ctx, double *fx, double *fy, double *f
 mdlj_status mdlj_set_timing(mdlj_ctx *ctx, int32_t on)
 {
     if (!ctx) return MDLJ_ERR_ARG;
-    if (on && !ctx->ev[0])
-        for (hipEvent_t &e : ctx->ev) HIPCHK(ctx, hipEventCreate(&e));
+    STCHK(collect_timing(ctx));
     ctx->timing = on != 0;
     ctx->t_force_us = ctx->t_build_us = 0;
     ctx->t_nforce = ctx->t_nbuild = 0;
     return MDLJ_OK;
 }
 
-mdlj_status mdlj_get_timing(const mdlj_ctx *ctx, double *force_us, double *build_us,
+mdlj_status mdlj_get_timing(mdlj_ctx *ctx, double *force_us, double *build_us,
                             int64_t *n_force, int64_t *n_build)
 {
     if (!ctx) return MDLJ_ERR_ARG;
+    STCHK(collect_timing(ctx));
     if (force_us) *force_us = ctx->t_force_us;
     if (build_us) *build_us = ctx->t_build_us;
     if (n_force) *n_force = ctx->t_nforce;

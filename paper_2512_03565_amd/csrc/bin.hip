@@ -79,7 +79,12 @@ __global__ void k_bin_count(int64_t n, double *__restrict__ x, double *__restric
     y[i] = p[1];
     z[i] = p[2];
     cell_of[i] = (int32_t)e;
-    rank[i] = atomicAdd(&count[e], 1);
+    const int32_t r = atomicAdd(&count[e], 1);
+    rank[i] = r;
+    // largest occupancy seen (one atomic per wavefront)
+    int32_t m = r + 1;
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0) atomicMax(&flags[2], m);
 }
 
 // Extended-cell counts: a halo cell holds as many records as its source.
@@ -468,14 +473,16 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     HIPCHK(ctx, hipGetLastError());
     STCHK(exclusive_scan(ctx, (const int32_t *)ctx->b_cnt_ext.p, start, g.ncell_ext));
     HIPCHK(ctx, hipGetLastError());
-    int32_t host[2] = {0, 0};
+    int32_t host[3] = {0, 0, 0};
     HIPCHK(ctx, hipMemcpyAsync(&host[0], flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(&host[2], flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipMemcpyAsync(&host[1], start + g.ncell_ext, sizeof(int32_t),
                                hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (host[0]) return set_err(ctx, MDLJ_ERR_NONFINITE, "non-finite particle position");
     const int64_t n_ext = host[1];
     if (n_ext < n) return set_err(ctx, MDLJ_ERR_HIP, "binning lost particles");
+    ctx->max_cell = host[2];
     STCHK(ensure(ctx, ctx->b_sorted, sizeof(PosT) * n_ext));
     STCHK(ensure(ctx, ctx->b_misc, sizeof(int32_t) * n_ext));
     STCHK(ensure(ctx, ctx->b_img, sizeof(char4) * n_ext));
@@ -492,17 +499,21 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     return MDLJ_OK;
 }
 
-mdlj_status unpermute_forces(mdlj_ctx *ctx, const ForceOut &fo, bool fold, double *ox,
-                             double *oy, double *oz)
+mdlj_status fold_forces(mdlj_ctx *ctx, const ForceOut &fo)
 {
-    hipStream_t s = ctx->stream;
     const int TB = 256;
-    if (fold)
-        k_fold<<<ceil_div(ctx->n_ext, TB), TB, 0, s>>>(ctx->n_ext, (const PosT *)ctx->b_sorted.p,
-                                                        (const int32_t *)ctx->b_slot_of.p, fo.fx,
-                                                        fo.fy, fo.fz);
-    k_unpermute<<<ceil_div(ctx->n, TB), TB, 0, s>>>(ctx->n, (const int32_t *)ctx->b_slot_of.p,
-                                                     fo.fx, fo.fy, fo.fz, ox, oy, oz);
+    k_fold<<<ceil_div(ctx->n_ext, TB), TB, 0, ctx->stream>>>(
+        ctx->n_ext, (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_slot_of.p, fo.fx, fo.fy,
+        fo.fz);
+    HIPCHK(ctx, hipGetLastError());
+    return MDLJ_OK;
+}
+
+mdlj_status unpermute_forces(mdlj_ctx *ctx, const ForceOut &fo, double *ox, double *oy, double *oz)
+{
+    const int TB = 256;
+    k_unpermute<<<ceil_div(ctx->n, TB), TB, 0, ctx->stream>>>(ctx->n, (const int32_t *)ctx->b_slot_of.p,
+                                                              fo.fx, fo.fy, fo.fz, ox, oy, oz);
     HIPCHK(ctx, hipGetLastError());
     return MDLJ_OK;
 }

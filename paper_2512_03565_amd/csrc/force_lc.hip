@@ -89,11 +89,13 @@ __global__ __launch_bounds__(64) void k_lc_ipl(const PosT *__restrict__ rec,
     if (E) wave_partial(bu, bw, 0.5, fo.partial, blockIdx.x);
 }
 
-template <typename T, bool E, bool MS, int AI>
+template <typename T, bool E, bool MS, int AI, bool STAGED>
 __global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
                                                 const int32_t *__restrict__ start, Grid g,
-                                                LJTable<T> tab, ForceOut fo, int remap)
+                                                LJTable<T> tab, ForceOut fo, int remap,
+                                                int cmax)
 {
+    extern __shared__ double stage[];
     constexpr int AJ = MDLJ_WAVE / AI;
     __shared__ int seg_b[9];
     __shared__ int seg_c[10];
@@ -123,14 +125,37 @@ __global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
     }
     __syncthreads();
     const int C = seg_c[9];
+    double *sx = stage, *sy = stage + cmax, *sz = stage + 2 * cmax;
+    int *st = (int *)(stage + 3 * cmax);
+    if (STAGED) {
+        stage_rows(rec, seg_b, seg_c, C, sx, sy, sz, st, MS, lane, MDLJ_WAVE);
+        __syncthreads();
+    }
+    // local index of the cell's own first particle in the staged order
+    const int own0 = seg_c[4] + (ib - seg_b[4]);
     const int ii = lane / AJ, jl = lane % AJ;
     double bu = 0.0, bw = 0.0;
     for (int i0 = ib; i0 < ie; i0 += AI) {
         const int i = i0 + ii;
         const bool act = i < ie;
         const PosT pi = rec[act ? i : ib];
+        const int iloc = own0 + (i - ib);
         Acc a;
         acc_zero(a);
+        if (STAGED) {
+            for (int k0 = jl; k0 < C; k0 += UNROLL * AJ) {
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) {
+                    const int k = k0 + u * AJ;
+                    const bool ok = k < C;
+                    const int kk = ok ? k : 0;
+                    const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, MS ? st[kk] : 0);
+                    double fxp, fyp, fzp;
+                    lj_pair<T, E>(pi.x, pi.y, pi.z, sx[kk], sy[kk], sz[kk],
+                                  act && ok && k != iloc, p, rc2, a, fxp, fyp, fzp);
+                }
+            }
+        } else {
         int r = 0;
         // U candidates per trip: their record loads are in flight together
         for (int k0 = jl; k0 < C; k0 += UNROLL * AJ) {
@@ -154,6 +179,7 @@ __global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
                 lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x, pj[u].y, pj[u].z,
                               act && jj[u] >= 0 && jj[u] != i, p, rc2, a, fxp, fyp, fzp);
             }
+        }
         }
         a.fx = seg_sum(a.fx, AJ);
         a.fy = seg_sum(a.fy, AJ);
@@ -236,12 +262,29 @@ void launch_lc(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, For
     }
     const int64_t nb = g.ncell_int;
     *nblocks = nb;
+    if (cfg.staged) {
+        const int cmax = 27 * ctx->max_cell;
+        const size_t lds = (size_t)cmax * (3 * sizeof(double) + (MS ? sizeof(int) : 0));
+        if (lds > (size_t)STAGE_LDS_BYTES) {
+            *nblocks = -2;
+            return;
+        }
+        switch (cfg.tile_i) {
+        case 1: k_lc_tile<T, E, MS, 1, true><<<nb, 64, lds, s>>>(rec, start, g, tab, fo, remap, cmax); break;
+        case 2: k_lc_tile<T, E, MS, 2, true><<<nb, 64, lds, s>>>(rec, start, g, tab, fo, remap, cmax); break;
+        case 4: k_lc_tile<T, E, MS, 4, true><<<nb, 64, lds, s>>>(rec, start, g, tab, fo, remap, cmax); break;
+        case 8: k_lc_tile<T, E, MS, 8, true><<<nb, 64, lds, s>>>(rec, start, g, tab, fo, remap, cmax); break;
+        case 16: k_lc_tile<T, E, MS, 16, true><<<nb, 64, lds, s>>>(rec, start, g, tab, fo, remap, cmax); break;
+        default: *nblocks = -1;
+        }
+        return;
+    }
     switch (cfg.tile_i) {
-    case 1: k_lc_tile<T, E, MS, 1><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
-    case 2: k_lc_tile<T, E, MS, 2><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
-    case 4: k_lc_tile<T, E, MS, 4><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
-    case 8: k_lc_tile<T, E, MS, 8><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
-    case 16: k_lc_tile<T, E, MS, 16><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap); break;
+    case 1: k_lc_tile<T, E, MS, 1, false><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap, 0); break;
+    case 2: k_lc_tile<T, E, MS, 2, false><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap, 0); break;
+    case 4: k_lc_tile<T, E, MS, 4, false><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap, 0); break;
+    case 8: k_lc_tile<T, E, MS, 8, false><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap, 0); break;
+    case 16: k_lc_tile<T, E, MS, 16, false><<<nb, 64, 0, s>>>(rec, start, g, tab, fo, remap, 0); break;
     default: *nblocks = -1;
     }
 }
@@ -267,6 +310,7 @@ mdlj_status lc_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
         if (ms) launch_lc<T, false, true>(ctx, cfg, tab, fo, &nb, remap);
         else launch_lc<T, false, false>(ctx, cfg, tab, fo, &nb, remap);
     }
+    if (nb == -2) return set_err(ctx, MDLJ_ERR_ARG, "cell neighbourhood too large for LDS staging");
     if (nb < 0) return set_err(ctx, MDLJ_ERR_ARG, "unsupported linked-cell tile shape");
     HIPCHK(ctx, hipGetLastError());
     *nblocks = nb;

@@ -67,6 +67,56 @@ __global__ void k_refresh(int64_t n_ext, PosT *__restrict__ rec, const char4 *__
     rec[k].z = z[o] + (double)c.z * lz;
 }
 
+// Sorted forces (read through slot_of) drive the kicks, so no separate
+// un-permute pass is needed between steps.
+// v += F dt / m; x += v dt  (the second half kick of one step fused with the
+// first half kick and the drift of the next)
+__global__ void k_kick_drift_sorted(int64_t n, double *__restrict__ x, double *__restrict__ y,
+                                    double *__restrict__ z, double *__restrict__ vx,
+                                    double *__restrict__ vy, double *__restrict__ vz,
+                                    const double *__restrict__ fx, const double *__restrict__ fy,
+                                    const double *__restrict__ fz,
+                                    const int32_t *__restrict__ slot_of,
+                                    const int32_t *__restrict__ type, InvMass im, double dt)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t s = slot_of[i];
+    const double h = 0.5 * dt * im.v[type[i]];
+    // two half kicks, rounded as the unfused form would round them
+    const double ux = (vx[i] + h * fx[s]) + h * fx[s];
+    const double uy = (vy[i] + h * fy[s]) + h * fy[s];
+    const double uz = (vz[i] + h * fz[s]) + h * fz[s];
+    vx[i] = ux;
+    vy[i] = uy;
+    vz[i] = uz;
+    x[i] += dt * ux;
+    y[i] += dt * uy;
+    z[i] += dt * uz;
+}
+
+// v += F dt / (2m) from sorted forces; also writes the caller-order forces
+__global__ void k_kick_sorted(int64_t n, double *__restrict__ vx, double *__restrict__ vy,
+                              double *__restrict__ vz, const double *__restrict__ fx,
+                              const double *__restrict__ fy, const double *__restrict__ fz,
+                              const int32_t *__restrict__ slot_of,
+                              const int32_t *__restrict__ type, InvMass im, double dt,
+                              double *__restrict__ ox, double *__restrict__ oy,
+                              double *__restrict__ oz)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t s = slot_of[i];
+    const double h = 0.5 * dt * im.v[type[i]];
+    const double gx = fx[s], gy = fy[s], gz = fz[s];
+    vx[i] += h * gx;
+    vy[i] += h * gy;
+    vz[i] += h * gz;
+    ox[i] = gx;
+    oy[i] = gy;
+    oz[i] = gz;
+}
+
 // flag := 1 if any particle moved more than sqrt(thr2) since the reference
 __global__ void k_displacement(int64_t n, const double *__restrict__ x,
                                const double *__restrict__ y, const double *__restrict__ z,
@@ -93,9 +143,13 @@ mdlj_status save_reference(mdlj_ctx *ctx)
     return MDLJ_OK;
 }
 
-mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far)
+mdlj_status launch_displacement_check(mdlj_ctx *ctx)
 {
     const int64_t n = ctx->n;
+    if (!ctx->h_flag) {
+        HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocDefault));
+        HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_flag, hipEventDisableTiming));
+    }
     int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
     HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
     const double h = 0.5 * ctx->skin;
@@ -103,11 +157,23 @@ mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far)
                                                              (const double *)ctx->b_xref.p, h * h,
                                                              flag);
     HIPCHK(ctx, hipGetLastError());
-    int32_t hf = 0;
-    HIPCHK(ctx, hipMemcpyAsync(&hf, flag, sizeof hf, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    *too_far = hf != 0;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_flag, flag, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->ev_flag, ctx->stream));
     return MDLJ_OK;
+}
+
+mdlj_status check_result(mdlj_ctx *ctx, bool *too_far)
+{
+    HIPCHK(ctx, hipEventSynchronize(ctx->ev_flag));
+    *too_far = ctx->h_flag[0] != 0;
+    return MDLJ_OK;
+}
+
+mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far)
+{
+    STCHK(launch_displacement_check(ctx));
+    return check_result(ctx, too_far);
 }
 
 mdlj_status refresh_records(mdlj_ctx *ctx)
@@ -131,17 +197,30 @@ mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double d
     const int64_t n = ctx->n;
     const InvMass im = inv_mass(ctx);
     const int TB = 256;
+    const int64_t nb = ceil_div(n, TB);
+    if (nsteps == 0) return MDLJ_OK;
     if (!ctx->forces_valid) STCHK(forces_internal(ctx, ctx->pos_changed, nullptr));
     ctx->pos_changed = false;
+    // first half kick and drift from the caller-order forces of x(t)
+    k_kick_drift<<<nb, TB, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z, vx, vy, vz, ctx->fx,
+                                             ctx->fy, ctx->fz, ctx->type, im, dt);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->forces_valid = false;
     for (int s = 0; s < nsteps; ++s) {
-        k_kick_drift<<<ceil_div(n, TB), TB, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z, vx, vy, vz,
-                                                              ctx->fx, ctx->fy, ctx->fz, ctx->type,
-                                                              im, dt);
-        HIPCHK(ctx, hipGetLastError());
-        STCHK(forces_internal(ctx, true, nullptr));
-        k_kick<<<ceil_div(n, TB), TB, 0, ctx->stream>>>(n, vx, vy, vz, ctx->fx, ctx->fy, ctx->fz,
-                                                        ctx->type, im, dt);
+        ForceOut fo;
+        STCHK(forces_internal(ctx, true, nullptr, &fo, false));
+        const int32_t *slot_of = (const int32_t *)ctx->b_slot_of.p;
+        if (s + 1 < nsteps) {
+            k_kick_drift_sorted<<<nb, TB, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z, vx, vy, vz,
+                                                            fo.fx, fo.fy, fo.fz, slot_of,
+                                                            ctx->type, im, dt);
+        } else {
+            k_kick_sorted<<<nb, TB, 0, ctx->stream>>>(n, vx, vy, vz, fo.fx, fo.fy, fo.fz, slot_of,
+                                                      ctx->type, im, dt, ctx->fx, ctx->fy,
+                                                      ctx->fz);
+        }
         HIPCHK(ctx, hipGetLastError());
     }
+    ctx->forces_valid = true;
     return MDLJ_OK;
 }

@@ -78,7 +78,7 @@ struct mdlj_ctx {
     int rebuild_every = 10;
     int shift_on = 1;
     int prec = MDLJ_PREC_F32PAIR_F64ACC;
-    mdlj_config cfg = {MDLJ_NBR_LC, MDLJ_ORD_I_PER_LANE, 1, 0, 0, 0};
+    mdlj_config cfg = {MDLJ_NBR_LC, MDLJ_ORD_I_PER_LANE, 1, 1, 0, 0, 0};
     std::string err;
 
     // caller-order particle state (device)
@@ -90,12 +90,14 @@ struct mdlj_ctx {
 
     // neighbour structure state
     bool built = false;           // structure matches cfg/positions
-    mdlj_config built_cfg = {-1, -1, -1, -1, -1, -1};
+    mdlj_config built_cfg = {-1, -1, -1, -1, -1, -1, -1};
     int steps_since_build = 0;
     double built_box[3] = {0, 0, 0};
     double built_rc = -1, built_skin = -1;
     Grid grid{};
     int64_t n_ext = 0;            // real + halo slots
+    int32_t max_cell = 0;         // most particles in one cell of the last binning
+    int32_t max_nbhd = 0;         // most particles in one 27-cell neighbourhood (VL build)
     int64_t nbr_cap = 0;          // Verlet list capacity per particle
     int64_t vl_max = 0;           // longest list of the last build
     int64_t vcl_cap = 0;          // cluster-pair list capacity per cluster
@@ -123,9 +125,17 @@ struct mdlj_ctx {
     // reusable host scratch
     std::vector<double> h_partial;
 
-    // kernel timing (HIP events on the context's stream)
+    // kernel timing (HIP events on the context's stream), read lazily
+    struct Timed {
+        hipEvent_t e0, e1, e2;
+        bool rebuilt;
+    };
     bool timing = false;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<Timed> ev_pending;
+    // displacement check result (pinned host memory) and its event
+    int32_t *h_flag = nullptr;
+    hipEvent_t ev_flag = nullptr;
     double t_force_us = 0, t_build_us = 0;
     int64_t t_nforce = 0, t_nbuild = 0;
     double last_force_us = 0, last_build_us = 0;
@@ -152,10 +162,11 @@ mdlj_status ensure(mdlj_ctx *ctx, DevBuf &b, size_t bytes);
 // Bins the caller-order positions into g (wrapping them in place), writes
 // the sorted real + halo records and slot_of[i] (slot of caller particle i).
 mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g);
-// Sorted FP64 forces (slots [0, n_ext)) back to caller order; when fold is
-// set, halo slots are first added onto the slot of the particle they copy.
-mdlj_status unpermute_forces(mdlj_ctx *ctx, const ForceOut &fo, bool fold, double *ox,
-                             double *oy, double *oz);
+// Halo slots carry forces applied to images by Newton-3 kernels: add them
+// onto the slot of the particle they copy.
+mdlj_status fold_forces(mdlj_ctx *ctx, const ForceOut &fo);
+// Sorted FP64 forces back to caller order.
+mdlj_status unpermute_forces(mdlj_ctx *ctx, const ForceOut &fo, double *ox, double *oy, double *oz);
 mdlj_status zero_forces(mdlj_ctx *ctx, const ForceOut &fo, int64_t nslots);
 // Sum of per-block (U, W) partials.
 mdlj_status reduce_partials(mdlj_ctx *ctx, const double *partial, int64_t nblocks,
@@ -171,6 +182,10 @@ mdlj_status check_finite(mdlj_ctx *ctx, const double *x, const double *y, const 
 // --- integrator and record upkeep (integrate.hip) ---------------------------
 mdlj_status save_reference(mdlj_ctx *ctx);
 mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far);
+// Enqueue the skin/2 displacement check; its result lands in pinned host
+// memory behind ctx->ev_flag (read with check_result).
+mdlj_status launch_displacement_check(mdlj_ctx *ctx);
+mdlj_status check_result(mdlj_ctx *ctx, bool *too_far);
 mdlj_status refresh_records(mdlj_ctx *ctx);
 mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt, int nsteps);
 
@@ -179,9 +194,14 @@ mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double d
 mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed, bool *rebuilt);
 mdlj_status run_force_kernel(mdlj_ctx *ctx, const mdlj_config &c, bool energy, ForceOut &fo,
                              int64_t *nblocks);
-// Full evaluation with the current configuration into ctx->fx/fy/fz
-// (caller order); UW (host, may be null) receives U and W.
-mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW);
+// Full evaluation with the current configuration.  Sorted forces (halo
+// images folded) are returned in *fo when fo is given; when to_caller is set
+// they are also written to ctx->fx/fy/fz in caller order.  UW (host, may be
+// null) receives U and W (this synchronises).
+mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW, ForceOut *fo = nullptr,
+                            bool to_caller = true);
+// Sum up timed calls whose events have completed (synchronises).
+mdlj_status collect_timing(mdlj_ctx *ctx);
 bool needs_fold(const mdlj_config &c);
 
 // --- tuning (tune.cpp, mlp.hip) ---------------------------------------------

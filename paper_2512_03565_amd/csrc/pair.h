@@ -144,3 +144,24 @@ __device__ __forceinline__ void wave_partial(double u, double w, double scale, d
         partial[2 * blk + 1] = scale * w;
     }
 }
+
+// LDS staging of a cell's 27-cell neighbourhood: the nine contiguous runs of
+// sorted records (rows of three cells) are copied into LDS as separate x, y,
+// z (FP64) and species arrays, candidate k at index k.  At most this many
+// bytes of LDS per workgroup are used for it.
+constexpr int STAGE_LDS_BYTES = 64 * 1024;
+
+__device__ __forceinline__ void stage_rows(const PosT *__restrict__ rec, const int *seg_b,
+                                           const int *seg_c, int C, double *sx, double *sy,
+                                           double *sz, int *st, bool types, int lane, int nthr)
+{
+    int r = 0;
+    for (int k = lane; k < C; k += nthr) {
+        while (k >= seg_c[r + 1]) ++r;
+        const PosT p = rec[seg_b[r] + (k - seg_c[r])];
+        sx[k] = p.x;
+        sy[k] = p.y;
+        sz[k] = p.z;
+        if (types) st[k] = p.t;
+    }
+}

@@ -19,6 +19,33 @@
 
 #include "internal.h"
 
+// Reduce S samples of each of K configurations (row-major [K][S], +inf or
+// NaN for a configuration that cannot run) to one value each -- the mean
+// with the first sample dropped as warm-up (mode 0, all S when S == 1) or
+// the minimum (mode 1) -- and pick the smallest, lower index on ties.
+// Returns the chosen index or -1 when none is finite.
+static int select_config(const double *samples, int K, int S, int mode, double *values)
+{
+    int best = -1;
+    for (int k = 0; k < K; ++k) {
+        const double *row = samples + (size_t)k * S;
+        double v;
+        if (mode == 1) {
+            v = std::numeric_limits<double>::infinity();
+            for (int s = 0; s < S; ++s) v = row[s] < v ? row[s] : v;
+        } else {
+            const int first = S > 1 ? 1 : 0;
+            double sum = 0;
+            for (int s = first; s < S; ++s) sum += row[s];
+            v = sum / (S - first);
+        }
+        if (!(v == v)) v = std::numeric_limits<double>::infinity();  // NaN -> cannot run
+        values[k] = v;
+        if (v < std::numeric_limits<double>::infinity() && (best < 0 || v < values[best])) best = k;
+    }
+    return best;
+}
+
 namespace {
 
 struct Events {
@@ -62,22 +89,19 @@ mdlj_status measure(mdlj_ctx *ctx, const mdlj_config &c, int samples, double *ou
         HIPCHK(ctx, hipEventRecord(ev.b, ctx->stream));
         STCHK(elapsed_us(ctx, ev, &upkeep_us));
     }
-    double sum = 0;
-    int cnt = 0;
+    std::vector<double> t(samples);
     for (int s = 0; s < samples; ++s) {
         ForceOut fo;
         int64_t nb = 0;
         HIPCHK(ctx, hipEventRecord(ev.a, ctx->stream));
         STCHK(run_force_kernel(ctx, c, false, fo, &nb));
-        STCHK(unpermute_forces(ctx, fo, needs_fold(c), ctx->fx, ctx->fy, ctx->fz));
+        if (needs_fold(c)) STCHK(fold_forces(ctx, fo));
+        STCHK(unpermute_forces(ctx, fo, ctx->fx, ctx->fy, ctx->fz));
         HIPCHK(ctx, hipEventRecord(ev.b, ctx->stream));
-        double us = 0;
-        STCHK(elapsed_us(ctx, ev, &us));
-        if (s == 0 && samples > 1) continue;  // warm-up sample
-        sum += us;
-        ++cnt;
+        STCHK(elapsed_us(ctx, ev, &t[s]));
     }
-    double force_us = sum / (cnt > 0 ? cnt : 1);
+    double force_us = 0;
+    select_config(t.data(), 1, samples, 0, &force_us);
     if (c.nbr_algo == MDLJ_NBR_LC) {
         *out = force_us + build_us;
     } else {
@@ -154,6 +178,31 @@ mdlj_status mdlj_tune(mdlj_ctx *ctx, int32_t mode, int32_t samples, mdlj_config 
     }
     if (chosen) *chosen = ctx->cfg;
     if (step_us) *step_us = us;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_tune_select(const double *samples, int32_t k, int32_t s, int32_t mode,
+                             double *values, int32_t *chosen)
+{
+    if (!samples || !values || !chosen || k < 1 || s < 1 || (mode != 0 && mode != 1))
+        return MDLJ_ERR_ARG;
+    *chosen = select_config(samples, k, s, mode, values);
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_retune_needed(const float *before8, const float *now8, double threshold,
+                               int32_t *needed)
+{
+    if (!before8 || !now8 || !needed || !(threshold >= 0)) return MDLJ_ERR_ARG;
+    // density (feature 1) and cell-occupancy spread (feature 5) are the
+    // quantities whose change moves the optimum (section 5)
+    const int idx[2] = {1, 5};
+    *needed = 0;
+    for (int q = 0; q < 2; ++q) {
+        const double a = before8[idx[q]], b = now8[idx[q]];
+        const double den = fabs(a) > 1e-12 ? fabs(a) : 1e-12;
+        if (fabs(b - a) / den > threshold) *needed = 1;
+    }
     return MDLJ_OK;
 }
 

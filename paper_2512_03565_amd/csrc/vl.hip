@@ -13,6 +13,8 @@
 //     forces are then summed over the segment.
 // Lists index the sorted records, halo images included, so no minimum
 // image is applied in the force loop.
+#include <algorithm>
+
 #include "pair.h"
 
 namespace {
@@ -44,14 +46,21 @@ __global__ __launch_bounds__(256) void k_vl_build(const PosT *__restrict__ rec,
             const int dy = r % 3 - 1, dz = r / 3 - 1;
             const int64_t ej = e + dy * g.stride[1] + dz * g.stride[2] - 1;
             const int32_t jb = start[ej], je = start[ej + 3];
-            for (int32_t j = jb; j < je; ++j) {
-                const PosT pj = rec[j];
-                const double dx = pi.x - pj.x, dyy = pi.y - pj.y, dzz = pi.z - pj.z;
-                const bool in = (j != i) && (dx * dx + dyy * dyy + dzz * dzz < rl2) &&
-                                (!half || pj.orig > pi.orig);
-                if (in) {
-                    if (cnt < cap) out[(int64_t)cnt * sk] = j;
-                    ++cnt;
+            for (int32_t j0 = jb; j0 < je; j0 += UNROLL) {
+                PosT pj[UNROLL];
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) pj[u] = rec[j0 + u < je ? j0 + u : jb];
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) {
+                    const int32_t j = j0 + u;
+                    const double dx = pi.x - pj[u].x, dyy = pi.y - pj[u].y, dzz = pi.z - pj[u].z;
+                    const bool in = j < je && (j != i) &&
+                                    (dx * dx + dyy * dyy + dzz * dzz < rl2) &&
+                                    (!half || pj[u].orig > pi.orig);
+                    if (in) {
+                        if (cnt < cap) out[(int64_t)cnt * sk] = j;
+                        ++cnt;
+                    }
                 }
             }
         }
@@ -60,6 +69,143 @@ __global__ __launch_bounds__(256) void k_vl_build(const PosT *__restrict__ rec,
     // longest list of the wavefront, one atomic per wavefront
     for (int o = 32; o > 0; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o));
     if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0 && cnt > 0) atomicMax(maxlen, cnt);
+}
+
+// Cell-local lists for the staged kernel: entry = index of j in the
+// concatenation of the nine neighbour rows of i's cell (the order in which
+// the force kernel stages them into LDS), 16 bits, row-major per i.
+__global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__ rec,
+                                                        const int32_t *__restrict__ start,
+                                                        const int32_t *__restrict__ ilist,
+                                                        const int32_t *__restrict__ cell_of,
+                                                        Grid g, int64_t n, double rl2,
+                                                        int32_t cap, uint16_t *__restrict__ nbr,
+                                                        int32_t *__restrict__ len,
+                                                        int32_t *__restrict__ maxlen,
+                                                        int32_t *__restrict__ maxnb)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t cnt = 0, base = 0;
+    if (t < n) {
+        const int32_t i = ilist[t];
+        const PosT pi = rec[i];
+        const int64_t e = cell_of[pi.orig];
+        uint16_t *out = nbr + t * cap;
+        for (int r = 0; r < 9; ++r) {
+            const int dy = r % 3 - 1, dz = r / 3 - 1;
+            const int64_t ej = e + dy * g.stride[1] + dz * g.stride[2] - 1;
+            const int32_t jb = start[ej], je = start[ej + 3];
+            for (int32_t j0 = jb; j0 < je; j0 += UNROLL) {
+                PosT pj[UNROLL];
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) pj[u] = rec[j0 + u < je ? j0 + u : jb];
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) {
+                    const int32_t j = j0 + u;
+                    const double dx = pi.x - pj[u].x, dyy = pi.y - pj[u].y, dzz = pi.z - pj[u].z;
+                    if (j < je && j != i && dx * dx + dyy * dyy + dzz * dzz < rl2) {
+                        if (cnt < cap) out[cnt] = (uint16_t)(base + (j - jb));
+                        ++cnt;
+                    }
+                }
+            }
+            base += je - jb;
+        }
+        len[t] = cnt;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        cnt = max(cnt, __shfl_xor(cnt, o));
+        base = max(base, __shfl_xor(base, o));
+    }
+    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0) {
+        if (cnt > 0) atomicMax(maxlen, cnt);
+        if (base > 0) atomicMax(maxnb, base);
+    }
+}
+
+// Staged wave-per-i: one workgroup (one wavefront) per cell stages the
+// cell's 27-cell neighbourhood in LDS, then g i's at a time, 64/g lanes per
+// i, stride along the cell-local lists and read j from LDS.
+template <typename T, bool E, bool MS, int G>
+__global__ __launch_bounds__(64) void k_vl_lds(const PosT *__restrict__ rec,
+                                               const int32_t *__restrict__ start,
+                                               const int32_t *__restrict__ ibase, Grid g,
+                                               const uint16_t *__restrict__ nbr,
+                                               const int32_t *__restrict__ len, int32_t cap,
+                                               int cmax, LJTable<T> tab, ForceOut fo, int remap)
+{
+    constexpr int SEG = MDLJ_WAVE / G;
+    extern __shared__ double stage[];
+    __shared__ int seg_b[9];
+    __shared__ int seg_c[10];
+    __shared__ LdsTable<T> lt;
+    const double rc2 = tab.rc2d;
+    const int lane = threadIdx.x;
+    if (MS) lds_table_load(lt, tab, lane, MDLJ_WAVE);
+    const int64_t c = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int cx = (int)(c % g.n[0]);
+    const int cy = (int)((c / g.n[0]) % g.n[1]);
+    const int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
+                       cx + g.h[0];
+    const int ib = start[ei], ie = start[ei + 1];
+    if (lane < 9) {
+        const int dy = lane % 3 - 1, dz = lane / 3 - 1;
+        const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
+                           (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx - 1 + g.h[0];
+        seg_b[lane] = start[ej];
+        seg_c[lane + 1] = start[ej + 3] - start[ej];
+    }
+    __syncthreads();
+    if (lane == 0) {
+        seg_c[0] = 0;
+        for (int r = 0; r < 9; ++r) seg_c[r + 1] += seg_c[r];
+    }
+    __syncthreads();
+    const int C = seg_c[9];
+    double *sx = stage, *sy = stage + cmax, *sz = stage + 2 * cmax;
+    int *st = (int *)(stage + 3 * cmax);
+    stage_rows(rec, seg_b, seg_c, C, sx, sy, sz, st, MS, lane, MDLJ_WAVE);
+    __syncthreads();
+    const int64_t t0 = ibase[c];
+    const int l = lane % SEG;
+    double bu = 0.0, bw = 0.0;
+    for (int i0 = ib; i0 < ie; i0 += G) {
+        const int i = i0 + lane / SEG;
+        const bool act = i < ie;
+        const PosT pi = rec[act ? i : ib];
+        const int64_t t = t0 + (act ? i - ib : 0);
+        const int32_t L = act ? len[t] : 0;
+        const uint16_t *row = nbr + t * cap;
+        Acc a;
+        acc_zero(a);
+        for (int32_t k0 = l; k0 < L; k0 += UNROLL * SEG) {
+            int kk[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) kk[u] = k0 + u * SEG < L ? (int)row[k0 + u * SEG] : -1;
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const int k = kk[u] >= 0 ? kk[u] : 0;
+                const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, MS ? st[k] : 0);
+                double fxp, fyp, fzp;
+                lj_pair<T, E>(pi.x, pi.y, pi.z, sx[k], sy[k], sz[k], kk[u] >= 0, p, rc2, a, fxp,
+                              fyp, fzp);
+            }
+        }
+        a.fx = seg_sum(a.fx, SEG);
+        a.fy = seg_sum(a.fy, SEG);
+        a.fz = seg_sum(a.fz, SEG);
+        if (act && l == 0) {
+            fo.fx[i] = a.fx;
+            fo.fy[i] = a.fy;
+            fo.fz[i] = a.fz;
+        }
+        if (E) {
+            bu += a.u;
+            bw += a.w;
+        }
+    }
+    if (E) wave_partial(bu, bw, 0.5, fo.partial, blockIdx.x);
 }
 
 // i-per-lane over ELL lists.
@@ -207,6 +353,23 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         return nb * (TB / MDLJ_WAVE);
     }
     const int32_t cap = (int32_t)ctx->nbr_cap;
+    if (cfg.staged) {
+        const Grid &g = ctx->grid;
+        const int cmax = ctx->max_nbhd;
+        const size_t lds = (size_t)cmax * (3 * sizeof(double) + (MS ? sizeof(int) : 0));
+        if (lds > (size_t)STAGE_LDS_BYTES || N3) return -2;
+        const int64_t nbc = g.ncell_int;
+        const int32_t *ibase = (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1;
+        const uint16_t *nbr16 = (const uint16_t *)ctx->b_nbr.p;
+        const int32_t *start = (const int32_t *)ctx->b_start.p;
+        switch (cfg.tile_i) {
+        case 2: k_vl_lds<T, E, MS, 2><<<nbc, 64, lds, s>>>(rec, start, ibase, g, nbr16, len, cap, cmax, tab, fo, remap); break;
+        case 4: k_vl_lds<T, E, MS, 4><<<nbc, 64, lds, s>>>(rec, start, ibase, g, nbr16, len, cap, cmax, tab, fo, remap); break;
+        case 8: k_vl_lds<T, E, MS, 8><<<nbc, 64, lds, s>>>(rec, start, ibase, g, nbr16, len, cap, cmax, tab, fo, remap); break;
+        default: return -1;
+        }
+        return nbc;
+    }
     const int64_t waves = ceil_div(n, cfg.tile_i);
     const int64_t nb = ceil_div(waves, TB / MDLJ_WAVE);
     switch (cfg.tile_i) {
@@ -238,7 +401,7 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
     if (cfg.newton3) STCHK(zero_forces(ctx, fo, ctx->n_ext));
     int64_t nw;
     if (energy) {
-        const int64_t maxw = ctx->n + 64;  // >= waves of every launch shape
+        const int64_t maxw = std::max<int64_t>(ctx->n + 64, ctx->grid.ncell_int);
         STCHK(ensure(ctx, ctx->b_partial, sizeof(double) * 2 * maxw));
         fo.partial = (double *)ctx->b_partial.p;
         nw = ms ? launch_vl_n3<T, true, true>(ctx, cfg, tab, fo, remap)
@@ -247,6 +410,7 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
         nw = ms ? launch_vl_n3<T, false, true>(ctx, cfg, tab, fo, remap)
                 : launch_vl_n3<T, false, false>(ctx, cfg, tab, fo, remap);
     }
+    if (nw == -2) return set_err(ctx, MDLJ_ERR_ARG, "neighbourhood too large for LDS staging");
     if (nw < 0) return set_err(ctx, MDLJ_ERR_ARG, "unsupported Verlet-list shape");
     HIPCHK(ctx, hipGetLastError());
     *nblocks = nw;
@@ -268,28 +432,43 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
     cap = (cap + 3) & ~(int64_t)3;
     STCHK(ensure(ctx, ctx->b_nlen, sizeof(int32_t) * n));
     int32_t *maxlen = (int32_t *)ctx->b_flags.p + 12;
+    int32_t *maxnb = (int32_t *)ctx->b_flags.p + 14;
     const bool rowmajor = cfg.order != MDLJ_ORD_I_PER_LANE;
+    const bool local = cfg.staged != 0;
+    const size_t esize = local ? sizeof(uint16_t) : sizeof(int32_t);
     for (int attempt = 0; attempt < 3; ++attempt) {
-        if ((double)cap * (double)n * 4.0 > 64e9) return set_err(ctx, MDLJ_ERR_OVERFLOW, "Verlet lists too large");
-        STCHK(ensure(ctx, ctx->b_nbr, sizeof(int32_t) * n * cap));
-        HIPCHK(ctx, hipMemsetAsync(maxlen, 0, sizeof(int32_t), ctx->stream));
-        const int64_t sk = rowmajor ? 1 : n;
-        const int64_t st = rowmajor ? cap : 1;
-        k_vl_build<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
-            (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
-            (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, g, n, rl * rl,
-            cfg.newton3 ? 1 : 0, sk, st, (int32_t)cap, (int32_t *)ctx->b_nbr.p,
-            (int32_t *)ctx->b_nlen.p, maxlen);
+        if ((double)cap * (double)n * (double)esize > 64e9)
+            return set_err(ctx, MDLJ_ERR_OVERFLOW, "Verlet lists too large");
+        STCHK(ensure(ctx, ctx->b_nbr, esize * n * cap));
+        HIPCHK(ctx, hipMemsetAsync(maxlen, 0, 4 * sizeof(int32_t), ctx->stream));
+        if (local) {
+            k_vl_build_local<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
+                (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
+                (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, g, n, rl * rl,
+                (int32_t)cap, (uint16_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen, maxnb);
+        } else {
+            const int64_t sk = rowmajor ? 1 : n;
+            const int64_t st = rowmajor ? cap : 1;
+            k_vl_build<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
+                (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
+                (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, g, n, rl * rl,
+                cfg.newton3 ? 1 : 0, sk, st, (int32_t)cap, (int32_t *)ctx->b_nbr.p,
+                (int32_t *)ctx->b_nlen.p, maxlen);
+        }
         HIPCHK(ctx, hipGetLastError());
-        int32_t hmax = 0;
-        HIPCHK(ctx, hipMemcpyAsync(&hmax, maxlen, sizeof hmax, hipMemcpyDeviceToHost, ctx->stream));
+        int32_t hmax[3] = {0, 0, 0};
+        HIPCHK(ctx, hipMemcpyAsync(hmax, maxlen, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        ctx->vl_max = hmax;
-        if (hmax <= cap) {
+        ctx->vl_max = hmax[0];
+        ctx->max_nbhd = hmax[2];
+        if (local && hmax[2] > 65535)
+            return set_err(ctx, MDLJ_ERR_ARG, "neighbourhood too large for 16-bit local lists");
+        if (hmax[0] <= cap) {
             ctx->nbr_cap = cap;
             return MDLJ_OK;
         }
-        cap = ((int64_t)(hmax * 1.1) + 8 + 3) & ~(int64_t)3;
+        cap = ((int64_t)(hmax[0] * 1.1) + 8 + 3) & ~(int64_t)3;
     }
     return set_err(ctx, MDLJ_ERR_OVERFLOW, "Verlet list capacity could not be grown");
 }

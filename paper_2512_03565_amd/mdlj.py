@@ -31,11 +31,12 @@ ORD_NAMES = {0: "i-per-lane", 1: "cluster-tile", 2: "wave-per-i"}
 
 class mdlj_config(C.Structure):
     _fields_ = [("nbr_algo", C.c_int32), ("order", C.c_int32), ("tile_i", C.c_int32),
-                ("tile_j", C.c_int32), ("cluster_size", C.c_int32), ("newton3", C.c_int32)]
+                ("tile_j", C.c_int32), ("cluster_size", C.c_int32), ("newton3", C.c_int32),
+                ("staged", C.c_int32)]
 
     def astuple(self):
         return (self.nbr_algo, self.order, self.tile_i, self.tile_j, self.cluster_size,
-                self.newton3)
+                self.newton3, self.staged)
 
     def __repr__(self):
         return config_name(self)
@@ -43,13 +44,14 @@ class mdlj_config(C.Structure):
 
 def config_name(c) -> str:
     t = c.astuple() if hasattr(c, "astuple") else tuple(c)
-    nb, o, ti, tj, m, n3 = t
+    t = tuple(t) + (0,) * (7 - len(t))
+    nb, o, ti, tj, m, n3, st = t
     s = NBR_NAMES[nb] + (str(m) if nb == NBR_VCL else "") + "/" + ORD_NAMES[o]
     if o == ORD_I_PER_LANE and nb == NBR_LC:
         s += f"/k{ti}"
     elif o != ORD_I_PER_LANE:
         s += f"/{ti}x{tj}"
-    return s + ("/n3" if n3 else "")
+    return s + ("/n3" if n3 else "") + ("/lds" if st else "")
 
 
 class MdljError(RuntimeError):
@@ -111,6 +113,9 @@ _SIGS = {
     "mdlj_mlp_train": [_ctxp, C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32, C.c_int32,
                        C.c_int32, C.c_double, C.c_uint64, C.POINTER(C.c_double)],
     "mdlj_mlp_stats": [_ctxp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+    "mdlj_tune_select": [_d, C.c_int32, C.c_int32, C.c_int32, _d, C.POINTER(C.c_int32)],
+    "mdlj_retune_needed": [C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_double,
+                           C.POINTER(C.c_int32)],
     "mdlj_get_timing": [_ctxp, _d, _d, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
 }
 for _name, _args in _SIGS.items():
@@ -390,6 +395,25 @@ class System:
         f = (C.c_float * 8)()
         check(lib.mdlj_features(self.ctx, f), self.ctx)
         return np.array(f[:], np.float32)
+
+
+def tune_select(samples, mode=0):
+    """Reduced value per configuration and the chosen index for a [K, S]
+    table of timings (the full-search decision rule of the tuner)."""
+    a = np.ascontiguousarray(np.atleast_2d(samples), np.float64)
+    vals = np.empty(a.shape[0])
+    ch = C.c_int32()
+    check(lib.mdlj_tune_select(a.ctypes.data_as(_d), a.shape[0], a.shape[1], int(mode),
+                               vals.ctypes.data_as(_d), C.byref(ch)))
+    return vals, ch.value
+
+
+def retune_needed(before, now, threshold=0.1):
+    b = np.ascontiguousarray(before, np.float32)
+    n = np.ascontiguousarray(now, np.float32)
+    out = C.c_int32()
+    check(lib.mdlj_retune_needed(_fp(b), _fp(n), float(threshold), C.byref(out)))
+    return bool(out.value)
 
 
 def version() -> str:

@@ -24,9 +24,11 @@ def m():
 
 
 def lc_configs(m):
-    return [(m.NBR_LC, m.ORD_I_PER_LANE, k, 1, 0, 0) for k in (1, 2, 4)] + \
-           [(m.NBR_LC, m.ORD_CLUSTER_TILE, a, 64 // a, 0, 0) for a in (8, 16)] + \
-           [(m.NBR_LC, m.ORD_WAVE_PER_I, g, 64 // g, 0, 0) for g in (1, 2, 4)]
+    out = [(m.NBR_LC, m.ORD_I_PER_LANE, k, 1, 0, 0, 0) for k in (1, 2, 4)]
+    for st in (0, 1):
+        out += [(m.NBR_LC, m.ORD_CLUSTER_TILE, a, 64 // a, 0, 0, st) for a in (8, 16)]
+        out += [(m.NBR_LC, m.ORD_WAVE_PER_I, g, 64 // g, 0, 0, st) for g in (1, 2, 4)]
+    return out
 
 
 def check_scene(m, orc, s, configs, precs=(0, 1), label=""):
