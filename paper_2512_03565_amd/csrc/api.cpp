@@ -108,10 +108,12 @@ static std::vector<mdlj_config> build_space()
     // Verlet lists
     for (int n3 : {0, 1}) {
         v.push_back({MDLJ_NBR_VL, MDLJ_ORD_I_PER_LANE, 0, 0, 0, n3, 0});
-        for (int g : {1, 2, 4, 8})
+        for (int g : {1, 2, 4, 8, 16})
             v.push_back({MDLJ_NBR_VL, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, n3, 0});
     }
-    for (int g : {2, 4, 8}) v.push_back({MDLJ_NBR_VL, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, 0, 1});
+    // staged: tile_i = i's per wavefront, tile_j = list entries per lane per trip
+    for (int gv : {802, 804, 1602, 1604, 408})
+        v.push_back({MDLJ_NBR_VL, MDLJ_ORD_WAVE_PER_I, gv / 100, gv % 100, 0, 0, 1});
     // Verlet cluster lists
     for (int m : {4, 8})
         for (int n3 : {0, 1}) {
@@ -303,11 +305,14 @@ mdlj_status collect_timing(mdlj_ctx *ctx)
 mdlj_status run_force_kernel(mdlj_ctx *ctx, const mdlj_config &c, bool energy, ForceOut &fo,
                              int64_t *nblocks)
 {
-    STCHK(ensure(ctx, ctx->b_fsorted, sizeof(double) * 3 * ctx->n_ext));
+    // one slot per record plus the padding record (Newton-3 kernels add
+    // zero to it); the padding slot is never read back
+    const int64_t stride = ctx->n_ext + 1;
+    STCHK(ensure(ctx, ctx->b_fsorted, sizeof(double) * 3 * stride));
     double *f = (double *)ctx->b_fsorted.p;
     fo.fx = f;
-    fo.fy = f + ctx->n_ext;
-    fo.fz = f + 2 * ctx->n_ext;
+    fo.fy = f + stride;
+    fo.fz = f + 2 * stride;
     fo.partial = nullptr;
     switch (c.nbr_algo) {
     case MDLJ_NBR_LC: return lc_forces(ctx, c, energy, fo, nblocks);

@@ -267,6 +267,18 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
     }
 }
 
+// The padding record at slot n_ext: far outside the box, no particle.
+__global__ void k_pad_record(PosT *__restrict__ rec, int64_t slot)
+{
+    if (threadIdx.x == 0) {
+        PosT p;
+        p.x = p.y = p.z = 1.0e7;
+        p.t = 0;
+        p.orig = -1;
+        rec[slot] = p;
+    }
+}
+
 __global__ void k_unpermute(int64_t n, const int32_t *__restrict__ slot_of,
                             const double *__restrict__ fx, const double *__restrict__ fy,
                             const double *__restrict__ fz, double *__restrict__ ox,
@@ -483,7 +495,7 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     const int64_t n_ext = host[1];
     if (n_ext < n) return set_err(ctx, MDLJ_ERR_HIP, "binning lost particles");
     ctx->max_cell = host[2];
-    STCHK(ensure(ctx, ctx->b_sorted, sizeof(PosT) * n_ext));
+    STCHK(ensure(ctx, ctx->b_sorted, sizeof(PosT) * (n_ext + 1)));
     STCHK(ensure(ctx, ctx->b_misc, sizeof(int32_t) * n_ext));
     STCHK(ensure(ctx, ctx->b_img, sizeof(char4) * n_ext));
     int32_t *sorted_orig = (int32_t *)ctx->b_misc.p;
@@ -493,6 +505,7 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     k_fill<<<ceil_div(g.ncell_ext, TB / MDLJ_WAVE), TB, 0, s>>>(
         g, start, sorted_orig, ctx->x, ctx->y, ctx->z, ctx->type, (PosT *)ctx->b_sorted.p,
         (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p);
+    k_pad_record<<<1, 64, 0, s>>>((PosT *)ctx->b_sorted.p, n_ext);
     HIPCHK(ctx, hipGetLastError());
     ctx->grid = g;
     ctx->n_ext = n_ext;

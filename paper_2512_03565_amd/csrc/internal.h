@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mdlj.h"
+#include "mdlj.h"
 
 #define MDLJ_MAX_SPECIES 8
 #define MDLJ_WAVE 64

@@ -101,7 +101,8 @@ __device__ __forceinline__ void lj_pair(double pxi, double pyi, double pzi, doub
     const T sr2 = p.sig2 * ir2;
     const T s6 = sr2 * sr2 * sr2;
     const T rf = p.eps24 * s6 * (T(2) * s6 - T(1));
-    const double fs = in ? (double)(rf * ir2) : 0.0;
+    const T fsT = in ? rf * ir2 : T(0);
+    const double fs = (double)fsT;
     fxp = fs * dx;
     fyp = fs * dy;
     fzp = fs * dz;
@@ -144,6 +145,32 @@ __device__ __forceinline__ void wave_partial(double u, double w, double scale, d
         partial[2 * blk + 1] = scale * w;
     }
 }
+
+// Raw buffer access to the sorted records: 32-bit byte offsets from one
+// descriptor (and hardware range checks, reads past the end return zero).
+// The descriptor's third dword is the gfx9-family default for raw buffers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t records_rsrc(const PosT *rec, int64_t count)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)rec, (short)0, (int)(count * sizeof(PosT)),
+                                             0x00020000);
+}
+
+// x, y, z of record j (one 16-byte and one 8-byte buffer load).
+__device__ __forceinline__ void load_xyz(__amdgpu_buffer_rsrc_t r, int32_t j, double &x, double &y,
+                                         double &z)
+{
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, j * (int)sizeof(PosT), 0, 0);
+    const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, j * (int)sizeof(PosT) + 16, 0, 0);
+    x = __builtin_bit_cast(double, (unsigned long long)a.x | ((unsigned long long)a.y << 32));
+    y = __builtin_bit_cast(double, (unsigned long long)a.z | ((unsigned long long)a.w << 32));
+    z = __builtin_bit_cast(double, (unsigned long long)b.x | ((unsigned long long)b.y << 32));
+}
+
+// Position of the padding record that list rows are filled up with: far
+// outside any box, so a pair with it never falls inside the cutoff.
+constexpr double PAD_COORD = 1.0e7;
 
 // LDS staging of a cell's 27-cell neighbourhood: the nine contiguous runs of
 // sorted records (rows of three cells) are copied into LDS as separate x, y,

@@ -417,7 +417,7 @@ mdlj_status vcl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, For
     fill_table<T>(ctx, &tab);
     const bool ms = ctx->nspec > 1;
     const int remap = 1;
-    if (cfg.newton3) STCHK(zero_forces(ctx, fo, ctx->n_ext));
+    if (cfg.newton3) STCHK(zero_forces(ctx, fo, ctx->n_ext + 1));
     int64_t nw;
     if (energy) {
         const int64_t maxw = ctx->n_ext + 64;

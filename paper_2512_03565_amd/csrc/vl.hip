@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_vl_build(const PosT *__restrict__ rec,
                                                   const int32_t *__restrict__ ilist,
                                                   const int32_t *__restrict__ cell_of, Grid g,
                                                   int64_t n, double rl2, int half, int64_t sk,
-                                                  int64_t st, int32_t cap,
+                                                  int64_t st, int32_t cap, int32_t pad,
                                                   int32_t *__restrict__ nbr,
                                                   int32_t *__restrict__ len,
                                                   int32_t *__restrict__ maxlen)
@@ -64,6 +64,8 @@ __global__ __launch_bounds__(256) void k_vl_build(const PosT *__restrict__ rec,
                 }
             }
         }
+        // pad to a multiple of 8 with the padding record (slot pad)
+        for (int32_t k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k) out[(int64_t)k * sk] = pad;
         len[t] = cnt;
     }
     // longest list of the wavefront, one atomic per wavefront
@@ -71,9 +73,13 @@ __global__ __launch_bounds__(256) void k_vl_build(const PosT *__restrict__ rec,
     if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0 && cnt > 0) atomicMax(maxlen, cnt);
 }
 
-// Cell-local lists for the staged kernel: entry = index of j in the
-// concatenation of the nine neighbour rows of i's cell (the order in which
-// the force kernel stages them into LDS), 16 bits, row-major per i.
+// Lists for the staged kernel: entry = index of j in the concatenation of
+// the nine neighbour rows of i's x-tile (STAGE_K consecutive cells along x
+// and one halo cell either side), the order in which the force kernel
+// stages them into LDS; 16 bits, row-major per i, padded to a multiple of 8
+// with the index one past the staged particles (a far-away padding entry).
+constexpr int STAGE_K = 4;
+
 __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__ rec,
                                                         const int32_t *__restrict__ start,
                                                         const int32_t *__restrict__ ilist,
@@ -90,9 +96,17 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
         const int32_t i = ilist[t];
         const PosT pi = rec[i];
         const int64_t e = cell_of[pi.orig];
+        // x-tile of i's cell
+        const int cx = (int)(e % g.stride[1]) - g.h[0];
+        const int cx0 = (cx / STAGE_K) * STAGE_K;
+        const int ncx = min(STAGE_K, g.n[0] - cx0);
+        const int64_t erow = e - (cx + g.h[0]);  // first cell of i's x-row
         uint16_t *out = nbr + t * cap;
         for (int r = 0; r < 9; ++r) {
             const int dy = r % 3 - 1, dz = r / 3 - 1;
+            const int64_t et = erow + dy * g.stride[1] + dz * g.stride[2] + cx0 - 1 + g.h[0];
+            const int32_t tb = start[et], te = start[et + ncx + 2];
+            // only i's own 3 cells of this row can hold partners
             const int64_t ej = e + dy * g.stride[1] + dz * g.stride[2] - 1;
             const int32_t jb = start[ej], je = start[ej + 3];
             for (int32_t j0 = jb; j0 < je; j0 += UNROLL) {
@@ -104,13 +118,14 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
                     const int32_t j = j0 + u;
                     const double dx = pi.x - pj[u].x, dyy = pi.y - pj[u].y, dzz = pi.z - pj[u].z;
                     if (j < je && j != i && dx * dx + dyy * dyy + dzz * dzz < rl2) {
-                        if (cnt < cap) out[cnt] = (uint16_t)(base + (j - jb));
+                        if (cnt < cap) out[cnt] = (uint16_t)(base + (j - tb));
                         ++cnt;
                     }
                 }
             }
-            base += je - jb;
+            base += te - tb;
         }
+        for (int32_t k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k) out[k] = (uint16_t)base;
         len[t] = cnt;
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -123,41 +138,49 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
     }
 }
 
-// Staged wave-per-i: one workgroup (one wavefront) per cell stages the
-// cell's 27-cell neighbourhood in LDS, then g i's at a time, 64/g lanes per
-// i, stride along the cell-local lists and read j from LDS.
-template <typename T, bool E, bool MS, int G>
-__global__ __launch_bounds__(64) void k_vl_lds(const PosT *__restrict__ rec,
-                                               const int32_t *__restrict__ start,
-                                               const int32_t *__restrict__ ibase, Grid g,
-                                               const uint16_t *__restrict__ nbr,
-                                               const int32_t *__restrict__ len, int32_t cap,
-                                               int cmax, LJTable<T> tab, ForceOut fo, int remap)
+// Staged wave-per-i: a workgroup of 4 wavefronts owns STAGE_K consecutive
+// cells along x and copies their common neighbourhood (nine rows of
+// STAGE_K + 2 cells) into LDS; its wavefronts then take g i's at a time,
+// 64/g lanes per i, each lane reading V list entries per trip (one 16-, 8-
+// or 4-byte load) and the j-particles from LDS.
+template <typename T, bool E, bool MS, int G, int V>
+__global__ __launch_bounds__(256) void k_vl_lds(const PosT *__restrict__ rec,
+                                                const int32_t *__restrict__ start,
+                                                const int32_t *__restrict__ ibase, Grid g,
+                                                int tiles_x, const uint16_t *__restrict__ nbr,
+                                                const int32_t *__restrict__ len, int32_t cap,
+                                                int cmax, LJTable<T> tab, ForceOut fo, int remap)
 {
     constexpr int SEG = MDLJ_WAVE / G;
+    constexpr int NW = 4;
     extern __shared__ double stage[];
     __shared__ int seg_b[9];
     __shared__ int seg_c[10];
     __shared__ LdsTable<T> lt;
+    __shared__ double red[2 * NW];
     const double rc2 = tab.rc2d;
-    const int lane = threadIdx.x;
-    if (MS) lds_table_load(lt, tab, lane, MDLJ_WAVE);
-    const int64_t c = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int cx = (int)(c % g.n[0]);
-    const int cy = (int)((c / g.n[0]) % g.n[1]);
-    const int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    const int tid = threadIdx.x;
+    const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
+    if (MS) lds_table_load(lt, tab, tid, blockDim.x);
+    const int64_t tile = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int tx = (int)(tile % tiles_x);
+    const int64_t rr = tile / tiles_x;
+    const int cy = (int)(rr % g.n[1]);
+    const int cz = (int)(rr / g.n[1]);
+    const int cx0 = tx * STAGE_K;
+    const int ncx = min(STAGE_K, g.n[0] - cx0);
     const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
-                       cx + g.h[0];
-    const int ib = start[ei], ie = start[ei + 1];
-    if (lane < 9) {
-        const int dy = lane % 3 - 1, dz = lane / 3 - 1;
+                       cx0 + g.h[0];
+    const int ib = start[ei], ie = start[ei + ncx];
+    if (tid < 9) {
+        const int dy = tid % 3 - 1, dz = tid / 3 - 1;
         const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
-                           (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx - 1 + g.h[0];
-        seg_b[lane] = start[ej];
-        seg_c[lane + 1] = start[ej + 3] - start[ej];
+                           (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx0 - 1 + g.h[0];
+        seg_b[tid] = start[ej];
+        seg_c[tid + 1] = start[ej + ncx + 2] - start[ej];
     }
     __syncthreads();
-    if (lane == 0) {
+    if (tid == 0) {
         seg_c[0] = 0;
         for (int r = 0; r < 9; ++r) seg_c[r + 1] += seg_c[r];
     }
@@ -165,12 +188,18 @@ __global__ __launch_bounds__(64) void k_vl_lds(const PosT *__restrict__ rec,
     const int C = seg_c[9];
     double *sx = stage, *sy = stage + cmax, *sz = stage + 2 * cmax;
     int *st = (int *)(stage + 3 * cmax);
-    stage_rows(rec, seg_b, seg_c, C, sx, sy, sz, st, MS, lane, MDLJ_WAVE);
+    stage_rows(rec, seg_b, seg_c, C, sx, sy, sz, st, MS, tid, blockDim.x);
+    if (tid == 0) {
+        sx[C] = sy[C] = sz[C] = PAD_COORD;
+        if (MS) st[C] = 0;
+    }
     __syncthreads();
-    const int64_t t0 = ibase[c];
+    // compact index of the tile's first particle (cells of a tile are consecutive)
+    const int64_t c0 = (int64_t)cx0 + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz);
+    const int64_t t0 = ibase[c0];
     const int l = lane % SEG;
     double bu = 0.0, bw = 0.0;
-    for (int i0 = ib; i0 < ie; i0 += G) {
+    for (int i0 = ib + wv * G; i0 < ie; i0 += NW * G) {
         const int i = i0 + lane / SEG;
         const bool act = i < ie;
         const PosT pi = rec[act ? i : ib];
@@ -179,17 +208,23 @@ __global__ __launch_bounds__(64) void k_vl_lds(const PosT *__restrict__ rec,
         const uint16_t *row = nbr + t * cap;
         Acc a;
         acc_zero(a);
-        for (int32_t k0 = l; k0 < L; k0 += UNROLL * SEG) {
-            int kk[UNROLL];
+        for (int32_t k0 = V * l; k0 < L; k0 += V * SEG) {
+            uint32_t w[4];
+            if (V == 8) {
+                const uint4 q = ((const uint4 *)row)[k0 >> 3];
+                w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+            } else if (V == 4) {
+                const uint2 q = ((const uint2 *)row)[k0 >> 2];
+                w[0] = q.x; w[1] = q.y;
+            } else {
+                w[0] = ((const uint32_t *)row)[k0 >> 1];
+            }
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) kk[u] = k0 + u * SEG < L ? (int)row[k0 + u * SEG] : -1;
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const int k = kk[u] >= 0 ? kk[u] : 0;
+            for (int u = 0; u < V; ++u) {
+                const int k = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
                 const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, MS ? st[k] : 0);
                 double fxp, fyp, fzp;
-                lj_pair<T, E>(pi.x, pi.y, pi.z, sx[k], sy[k], sz[k], kk[u] >= 0, p, rc2, a, fxp,
-                              fyp, fzp);
+                lj_pair<T, E>(pi.x, pi.y, pi.z, sx[k], sy[k], sz[k], true, p, rc2, a, fxp, fyp, fzp);
             }
         }
         a.fx = seg_sum(a.fx, SEG);
@@ -205,7 +240,24 @@ __global__ __launch_bounds__(64) void k_vl_lds(const PosT *__restrict__ rec,
             bw += a.w;
         }
     }
-    if (E) wave_partial(bu, bw, 0.5, fo.partial, blockIdx.x);
+    if (E) {
+        bu = seg_sum(bu, MDLJ_WAVE);
+        bw = seg_sum(bw, MDLJ_WAVE);
+        if (lane == 0) {
+            red[2 * wv] = bu;
+            red[2 * wv + 1] = bw;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double u = 0, w = 0;
+            for (int q = 0; q < NW; ++q) {
+                u += red[2 * q];
+                w += red[2 * q + 1];
+            }
+            fo.partial[2 * blockIdx.x] = 0.5 * u;
+            fo.partial[2 * blockIdx.x + 1] = 0.5 * w;
+        }
+    }
 }
 
 // i-per-lane over ELL lists.
@@ -273,8 +325,8 @@ __global__ __launch_bounds__(256) void k_vl_wpi(const PosT *__restrict__ rec,
                                                 const int32_t *__restrict__ ilist,
                                                 const int32_t *__restrict__ nbr,
                                                 const int32_t *__restrict__ len, int64_t n,
-                                                int32_t cap, LJTable<T> tab, ForceOut fo,
-                                                int remap)
+                                                int32_t cap, int64_t nrec, LJTable<T> tab,
+                                                ForceOut fo, int remap)
 {
     constexpr int SEG = MDLJ_WAVE / G;
     __shared__ LdsTable<T> lt;
@@ -295,21 +347,24 @@ __global__ __launch_bounds__(256) void k_vl_wpi(const PosT *__restrict__ rec,
         i = ilist[t];
         const PosT pi = rec[i];
         const int32_t L = len[t];
-        const int32_t *row = nbr + t * cap;
-        for (int32_t k0 = l; k0 < L; k0 += UNROLL * SEG) {
-            int32_t jj[UNROLL];
+        // lane l takes entries [4l, 4l+3] of each window of 4*SEG, read as one
+        // 16-byte load; rows are 16-byte aligned and padded to a multiple of
+        // 8 with the padding record, so every loaded index is valid
+        const int4 *row = (const int4 *)(nbr + t * cap);
+        const __amdgpu_buffer_rsrc_t rr = records_rsrc(rec, nrec);
+        for (int32_t k0 = 4 * l; k0 < L; k0 += 4 * SEG) {
+            const int4 q = row[k0 >> 2];
+            const int32_t jj[4] = {q.x, q.y, q.z, q.w};
+            double xj[4], yj[4], zj[4];
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) jj[u] = k0 + u * SEG < L ? row[k0 + u * SEG] : -1;
-            PosT pj[UNROLL];
+            for (int u = 0; u < 4; ++u) load_xyz(rr, jj[u], xj[u], yj[u], zj[u]);
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) pj[u] = rec[jj[u] >= 0 ? jj[u] : i];
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj[u].t);
+            for (int u = 0; u < 4; ++u) {
+                const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, MS ? rec[jj[u]].t : 0);
                 double fxp, fyp, fzp;
-                lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x, pj[u].y, pj[u].z, jj[u] >= 0, p, rc2, a,
-                              fxp, fyp, fzp);
-                if (N3 && jj[u] >= 0) {
+                lj_pair<T, E>(pi.x, pi.y, pi.z, xj[u], yj[u], zj[u], true, p, rc2, a, fxp, fyp,
+                              fzp);
+                if (N3) {
                     atomicAdd(&fo.fx[jj[u]], -fxp);
                     atomicAdd(&fo.fy[jj[u]], -fyp);
                     atomicAdd(&fo.fz[jj[u]], -fzp);
@@ -353,30 +408,42 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         return nb * (TB / MDLJ_WAVE);
     }
     const int32_t cap = (int32_t)ctx->nbr_cap;
+    const int64_t nrec = ctx->n_ext + 1;  // records + the padding record
     if (cfg.staged) {
         const Grid &g = ctx->grid;
-        const int cmax = ctx->max_nbhd;
+        const int cmax = ctx->max_nbhd + 1;  // + the padding entry
         const size_t lds = (size_t)cmax * (3 * sizeof(double) + (MS ? sizeof(int) : 0));
         if (lds > (size_t)STAGE_LDS_BYTES || N3) return -2;
-        const int64_t nbc = g.ncell_int;
+        const int tiles_x = (int)ceil_div(g.n[0], STAGE_K);
+        const int64_t nbt = (int64_t)tiles_x * g.n[1] * g.n[2];
         const int32_t *ibase = (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1;
         const uint16_t *nbr16 = (const uint16_t *)ctx->b_nbr.p;
         const int32_t *start = (const int32_t *)ctx->b_start.p;
-        switch (cfg.tile_i) {
-        case 2: k_vl_lds<T, E, MS, 2><<<nbc, 64, lds, s>>>(rec, start, ibase, g, nbr16, len, cap, cmax, tab, fo, remap); break;
-        case 4: k_vl_lds<T, E, MS, 4><<<nbc, 64, lds, s>>>(rec, start, ibase, g, nbr16, len, cap, cmax, tab, fo, remap); break;
-        case 8: k_vl_lds<T, E, MS, 8><<<nbc, 64, lds, s>>>(rec, start, ibase, g, nbr16, len, cap, cmax, tab, fo, remap); break;
+#define VL_LDS(GG, VV)                                                                        \
+    k_vl_lds<T, E, MS, GG, VV><<<nbt, 256, lds, s>>>(rec, start, ibase, g, tiles_x, nbr16, len, \
+                                                     cap, cmax, tab, fo, remap)
+        const int key = cfg.tile_i * 100 + cfg.tile_j;
+        switch (key) {
+        case 802: VL_LDS(8, 2); break;
+        case 804: VL_LDS(8, 4); break;
+        case 1602: VL_LDS(16, 2); break;
+        case 1604: VL_LDS(16, 4); break;
+        case 408: VL_LDS(4, 8); break;
         default: return -1;
         }
-        return nbc;
+#undef VL_LDS
+        return nbt;
     }
+    // 32-bit buffer offsets: records must stay under 2 GiB
+    if (nrec * (int64_t)sizeof(PosT) >= ((int64_t)1 << 31)) return -3;
     const int64_t waves = ceil_div(n, cfg.tile_i);
     const int64_t nb = ceil_div(waves, TB / MDLJ_WAVE);
     switch (cfg.tile_i) {
-    case 1: k_vl_wpi<T, E, MS, N3, 1><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, tab, fo, remap); break;
-    case 2: k_vl_wpi<T, E, MS, N3, 2><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, tab, fo, remap); break;
-    case 4: k_vl_wpi<T, E, MS, N3, 4><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, tab, fo, remap); break;
-    case 8: k_vl_wpi<T, E, MS, N3, 8><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, tab, fo, remap); break;
+    case 1: k_vl_wpi<T, E, MS, N3, 1><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, nrec, tab, fo, remap); break;
+    case 2: k_vl_wpi<T, E, MS, N3, 2><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, nrec, tab, fo, remap); break;
+    case 4: k_vl_wpi<T, E, MS, N3, 4><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, nrec, tab, fo, remap); break;
+    case 8: k_vl_wpi<T, E, MS, N3, 8><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, nrec, tab, fo, remap); break;
+    case 16: k_vl_wpi<T, E, MS, N3, 16><<<nb, TB, 0, s>>>(rec, ilist, nbr, len, n, cap, nrec, tab, fo, remap); break;
     default: return -1;
     }
     return nb * (TB / MDLJ_WAVE);
@@ -398,7 +465,7 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
     fill_table<T>(ctx, &tab);
     const bool ms = ctx->nspec > 1;
     const int remap = 1;
-    if (cfg.newton3) STCHK(zero_forces(ctx, fo, ctx->n_ext));
+    if (cfg.newton3) STCHK(zero_forces(ctx, fo, ctx->n_ext + 1));
     int64_t nw;
     if (energy) {
         const int64_t maxw = std::max<int64_t>(ctx->n + 64, ctx->grid.ncell_int);
@@ -411,6 +478,7 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
                 : launch_vl_n3<T, false, false>(ctx, cfg, tab, fo, remap);
     }
     if (nw == -2) return set_err(ctx, MDLJ_ERR_ARG, "neighbourhood too large for LDS staging");
+    if (nw == -3) return set_err(ctx, MDLJ_ERR_ARG, "too many records for 32-bit buffer offsets");
     if (nw < 0) return set_err(ctx, MDLJ_ERR_ARG, "unsupported Verlet-list shape");
     HIPCHK(ctx, hipGetLastError());
     *nblocks = nw;
@@ -429,7 +497,7 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
     const double est = (double)n / vol * 4.18879020478639 * rl * rl * rl * (cfg.newton3 ? 0.5 : 1.0);
     int64_t cap = (int64_t)(1.3 * est) + 16;
     if (ctx->nbr_cap > cap && ctx->built_cfg.newton3 == cfg.newton3) cap = ctx->nbr_cap;
-    cap = (cap + 3) & ~(int64_t)3;
+    cap = (cap + 7) & ~(int64_t)7;
     STCHK(ensure(ctx, ctx->b_nlen, sizeof(int32_t) * n));
     int32_t *maxlen = (int32_t *)ctx->b_flags.p + 12;
     int32_t *maxnb = (int32_t *)ctx->b_flags.p + 14;
@@ -452,8 +520,8 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
             k_vl_build<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
                 (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
                 (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, g, n, rl * rl,
-                cfg.newton3 ? 1 : 0, sk, st, (int32_t)cap, (int32_t *)ctx->b_nbr.p,
-                (int32_t *)ctx->b_nlen.p, maxlen);
+                cfg.newton3 ? 1 : 0, sk, st, (int32_t)cap, (int32_t)ctx->n_ext,
+                (int32_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen);
         }
         HIPCHK(ctx, hipGetLastError());
         int32_t hmax[3] = {0, 0, 0};
@@ -468,7 +536,7 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
             ctx->nbr_cap = cap;
             return MDLJ_OK;
         }
-        cap = ((int64_t)(hmax[0] * 1.1) + 8 + 3) & ~(int64_t)3;
+        cap = ((int64_t)(hmax[0] * 1.1) + 8 + 7) & ~(int64_t)7;
     }
     return set_err(ctx, MDLJ_ERR_OVERFLOW, "Verlet list capacity could not be grown");
 }

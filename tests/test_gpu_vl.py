@@ -22,8 +22,9 @@ def vl_configs(m):
     out = []
     for n3 in (0, 1):
         out.append((m.NBR_VL, m.ORD_I_PER_LANE, 0, 0, 0, n3))
-        out += [(m.NBR_VL, m.ORD_WAVE_PER_I, g, 64 // g, 0, n3) for g in (1, 2, 4, 8)]
-    out += [(m.NBR_VL, m.ORD_WAVE_PER_I, g, 64 // g, 0, 0, 1) for g in (2, 4, 8)]
+        out += [(m.NBR_VL, m.ORD_WAVE_PER_I, g, 64 // g, 0, n3) for g in (1, 2, 4, 8, 16)]
+    out += [(m.NBR_VL, m.ORD_WAVE_PER_I, g, v, 0, 0, 1) for g, v in ((8, 2), (8, 4), (16, 2),
+                                                                      (16, 4), (4, 8))]
     return out
 
 
@@ -70,7 +71,7 @@ def test_vl_refresh_and_early_rebuild(m, orc):
     with m.System(pos, box, rc, skin=0.3, rebuild_every=1000, precision=1) as sysm:
         for cfg in ((m.NBR_VL, m.ORD_I_PER_LANE, 0, 0, 0, 0),
                     (m.NBR_VL, m.ORD_WAVE_PER_I, 2, 32, 0, 1),
-                    (m.NBR_VL, m.ORD_WAVE_PER_I, 4, 16, 0, 0, 1)):
+                    (m.NBR_VL, m.ORD_WAVE_PER_I, 16, 4, 0, 0, 1)):
             sysm.set_config(cfg)
             sysm.set_positions(pos)
             sysm.set_timing(True)
@@ -95,7 +96,7 @@ def test_vl_refresh_and_early_rebuild(m, orc):
 
 
 @pytest.mark.parametrize("cfg", [(0, 0, 1, 1, 0, 0), (0, 2, 2, 32, 0, 0), (1, 0, 0, 0, 0, 0),
-                                 (1, 2, 1, 64, 0, 1), (1, 2, 8, 8, 0, 0, 1), (0, 1, 16, 4, 0, 0, 1)])
+                                 (1, 2, 1, 64, 0, 1), (1, 2, 8, 2, 0, 0, 1), (0, 1, 16, 4, 0, 0, 1)])
 def test_velocity_verlet_trajectory_matches_oracle(m, orc, cfg):
     import torch
     s = scenes.config1()
