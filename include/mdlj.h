@@ -87,14 +87,22 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2 };
  *                tile_j j's per step (LC: 16x4, 8x8; VCL: cluster_size x
  *                64/cluster_size).
  *   WAVE_PER_I   tile_i = g, the i-particles per wavefront (LC: 1, 2, 4;
- *                VL: 1, 2, 4, 8); each gets 64/g lanes.
+ *                VL: 1, 2, 4, 8, 16); each gets 64/g lanes.  tile_j = 64/g,
+ *                except for staged VL, where tile_j = v, the list entries
+ *                each lane reads per trip (2, 4 or 8: one 4-, 8- or 16-byte
+ *                load); staged VL takes (g, v) in {(8,2), (8,4), (16,2),
+ *                (16,4), (4,8)}.
  * cluster_size is 4 or 8 for VCL, 0 otherwise.  newton3 = 1 computes each
  * pair once and applies F_ji = -F_ij with atomics (section 4.1.3).
- * staged = 1 (LC cluster-tile / wave-per-i, VL wave-per-i, full lists): a
- * workgroup owns one cell and first copies the particles of its 27-cell
- * neighbourhood into LDS with coalesced loads; j-particles are then read
- * from LDS (the Verlet list holds 16-bit LDS-local indices).  staged = 0
- * reads every j-particle from global memory.
+ * staged = 1 (full lists only): the particles a workgroup's i's can reach
+ * are first copied into LDS with coalesced loads and j-particles are then
+ * read from LDS.  LC cluster-tile / wave-per-i: a workgroup owns one cell
+ * and stages its 27-cell neighbourhood.  VL wave-per-i: a workgroup owns 4
+ * consecutive cells along x and stages the 9 rows of 6 cells around them;
+ * the Verlet list then holds 16-bit indices into that staged set.  A scene
+ * whose neighbourhoods do not fit the 64 KB staging budget rejects staged
+ * configurations with MDLJ_ERR_ARG.  staged = 0 reads every j-particle
+ * from global memory.
  */
 typedef struct {
     int32_t nbr_algo;

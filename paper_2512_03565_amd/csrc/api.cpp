@@ -195,7 +195,10 @@ static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
         if (!make_grid(ctx->box, rmin, h, false, &g))
             return set_err(ctx, MDLJ_ERR_GEOMETRY, "grid set-up failed");
         STCHK(bin_particles(ctx, g));
-        if (c.nbr_algo == MDLJ_NBR_VL) STCHK(vl_build(ctx, c));
+        if (c.nbr_algo == MDLJ_NBR_VL) {
+            STCHK(vl_build(ctx, c));
+            STCHK(build_halo_list(ctx));
+        }
     }
     if (c.nbr_algo != MDLJ_NBR_LC) STCHK(save_reference(ctx));
     ctx->built = true;
@@ -232,12 +235,19 @@ mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed,
 {
     *rebuilt = false;
     *check_pending = false;
+    const bool fused = ctx->upkeep_fused;
+    ctx->upkeep_fused = false;
     bool need = !structure_current(ctx, c);
     if (!need && positions_changed) {
         if (c.nbr_algo == MDLJ_NBR_LC) {
             need = true;
         } else if (ctx->steps_since_build >= ctx->rebuild_every) {
             need = true;
+        } else if (fused && c.nbr_algo == MDLJ_NBR_VL) {
+            // the integrator moved the interior records and tested the
+            // displacements; only the halo images are left
+            STCHK(finish_fused_upkeep(ctx));
+            *check_pending = true;
         } else {
             // lists stay exact while every particle moved less than skin/2
             STCHK(launch_displacement_check(ctx));
@@ -479,7 +489,7 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
                       &ctx->b_cpair,   &ctx->b_cstart,  &ctx->b_fold,
                       &ctx->b_pos,     &ctx->b_type,    &ctx->b_force,
                       &ctx->b_cnt_ext, &ctx->b_img,     &ctx->b_icnt,    &ctx->b_ilist,
-                      &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat};
+                      &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo};
     for (DevBuf *b : bufs) free_buf(*b);
     delete ctx;
     return MDLJ_OK;
@@ -581,6 +591,7 @@ mdlj_status mdlj_set_positions(mdlj_ctx *ctx, const double *x, const double *y, 
     }
     ctx->forces_valid = false;
     ctx->pos_changed = true;
+    ctx->upkeep_fused = false;
     return MDLJ_OK;
 }
 

@@ -11,6 +11,7 @@
 // the extended cell counts -> scatter caller indices -> order each cell by
 // caller index (so results do not depend on atomic order) -> fill records
 // of interior and halo cells.
+#include "atomics.h"
 #include "internal.h"
 
 namespace {
@@ -79,21 +80,29 @@ __global__ void k_bin_count(int64_t n, double *__restrict__ x, double *__restric
     y[i] = p[1];
     z[i] = p[2];
     cell_of[i] = (int32_t)e;
-    const int32_t r = atomicAdd(&count[e], 1);
-    rank[i] = r;
-    // largest occupancy seen (one atomic per wavefront)
-    int32_t m = r + 1;
-    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
-    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0) atomicMax(&flags[2], m);
+    rank[i] = atomicAdd(&count[e], 1);
 }
 
 // Extended-cell counts: a halo cell holds as many records as its source.
-__global__ void k_ext_counts(Grid g, const int32_t *__restrict__ count,
-                             int32_t *__restrict__ cnt_ext)
+// Also the largest occupancy, into flags[2] (one atomic per workgroup).
+__global__ __launch_bounds__(256) void k_ext_counts(Grid g, const int32_t *__restrict__ count,
+                                                    int32_t *__restrict__ cnt_ext,
+                                                    int32_t *__restrict__ flags)
 {
+    __shared__ int32_t red[256 / MDLJ_WAVE];
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g.ncell_ext) return;
-    cnt_ext[e] = count[source_cell(e, g)];
+    int32_t m = 0;
+    if (e < g.ncell_ext) {
+        m = count[source_cell(e, g)];
+        cnt_ext[e] = m;
+    }
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0) red[threadIdx.x / MDLJ_WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)blockDim.x / MDLJ_WAVE; ++w) m = max(m, red[w]);
+        if (m > 0) atomic_max_rare(&flags[2], m);
+    }
 }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(int64_t n,
@@ -193,38 +202,15 @@ __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
     sorted_orig[start[e] + rank[i]] = (int32_t)i;
 }
 
-__device__ __forceinline__ bool is_interior(int64_t e, const Grid &g)
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        int c = (int)((e / g.stride[a]) % g.e[a]) - g.h[a];
-        if (c < 0 || c >= g.n[a]) return false;
-    }
-    return true;
-}
-
-// Order every interior cell by caller index (insertion sort; cells are small).
-__global__ void k_order_cells(Grid g, const int32_t *__restrict__ start,
-                              int32_t *__restrict__ sorted_orig)
-{
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g.ncell_ext || !is_interior(e, g)) return;
-    int32_t b = start[e], en = start[e + 1];
-    for (int32_t k = b + 1; k < en; ++k) {
-        int32_t v = sorted_orig[k];
-        int32_t m = k - 1;
-        while (m >= b && sorted_orig[m] > v) {
-            sorted_orig[m + 1] = sorted_orig[m];
-            --m;
-        }
-        sorted_orig[m + 1] = v;
-    }
-}
-
 // One wavefront per extended cell: interior cells gather their records,
-// halo cells copy the records of their source cell shifted by +-L.
+// halo cells copy the records of their source cell shifted by +-L.  Within
+// a cell records are ordered by caller index (so the layout does not depend
+// on the order in which the counting atomics were served): element m of the
+// source cell's unordered list goes to slot b + (number of elements with a
+// smaller caller index).  Halo cells rank their source's list the same way,
+// so every image has the order of its source.
 __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict__ start,
-                                              int32_t *__restrict__ sorted_orig,
+                                              const int32_t *__restrict__ unordered,
                                               const double *__restrict__ x,
                                               const double *__restrict__ y,
                                               const double *__restrict__ z,
@@ -236,7 +222,7 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
     int64_t e = (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
     int lane = threadIdx.x & (MDLJ_WAVE - 1);
     if (e >= g.ncell_ext) return;
-    int32_t b = start[e], en = start[e + 1];
+    const int32_t b = start[e], cnt = start[e + 1] - b;
     double sh[3];
     signed char code[3];
     int64_t src = 0;
@@ -251,19 +237,28 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
         if (c >= g.n[a]) { s = c - g.n[a]; sh[a] = g.L[a]; code[a] = 1; interior = false; }
         src += (int64_t)(s + g.h[a]) * g.stride[a];
     }
-    int32_t sb = start[src];
-    for (int32_t k = b + lane; k < en; k += MDLJ_WAVE) {
-        int32_t i = interior ? sorted_orig[k] : sorted_orig[sb + (k - b)];
-        PosT r;
-        r.x = x[i] + sh[0];
-        r.y = y[i] + sh[1];
-        r.z = z[i] + sh[2];
-        r.t = type[i];
-        r.orig = i;
-        rec[k] = r;
-        img[k] = make_char4(code[0], code[1], code[2], 0);
-        if (interior) slot_of[i] = k;
-        else sorted_orig[k] = i;
+    const int32_t sb = start[src];
+    for (int32_t m0 = 0; m0 < cnt; m0 += MDLJ_WAVE) {
+        const int32_t m = m0 + lane;
+        const int32_t i = m < cnt ? unordered[sb + m] : INT32_MAX;
+        int32_t rank = 0;
+        for (int32_t q0 = 0; q0 < cnt; q0 += MDLJ_WAVE) {
+            const int32_t v = q0 + lane < cnt ? unordered[sb + q0 + lane] : INT32_MAX;
+            const int32_t nq = min(cnt - q0, MDLJ_WAVE);
+            for (int32_t q = 0; q < nq; ++q) rank += __builtin_amdgcn_readlane(v, q) < i;
+        }
+        if (m < cnt) {
+            const int32_t k = b + rank;
+            PosT r;
+            r.x = x[i] + sh[0];
+            r.y = y[i] + sh[1];
+            r.z = z[i] + sh[2];
+            r.t = type[i];
+            r.orig = i;
+            rec[k] = r;
+            img[k] = make_char4(code[0], code[1], code[2], 0);
+            if (interior) slot_of[i] = k;
+        }
     }
 }
 
@@ -481,7 +476,8 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     k_bin_count<<<ceil_div(n, TB), TB, 0, s>>>(n, ctx->x, ctx->y, ctx->z, g,
                                                  (int32_t *)ctx->b_cell_of.p,
                                                  (int32_t *)ctx->b_rank.p, count, flags);
-    k_ext_counts<<<ceil_div(g.ncell_ext, TB), TB, 0, s>>>(g, count, (int32_t *)ctx->b_cnt_ext.p);
+    k_ext_counts<<<ceil_div(g.ncell_ext, TB), TB, 0, s>>>(g, count, (int32_t *)ctx->b_cnt_ext.p,
+                                                  flags);
     HIPCHK(ctx, hipGetLastError());
     STCHK(exclusive_scan(ctx, (const int32_t *)ctx->b_cnt_ext.p, start, g.ncell_ext));
     HIPCHK(ctx, hipGetLastError());
@@ -498,12 +494,11 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     STCHK(ensure(ctx, ctx->b_sorted, sizeof(PosT) * (n_ext + 1)));
     STCHK(ensure(ctx, ctx->b_misc, sizeof(int32_t) * n_ext));
     STCHK(ensure(ctx, ctx->b_img, sizeof(char4) * n_ext));
-    int32_t *sorted_orig = (int32_t *)ctx->b_misc.p;
+    int32_t *unordered = (int32_t *)ctx->b_misc.p;
     k_scatter<<<ceil_div(n, TB), TB, 0, s>>>(n, (int32_t *)ctx->b_cell_of.p,
-                                              (int32_t *)ctx->b_rank.p, start, sorted_orig);
-    k_order_cells<<<ceil_div(g.ncell_ext, TB), TB, 0, s>>>(g, start, sorted_orig);
+                                              (int32_t *)ctx->b_rank.p, start, unordered);
     k_fill<<<ceil_div(g.ncell_ext, TB / MDLJ_WAVE), TB, 0, s>>>(
-        g, start, sorted_orig, ctx->x, ctx->y, ctx->z, ctx->type, (PosT *)ctx->b_sorted.p,
+        g, start, unordered, ctx->x, ctx->y, ctx->z, ctx->type, (PosT *)ctx->b_sorted.p,
         (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p);
     k_pad_record<<<1, 64, 0, s>>>((PosT *)ctx->b_sorted.p, n_ext);
     HIPCHK(ctx, hipGetLastError());

@@ -7,6 +7,10 @@
 // sorted records keep their slots; only their coordinates are refreshed
 // from the caller-order positions, halo images with the same +-L shift as
 // at build time.  Positions are left unwrapped until the next rebuild.
+#include <string.h>
+
+#include <vector>
+
 #include "internal.h"
 
 namespace {
@@ -95,6 +99,64 @@ __global__ void k_kick_drift_sorted(int64_t n, double *__restrict__ x, double *_
     z[i] += dt * uz;
 }
 
+// The same step for Verlet lists between rebuilds, with the list upkeep of
+// the next force call folded in: the new position also goes to the
+// particle's sorted record, and a particle that has now moved more than
+// sqrt(thr2) since the list build sets *flag.
+__global__ void k_kick_drift_fused(int64_t n, double *__restrict__ x, double *__restrict__ y,
+                                   double *__restrict__ z, double *__restrict__ vx,
+                                   double *__restrict__ vy, double *__restrict__ vz,
+                                   const double *__restrict__ fx, const double *__restrict__ fy,
+                                   const double *__restrict__ fz,
+                                   const int32_t *__restrict__ slot_of,
+                                   const int32_t *__restrict__ type, InvMass im, double dt,
+                                   PosT *__restrict__ rec, const double *__restrict__ xr,
+                                   double thr2, int32_t *__restrict__ flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t s = slot_of[i];
+    const double h = 0.5 * dt * im.v[type[i]];
+    const double ux = (vx[i] + h * fx[s]) + h * fx[s];
+    const double uy = (vy[i] + h * fy[s]) + h * fy[s];
+    const double uz = (vz[i] + h * fz[s]) + h * fz[s];
+    vx[i] = ux;
+    vy[i] = uy;
+    vz[i] = uz;
+    const double px = x[i] + dt * ux, py = y[i] + dt * uy, pz = z[i] + dt * uz;
+    x[i] = px;
+    y[i] = py;
+    z[i] = pz;
+    rec[s].x = px;
+    rec[s].y = py;
+    rec[s].z = pz;
+    const double dx = px - xr[i], dy = py - xr[n + i], dz = pz - xr[2 * n + i];
+    if (!(dx * dx + dy * dy + dz * dz <= thr2)) atomicOr(flag, 1);
+}
+
+// Halo records from their source records, one wavefront per halo cell:
+// rec = source + image * L (the same sum the full refresh forms from the
+// caller-order positions).  hl holds (halo cell, source cell) pairs.
+__global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__restrict__ hl,
+                                                      const int32_t *__restrict__ start,
+                                                      const char4 *__restrict__ img,
+                                                      PosT *__restrict__ rec, double lx, double ly,
+                                                      double lz)
+{
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
+    const int lane = threadIdx.x & (MDLJ_WAVE - 1);
+    if (w >= nh) return;
+    const int2 p = hl[w];
+    const int32_t b = start[p.x], cnt = start[p.x + 1] - b, sb = start[p.y];
+    for (int32_t m = lane; m < cnt; m += MDLJ_WAVE) {
+        const char4 c = img[b + m];
+        const PosT q = rec[sb + m];
+        rec[b + m].x = q.x + (double)c.x * lx;
+        rec[b + m].y = q.y + (double)c.y * ly;
+        rec[b + m].z = q.z + (double)c.z * lz;
+    }
+}
+
 // v += F dt / (2m) from sorted forces; also writes the caller-order forces
 __global__ void k_kick_sorted(int64_t n, double *__restrict__ vx, double *__restrict__ vy,
                               double *__restrict__ vz, const double *__restrict__ fx,
@@ -176,6 +238,55 @@ mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far)
     return check_result(ctx, too_far);
 }
 
+mdlj_status finish_fused_upkeep(mdlj_ctx *ctx)
+{
+    int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_flag, flag, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->ev_flag, ctx->stream));
+    if (ctx->nhalo > 0) {
+        k_refresh_halo<<<ceil_div(ctx->nhalo, 4), 256, 0, ctx->stream>>>(
+            ctx->nhalo, (const int2 *)ctx->b_halo.p, (const int32_t *)ctx->b_start.p,
+            (const char4 *)ctx->b_img.p, (PosT *)ctx->b_sorted.p, ctx->box[0], ctx->box[1],
+            ctx->box[2]);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    return MDLJ_OK;
+}
+
+mdlj_status build_halo_list(mdlj_ctx *ctx)
+{
+    const Grid &g = ctx->grid;
+    const int key[6] = {g.n[0], g.n[1], g.n[2], g.h[0], g.h[1], g.h[2]};
+    if (ctx->b_halo.p && memcmp(key, ctx->halo_key, sizeof key) == 0) return MDLJ_OK;
+    std::vector<int2> hl;
+    hl.reserve((size_t)(g.ncell_ext - g.ncell_int));
+    for (int cz = -g.h[2]; cz < g.n[2] + g.h[2]; ++cz)
+        for (int cy = -g.h[1]; cy < g.n[1] + g.h[1]; ++cy)
+            for (int cx = -g.h[0]; cx < g.n[0] + g.h[0]; ++cx) {
+                const int c[3] = {cx, cy, cz};
+                bool halo = false;
+                int64_t e = 0, src = 0;
+                for (int a = 0; a < 3; ++a) {
+                    int s = c[a];
+                    if (s < 0) { s += g.n[a]; halo = true; }
+                    if (s >= g.n[a]) { s -= g.n[a]; halo = true; }
+                    e += (int64_t)(c[a] + g.h[a]) * g.stride[a];
+                    src += (int64_t)(s + g.h[a]) * g.stride[a];
+                }
+                if (halo) hl.push_back(make_int2((int)e, (int)src));
+            }
+    ctx->nhalo = (int64_t)hl.size();
+    memcpy(ctx->halo_key, key, sizeof key);
+    if (hl.empty()) return MDLJ_OK;
+    STCHK(ensure(ctx, ctx->b_halo, sizeof(int2) * hl.size()));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->b_halo.p, hl.data(), sizeof(int2) * hl.size(),
+                               hipMemcpyHostToDevice, ctx->stream));
+    // the host vector is released on return
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MDLJ_OK;
+}
+
 mdlj_status refresh_records(mdlj_ctx *ctx)
 {
     k_refresh<<<ceil_div(ctx->n_ext, 256), 256, 0, ctx->stream>>>(
@@ -210,7 +321,22 @@ mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double d
         ForceOut fo;
         STCHK(forces_internal(ctx, true, nullptr, &fo, false));
         const int32_t *slot_of = (const int32_t *)ctx->b_slot_of.p;
-        if (s + 1 < nsteps) {
+        // lists kept for the next step (and a context with the fused
+        // upkeep state): positions, sorted records and the displacement test
+        // in one pass
+        const bool fuse = ctx->built && ctx->built_cfg.nbr_algo == MDLJ_NBR_VL &&
+                          ctx->cfg.nbr_algo == MDLJ_NBR_VL &&
+                          ctx->steps_since_build < ctx->rebuild_every && ctx->h_flag &&
+                          ctx->b_xref.bytes >= sizeof(double) * 3 * n;
+        if (s + 1 < nsteps && fuse) {
+            int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
+            const double h = 0.5 * ctx->skin;
+            HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+            k_kick_drift_fused<<<nb, TB, 0, ctx->stream>>>(
+                n, ctx->x, ctx->y, ctx->z, vx, vy, vz, fo.fx, fo.fy, fo.fz, slot_of, ctx->type, im,
+                dt, (PosT *)ctx->b_sorted.p, (const double *)ctx->b_xref.p, h * h, flag);
+            ctx->upkeep_fused = true;
+        } else if (s + 1 < nsteps) {
             k_kick_drift_sorted<<<nb, TB, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z, vx, vy, vz,
                                                             fo.fx, fo.fy, fo.fz, slot_of,
                                                             ctx->type, im, dt);

@@ -87,6 +87,9 @@ struct mdlj_ctx {
     double *fx = nullptr, *fy = nullptr, *fz = nullptr;  // last forces, caller order
     bool forces_valid = false;
     bool pos_changed = true;      // positions changed since the last force call
+    // the integrator already wrote the interior sorted records and the skin/2
+    // displacement flag for the current positions (Verlet lists only)
+    bool upkeep_fused = false;
 
     // neighbour structure state
     bool built = false;           // structure matches cfg/positions
@@ -106,7 +109,9 @@ struct mdlj_ctx {
     DevBuf b_pos, b_type, b_force;  // caller-order state above
     DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
-        b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat;
+        b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo;
+    int64_t nhalo = 0;            // entries of b_halo
+    int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 
     // tuner state
     std::vector<mdlj_config> space;
@@ -187,6 +192,11 @@ mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far);
 mdlj_status launch_displacement_check(mdlj_ctx *ctx);
 mdlj_status check_result(mdlj_ctx *ctx, bool *too_far);
 mdlj_status refresh_records(mdlj_ctx *ctx);
+// After a fused integrator step: copy the displacement flag to the host
+// (behind ctx->ev_flag) and refresh the halo records from their sources.
+mdlj_status finish_fused_upkeep(mdlj_ctx *ctx);
+// (halo cell, source cell) pairs of the current grid, for the halo refresh.
+mdlj_status build_halo_list(mdlj_ctx *ctx);
 mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt, int nsteps);
 
 // --- force evaluation (api.cpp) ---------------------------------------------

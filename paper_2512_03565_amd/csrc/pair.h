@@ -10,6 +10,7 @@
 // itself (reciprocal, powers, force factor, energy) runs in T.
 #pragma once
 
+#include "atomics.h"
 #include "internal.h"
 
 template <typename T>
@@ -85,9 +86,9 @@ __device__ __forceinline__ PairP<T> pair_params(const LJTable<T> &t, const LdsTa
 // in T.  The force factor is widened once and the force accumulated as
 // F += fs * d with FP64 fused multiply-adds, which on this hardware issue
 // at the FP32 rate.  Returns the force on i in (fxp, fyp, fzp) (zero when
-// masked or outside the cutoff).
+// masked or outside the cutoff) and whether the pair is inside the cutoff.
 template <typename T, bool E>
-__device__ __forceinline__ void lj_pair(double pxi, double pyi, double pzi, double pxj,
+__device__ __forceinline__ bool lj_pair(double pxi, double pyi, double pzi, double pxj,
                                         double pyj, double pzj, bool valid, const PairP<T> &p,
                                         double rc2, Acc &a, double &fxp, double &fyp, double &fzp)
 {
@@ -114,6 +115,7 @@ __device__ __forceinline__ void lj_pair(double pxi, double pyi, double pzi, doub
         a.u += in ? (double)u : 0.0;
         a.w += in ? (double)rf : 0.0;
     }
+    return in;
 }
 
 // Sum of v over the `width` consecutive lanes of a segment (width a power

@@ -194,7 +194,7 @@ __global__ void k_pair_search(ClusterGeom cg, const double *__restrict__ bb,
         }
     }
     len[I] = cnt;
-    atomicMax(maxlen, cnt);
+    atomic_max_rare(maxlen, cnt);
 }
 
 __device__ __forceinline__ void decode(int32_t e, const double *L, int32_t &J, double &sx,
@@ -277,7 +277,8 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
                     gy += __shfl_xor(gy, o, MDLJ_WAVE);
                     gz += __shfl_xor(gz, o, MDLJ_WAVE);
                 }
-                if (a == 0 && ok[u]) {
+                // skip j's that no i-lane reaches inside the cutoff (and dummies)
+                if (a == 0 && ok[u] && (gx != 0.0 || gy != 0.0 || gz != 0.0)) {
                     atomicAdd(&fo.fx[jslot], gx);
                     atomicAdd(&fo.fy[jslot], gy);
                     atomicAdd(&fo.fz[jslot], gz);
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(256) void k_vcl_ipl(const PosT *__restrict__ crec,
                     gy += __shfl_xor(gy, o, M);
                     gz += __shfl_xor(gz, o, M);
                 }
-                if (a == 0) {
+                if (a == 0 && (gx != 0.0 || gy != 0.0 || gz != 0.0)) {
                     atomicAdd(&fo.fx[jslot], gx);
                     atomicAdd(&fo.fy[jslot], gy);
                     atomicAdd(&fo.fz[jslot], gz);

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_vl_build(const PosT *__restrict__ rec,
     }
     // longest list of the wavefront, one atomic per wavefront
     for (int o = 32; o > 0; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o));
-    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0 && cnt > 0) atomicMax(maxlen, cnt);
+    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0 && cnt > 0) atomic_max_rare(maxlen, cnt);
 }
 
 // Lists for the staged kernel: entry = index of j in the concatenation of
@@ -133,8 +133,187 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
         base = max(base, __shfl_xor(base, o));
     }
     if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0) {
-        if (cnt > 0) atomicMax(maxlen, cnt);
-        if (base > 0) atomicMax(maxnb, base);
+        if (cnt > 0) atomic_max_rare(maxlen, cnt);
+        if (base > 0) atomic_max_rare(maxnb, base);
+    }
+}
+
+// Tiled build: one workgroup per x-tile (the tiles of the staged force
+// kernel) copies the tile's neighbourhood into LDS and lists, for each cell
+// of the tile, the staged indices of its 27 cells (nine runs of three
+// cells).  A wavefront then takes one i at a time: its 64 lanes test 64
+// candidates per trip and the hits are packed in candidate order with a
+// ballot and a lane prefix count, so each list row is written as one
+// contiguous run.  The lists equal those of the per-particle builds above
+// entry for entry.
+// LOCAL: 16-bit staged indices, rows padded with C (the staged count);
+// otherwise sorted-record slots at nbr[t * st + k * sk], padded with `pad`.
+// HALF keeps partners with a larger caller index only.
+// A tile whose neighbourhood exceeds cmax records its size in maxnb and
+// builds nothing; the host then falls back to the per-particle build.
+constexpr int BUILD_TB = 512;
+// slack after the candidate lists: a trip of 2 x 64 lanes may read past the
+// last list, into entries set to index 0
+constexpr int CAND_SLACK = 2 * MDLJ_WAVE;
+
+template <bool LOCAL, bool HALF, bool ELL>
+__global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
+    const PosT *__restrict__ rec, const int32_t *__restrict__ start,
+    const int32_t *__restrict__ ibase, Grid g, int tiles_x, double rl2, int cmax, int ccand,
+    int64_t n, int32_t cap, int32_t pad, void *__restrict__ nbr_out, int32_t *__restrict__ len,
+    int32_t *__restrict__ maxlen, int32_t *__restrict__ maxnb, int remap)
+{
+    constexpr int NW = BUILD_TB / MDLJ_WAVE;
+    constexpr int RC = STAGE_K + 3;  // cell starts per row: STAGE_K + 2 cells and the end
+    // staged record: x, y, z (and for slot lists the slot and caller index);
+    // strides of 6 and 10 dwords keep 64-bit LDS reads of consecutive
+    // records free of bank conflicts
+    constexpr int RW = LOCAL ? 3 : 5;  // record size in doubles
+    extern __shared__ double stage[];
+    __shared__ int rs[9][RC];        // start[] of the cells of each row
+    __shared__ int seg_c[10];        // staged offset of each row
+    __shared__ int nc[STAGE_K + 1];  // offsets of the tile cells' candidate lists
+    __shared__ int wmx[NW];
+    const int tid = threadIdx.x;
+    const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
+    const int64_t tile = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int tx = (int)(tile % tiles_x);
+    const int64_t rr = tile / tiles_x;
+    const int cy = (int)(rr % g.n[1]);
+    const int cz = (int)(rr / g.n[1]);
+    const int cx0 = tx * STAGE_K;
+    const int ncx = min(STAGE_K, g.n[0] - cx0);
+    // all cell starts of the nine rows in one round of loads
+    if (tid < 9 * (ncx + 3)) {
+        const int r = tid / (ncx + 3), c = tid % (ncx + 3);
+        const int dy = r % 3 - 1, dz = r / 3 - 1;
+        const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
+                           (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx0 - 1 + g.h[0];
+        rs[r][c] = start[ej + c];
+    }
+    const int64_t c0 = (int64_t)cx0 + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz);
+    const int64_t t0 = ibase[c0];
+    __syncthreads();
+    if (wv == 0) {
+        // lanes 0..8: row lengths; lanes 16..16+ncx-1: candidates of tile cell c
+        int v = 0;
+        if (lane < 9) v = rs[lane][ncx + 2] - rs[lane][0];
+        const int c = lane - 16;
+        if (c >= 0 && c < ncx)
+            for (int r = 0; r < 9; ++r) v += rs[r][c + 3] - rs[r][c];
+        // inclusive scans over lanes 0..15 and 16..31
+        for (int o = 1; o < 16; o <<= 1) {
+            const int u = __shfl_up(v, o, 16);
+            if ((lane & 15) >= o) v += u;
+        }
+        if (lane < 9) seg_c[lane + 1] = v;
+        if (lane == 0) seg_c[0] = 0;
+        if (c >= 0 && c < ncx) nc[c + 1] = v;
+        if (lane == 16) nc[0] = 0;
+    }
+    __syncthreads();
+    const int C = seg_c[9];
+    if (C > cmax || nc[ncx] > ccand) {  // block-uniform
+        if (tid == 0) atomicMax(maxnb, max(C, cmax + 1));
+        return;
+    }
+    double *srec = stage;
+    uint16_t *cand = (uint16_t *)(stage + (size_t)RW * cmax);
+    {
+        int r = 0;
+        for (int k = tid; k < C; k += BUILD_TB) {
+            while (k >= seg_c[r + 1]) ++r;
+            const int32_t slot = rs[r][0] + (k - seg_c[r]);
+            const PosT p = rec[slot];
+            double *d = srec + RW * k;
+            d[0] = p.x;
+            d[1] = p.y;
+            d[2] = p.z;
+            if (!LOCAL) {
+                int32_t *e = (int32_t *)(d + 3);
+                e[0] = slot;
+                e[1] = p.orig;
+            }
+        }
+    }
+    // candidate runs: tile cell c, row r -> row cells c .. c + 2
+    for (int q = wv; q < 9 * ncx; q += NW) {
+        const int c = q / 9, r = q % 9;
+        int off = nc[c];
+        for (int r2 = 0; r2 < r; ++r2) off += rs[r2][c + 3] - rs[r2][c];
+        const int b = seg_c[r] + rs[r][c] - rs[r][0], m = rs[r][c + 3] - rs[r][c];
+        for (int u = lane; u < m; u += MDLJ_WAVE) cand[off + u] = (uint16_t)(b + u);
+    }
+    if (tid < CAND_SLACK) cand[nc[ncx] + tid] = 0;
+    __syncthreads();
+    const int ib = rs[4][1], ie = rs[4][ncx + 1];
+    int32_t wmax = 0;
+    for (int i = ib + wv; i < ie; i += NW) {
+        const int own = seg_c[4] + (i - rs[4][0]);
+        int c = 0;
+        while (c + 1 < ncx && i >= rs[4][c + 2]) ++c;
+        const double *di = srec + RW * own;
+        const double xi = di[0], yi = di[1], zi = di[2];
+        const int32_t oi = HALF ? ((const int32_t *)(di + 3))[1] : 0;
+        const int pb = nc[c], pe = nc[c + 1];
+        const int64_t t = t0 + (i - ib);
+        uint16_t *row16 = (uint16_t *)nbr_out + t * cap;
+        int32_t *row32 = (int32_t *)nbr_out + (ELL ? t : t * cap);
+        uint32_t cnt = 0;
+        // two trips of 64 candidates in flight; every lane reads a valid
+        // index (slack entries are 0), lanes past the list are masked
+        for (int p0 = pb; p0 < pe; p0 += 2 * MDLJ_WAVE) {
+            const int rem = pe - p0;
+            const int ka = cand[p0 + lane];
+            const int kb = cand[p0 + MDLJ_WAVE + lane];
+            const double *da = srec + RW * ka;
+            const double *db = srec + RW * kb;
+            const double ax = xi - da[0], ay = yi - da[1], az = zi - da[2];
+            const double bx = xi - db[0], by = yi - db[1], bz = zi - db[2];
+            bool ha = (lane < rem) & (ka != own) & (ax * ax + ay * ay + az * az < rl2);
+            bool hb = (lane + MDLJ_WAVE < rem) & (kb != own) & (bx * bx + by * by + bz * bz < rl2);
+            if (HALF) {
+                ha &= ((const int32_t *)(da + 3))[1] > oi;
+                hb &= ((const int32_t *)(db + 3))[1] > oi;
+            }
+            const uint64_t ma = __builtin_amdgcn_ballot_w64(ha);
+            const uint64_t mb = __builtin_amdgcn_ballot_w64(hb);
+            const uint32_t na = (uint32_t)__builtin_popcountll(ma);
+            const uint32_t qa = __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)ma, cnt));
+            const uint32_t qb = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, cnt + na));
+            // row-major rows have slack after the last row, so an overlong row
+            // only spills into its neighbours (the host then rebuilds with a
+            // larger capacity); column-major rows must stop at cap
+            if (LOCAL) {
+                if (ha) row16[qa] = (uint16_t)ka;
+                if (hb) row16[qb] = (uint16_t)kb;
+            } else if (!ELL) {
+                if (ha) row32[qa] = ((const int32_t *)(da + 3))[0];
+                if (hb) row32[qb] = ((const int32_t *)(db + 3))[0];
+            } else {
+                if (ha && qa < (uint32_t)cap) row32[(int64_t)qa * n] = ((const int32_t *)(da + 3))[0];
+                if (hb && qb < (uint32_t)cap) row32[(int64_t)qb * n] = ((const int32_t *)(db + 3))[0];
+            }
+            cnt += na + (uint32_t)__builtin_popcountll(mb);
+        }
+        const int32_t pe8 = min((int32_t)((cnt + 7) & ~7u), cap);
+        for (int32_t q = (int32_t)cnt + lane; q < pe8; q += MDLJ_WAVE) {
+            if (LOCAL)
+                row16[q] = (uint16_t)C;
+            else
+                row32[ELL ? (int64_t)q * n : q] = pad;
+        }
+        if (lane == 0) len[t] = (int32_t)cnt;
+        wmax = max(wmax, (int32_t)cnt);
+    }
+    if (lane == 0) wmx[wv] = wmax;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < NW; ++w) wmax = max(wmax, wmx[w]);
+        if (wmax > 0) atomic_max_rare(maxlen, wmax);
+        atomic_max_rare(maxnb, C);
     }
 }
 
@@ -143,8 +322,10 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
 // STAGE_K + 2 cells) into LDS; its wavefronts then take g i's at a time,
 // 64/g lanes per i, each lane reading V list entries per trip (one 16-, 8-
 // or 4-byte load) and the j-particles from LDS.
+constexpr int VL_LDS_TB = 256;
+
 template <typename T, bool E, bool MS, int G, int V>
-__global__ __launch_bounds__(256) void k_vl_lds(const PosT *__restrict__ rec,
+__global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ rec,
                                                 const int32_t *__restrict__ start,
                                                 const int32_t *__restrict__ ibase, Grid g,
                                                 int tiles_x, const uint16_t *__restrict__ nbr,
@@ -152,7 +333,7 @@ __global__ __launch_bounds__(256) void k_vl_lds(const PosT *__restrict__ rec,
                                                 int cmax, LJTable<T> tab, ForceOut fo, int remap)
 {
     constexpr int SEG = MDLJ_WAVE / G;
-    constexpr int NW = 4;
+    constexpr int NW = VL_LDS_TB / MDLJ_WAVE;
     extern __shared__ double stage[];
     __shared__ int seg_b[9];
     __shared__ int seg_c[10];
@@ -295,9 +476,10 @@ __global__ __launch_bounds__(256) void k_vl_ipl(const PosT *__restrict__ rec,
             for (int u = 0; u < UNROLL; ++u) {
                 const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj[u].t);
                 double fxp, fyp, fzp;
-                lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x, pj[u].y, pj[u].z, jj[u] >= 0, p, rc2, a,
-                              fxp, fyp, fzp);
-                if (N3 && jj[u] >= 0) {
+                const bool in = lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x, pj[u].y, pj[u].z,
+                                              jj[u] >= 0, p, rc2, a, fxp, fyp, fzp);
+                // pairs in the skin (and list padding) add nothing to j
+                if (N3 && in) {
                     atomicAdd(&fo.fx[jj[u]], -fxp);
                     atomicAdd(&fo.fy[jj[u]], -fyp);
                     atomicAdd(&fo.fz[jj[u]], -fzp);
@@ -362,9 +544,10 @@ __global__ __launch_bounds__(256) void k_vl_wpi(const PosT *__restrict__ rec,
             for (int u = 0; u < 4; ++u) {
                 const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, MS ? rec[jj[u]].t : 0);
                 double fxp, fyp, fzp;
-                lj_pair<T, E>(pi.x, pi.y, pi.z, xj[u], yj[u], zj[u], true, p, rc2, a, fxp, fyp,
-                              fzp);
-                if (N3) {
+                const bool in = lj_pair<T, E>(pi.x, pi.y, pi.z, xj[u], yj[u], zj[u], true, p, rc2,
+                                              a, fxp, fyp, fzp);
+                // pairs in the skin and the padding entries add nothing to j
+                if (N3 && in) {
                     atomicAdd(&fo.fx[jj[u]], -fxp);
                     atomicAdd(&fo.fy[jj[u]], -fyp);
                     atomicAdd(&fo.fz[jj[u]], -fzp);
@@ -420,7 +603,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         const uint16_t *nbr16 = (const uint16_t *)ctx->b_nbr.p;
         const int32_t *start = (const int32_t *)ctx->b_start.p;
 #define VL_LDS(GG, VV)                                                                        \
-    k_vl_lds<T, E, MS, GG, VV><<<nbt, 256, lds, s>>>(rec, start, ibase, g, tiles_x, nbr16, len, \
+    k_vl_lds<T, E, MS, GG, VV><<<nbt, VL_LDS_TB, lds, s>>>(rec, start, ibase, g, tiles_x, nbr16, len, \
                                                      cap, cmax, tab, fo, remap)
         const int key = cfg.tile_i * 100 + cfg.tile_j;
         switch (key) {
@@ -485,6 +668,51 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
     return MDLJ_OK;
 }
 
+size_t build_tile_lds(bool local, int cmax, int ccand)
+{
+    return (size_t)cmax * (local ? 3 : 5) * sizeof(double) +
+           (size_t)(ccand + CAND_SLACK) * sizeof(uint16_t);
+}
+
+mdlj_status launch_build_tile(mdlj_ctx *ctx, bool local, bool half, bool ell, double rl2,
+                              int cmax, int ccand, int32_t cap)
+{
+    const Grid &g = ctx->grid;
+    const int tiles_x = (int)ceil_div(g.n[0], STAGE_K);
+    const int64_t nbt = (int64_t)tiles_x * g.n[1] * g.n[2];
+    const size_t lds = build_tile_lds(local, cmax, ccand);
+    const PosT *rec = (const PosT *)ctx->b_sorted.p;
+    const int32_t *start = (const int32_t *)ctx->b_start.p;
+    const int32_t *ibase = (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1;
+    int32_t *maxlen = (int32_t *)ctx->b_flags.p + 12;
+    int32_t *maxnb = (int32_t *)ctx->b_flags.p + 14;
+    int32_t *len = (int32_t *)ctx->b_nlen.p;
+    void *nbr = ctx->b_nbr.p;
+    const int32_t pad = (int32_t)ctx->n_ext;
+    const int64_t n = ctx->n;
+    hipStream_t s = ctx->stream;
+#define VL_BT(L, H, E)                                                                          \
+    k_vl_build_tile<L, H, E><<<nbt, BUILD_TB, lds, s>>>(rec, start, ibase, g, tiles_x, rl2, cmax, \
+                                                        ccand, n, cap, pad, nbr, len, maxlen,   \
+                                                        maxnb, 1)
+    if (local) {
+        if (half || ell) return set_err(ctx, MDLJ_ERR_ARG, "local lists are full row-major lists");
+        VL_BT(true, false, false);
+    } else if (ell) {
+        if (half)
+            VL_BT(false, true, true);
+        else
+            VL_BT(false, false, true);
+    } else if (half) {
+        VL_BT(false, true, false);
+    } else {
+        VL_BT(false, false, false);
+    }
+#undef VL_BT
+    HIPCHK(ctx, hipGetLastError());
+    return MDLJ_OK;
+}
+
 }  // namespace
 
 mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
@@ -504,19 +732,32 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
     const bool rowmajor = cfg.order != MDLJ_ORD_I_PER_LANE;
     const bool local = cfg.staged != 0;
     const size_t esize = local ? sizeof(uint16_t) : sizeof(int32_t);
+    // LDS of the tiled build: staged records (x, y, z; slot unless local;
+    // caller index for half lists) and the tile cells' candidate lists
+    const int cmax = 9 * (STAGE_K + 2) * ctx->max_cell;
+    const int ccand = STAGE_K * 27 * ctx->max_cell;
+    bool tile_ok = ctx->max_cell > 0 &&
+                   build_tile_lds(local, cmax, ccand) <= (size_t)STAGE_LDS_BYTES;
+    // a row of the tiled build may run past its capacity before the host
+    // sees it (it then rebuilds): slack of the longest possible row
+    const int64_t slack = rowmajor ? 27 * (int64_t)ctx->max_cell + 8 : 0;
     for (int attempt = 0; attempt < 3; ++attempt) {
         if ((double)cap * (double)n * (double)esize > 64e9)
             return set_err(ctx, MDLJ_ERR_OVERFLOW, "Verlet lists too large");
-        STCHK(ensure(ctx, ctx->b_nbr, esize * n * cap));
+        STCHK(ensure(ctx, ctx->b_nbr, esize * (n * cap + slack)));
         HIPCHK(ctx, hipMemsetAsync(maxlen, 0, 4 * sizeof(int32_t), ctx->stream));
-        if (local) {
+        const int64_t sk = rowmajor ? 1 : n;
+        const int64_t st = rowmajor ? cap : 1;
+        const bool tiled = tile_ok;
+        if (tiled) {
+            STCHK(launch_build_tile(ctx, local, cfg.newton3 != 0, !rowmajor, rl * rl, cmax, ccand,
+                                    (int32_t)cap));
+        } else if (local) {
             k_vl_build_local<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
                 (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
                 (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, g, n, rl * rl,
                 (int32_t)cap, (uint16_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen, maxnb);
         } else {
-            const int64_t sk = rowmajor ? 1 : n;
-            const int64_t st = rowmajor ? cap : 1;
             k_vl_build<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
                 (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
                 (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, g, n, rl * rl,
@@ -528,6 +769,12 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         HIPCHK(ctx, hipMemcpyAsync(hmax, maxlen, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
                                    ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (tiled && hmax[2] > cmax) {
+            // a tile over the staging limit built nothing: per-particle build
+            tile_ok = false;
+            --attempt;
+            continue;
+        }
         ctx->vl_max = hmax[0];
         ctx->max_nbhd = hmax[2];
         if (local && hmax[2] > 65535)

@@ -60,6 +60,23 @@ def test_vl_config2_100k(m, orc):
     check(m, orc, scenes.config2(), vl_configs(m), "cfg2")
 
 
+def test_vl_dense_large_cells_fall_back(m, orc):
+    # rc = 4: about 70 particles per cell, too many to stage a tile's
+    # neighbourhood in LDS, so the lists come from the per-particle build and
+    # staged configurations are refused with MDLJ_ERR_ARG
+    pos, box = scenes.fcc_lattice(8, 8, 8, 0.9, 0.05, seed=41)
+    s = dict(pos=pos, box=box, rc=4.0, eps=[1.0], sig=[1.0], types=None)
+    plain = [c for c in vl_configs(m) if len(c) < 7]
+    check(m, orc, s, plain, "dense")
+    with m.System(pos, box, 4.0, skin=0.3) as sysm:
+        for cfg in vl_configs(m):
+            if len(cfg) == 7:
+                with pytest.raises(m.MdljError) as ei:
+                    sysm.set_config(cfg)
+                    sysm.forces()
+                assert ei.value.status == -1, cfg
+
+
 def test_vl_zero_skin_equals_cutoff_lists(m, orc):
     check(m, orc, scenes.config1(), vl_configs(m)[:2], "skin0", skin=0.0)
 
@@ -114,3 +131,26 @@ def test_velocity_verlet_trajectory_matches_oracle(m, orc, cfg):
     assert np.abs(v - v_ref).max() < 1e-9, cfg
     assert P.force_error(f, f_ref) < 1e-9, cfg
     assert U == pytest.approx(ep[-1], rel=1e-10)
+
+
+@pytest.mark.parametrize("cfg", [(1, 2, 16, 4, 0, 0, 1), (1, 2, 4, 16, 0, 1)])
+def test_velocity_verlet_fast_particles_force_early_rebuilds(m, orc, cfg):
+    # velocities 15x thermal: particles cross skin/2 between scheduled
+    # rebuilds, so the displacement test of the integrator must trigger them
+    import torch
+    s = scenes.config1()
+    v0 = 15.0 * s["vel"]
+    p_ref, v_ref, f_ref, ep, ek = orc.vv(s["pos"], v0, s["box"], s["rc"], s["dt"], 12)
+    with m.System(s["pos"], s["box"], s["rc"], skin=0.3, rebuild_every=6, precision=1) as sysm:
+        sysm.set_config(cfg)
+        vel = [torch.tensor(np.ascontiguousarray(v0[:, k]), device="cuda") for k in range(3)]
+        sysm.set_timing(True)
+        sysm.step_vv(vel, s["dt"], 12)
+        _, _, nf, nb = sysm.get_timing()
+        pos = sysm.get_positions()
+    assert nb >= 5, (cfg, nf, nb)  # the schedule alone gives at most 3
+    v = torch.stack(vel, 1).cpu().numpy()
+    d = pos - p_ref
+    d -= s["box"] * np.rint(d / s["box"])
+    assert np.abs(d).max() < 1e-10, cfg
+    assert np.abs(v - v_ref).max() < 1e-8, cfg
