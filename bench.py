@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 # MD steps here compute forces only.
 FLOP_PER_PAIR = 26.0
 PEAK_FP32 = 157.3e12     # MI355X vector FP32 (packed) FLOP/s
+TUNER_WEIGHTS = os.path.join(ROOT, "paper_2512_03565_amd", "data", "tuner_mlp.bin")
 
 
 def parse():
@@ -49,6 +50,11 @@ def parse():
                     help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default=None, help="run one mode only: fixed|exhaustive|learned")
+    ap.add_argument("--config", default=None,
+                    help="run this configuration (by name) without tuning, e.g. for profiling")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="afterwards, copy a MIB-MiB device buffer 5 times (a plain copy of "
+                         "known size, to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -113,11 +119,19 @@ def main():
     modes = ["fixed", "exhaustive", "learned"]
     if args.only:
         modes = [args.only]
+    if args.config:
+        modes = ["given"]
     for mode in modes:
         sysm.set_positions(pos_d)
         vel = [torch.tensor(np.ascontiguousarray(vel0[:, k]), device="cuda") for k in range(3)]
         t0 = time.perf_counter()
-        if mode == "fixed":
+        if mode == "given":
+            names = [mdlj.config_name(c) for c in sysm.configs()]
+            if args.config not in names:
+                sys.exit(f"unknown configuration {args.config!r}; one of {names}")
+            sysm.set_config(sysm.configs()[names.index(args.config)])
+            cfg, tune_us = sysm.tune(mdlj.TUNE_FIXED, args.samples)
+        elif mode == "fixed":
             sysm.set_config((mdlj.NBR_LC, mdlj.ORD_I_PER_LANE, 1, 1, 0, 0))
             cfg, tune_us = sysm.tune(mdlj.TUNE_FIXED, args.samples)
         elif mode == "exhaustive":
@@ -125,6 +139,8 @@ def main():
             table = sysm.tune_results()
             space = [mdlj.config_name(c) for c in sysm.configs()]
         else:
+            if os.path.exists(TUNER_WEIGHTS):
+                sysm.mlp_load(TUNER_WEIGHTS)
             cfg, tune_us = sysm.tune(mdlj.TUNE_LEARNED, args.samples)
         tune_s = time.perf_counter() - t0
         r = run_mode(mdlj, torch, sysm, vel, s["dt"], args.steps, args.warmup, pairs)
@@ -133,6 +149,15 @@ def main():
         r["tuning_s"] = tune_s
         results[mode] = r
         print(f"# {mode}: {r}", file=sys.stderr, flush=True)
+    if args.copy_probe:
+        import torch as _t
+        a = _t.empty(args.copy_probe * (1 << 20) // 8, dtype=_t.float64, device="cuda")
+        b = _t.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(5):
+            b.copy_(a)
+        _t.cuda.synchronize()
+        print(f"# copy probe: 5 copies of {a.numel() * 8} bytes", file=sys.stderr, flush=True)
     head = results.get("exhaustive") or results[modes[0]]
     kern_us = head["force_kernel_us"]
     achieved = FLOP_PER_PAIR * pairs / (kern_us * 1e-6)

@@ -165,10 +165,10 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
 {
     constexpr int NW = BUILD_TB / MDLJ_WAVE;
     constexpr int RC = STAGE_K + 3;  // cell starts per row: STAGE_K + 2 cells and the end
-    // staged record: x, y, z (and for slot lists the slot and caller index);
-    // strides of 6 and 10 dwords keep 64-bit LDS reads of consecutive
-    // records free of bank conflicts
-    constexpr int RW = LOCAL ? 3 : 5;  // record size in doubles
+    // staged record: x, y, z (a stride of 6 dwords keeps 64-bit LDS reads of
+    // consecutive records free of bank conflicts); slot lists also stage
+    // each record's slot and caller index in arrays of their own
+    constexpr int RW = 3;
     extern __shared__ double stage[];
     __shared__ int rs[9][RC];        // start[] of the cells of each row
     __shared__ int seg_c[10];        // staged offset of each row
@@ -218,7 +218,9 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         return;
     }
     double *srec = stage;
-    uint16_t *cand = (uint16_t *)(stage + (size_t)RW * cmax);
+    int32_t *sslot = (int32_t *)(stage + (size_t)RW * cmax);
+    int32_t *sorig = sslot + (LOCAL ? 0 : cmax);
+    uint16_t *cand = (uint16_t *)(sorig + (HALF ? cmax : 0));
     {
         int r = 0;
         for (int k = tid; k < C; k += BUILD_TB) {
@@ -229,11 +231,8 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
             d[0] = p.x;
             d[1] = p.y;
             d[2] = p.z;
-            if (!LOCAL) {
-                int32_t *e = (int32_t *)(d + 3);
-                e[0] = slot;
-                e[1] = p.orig;
-            }
+            if (!LOCAL) sslot[k] = slot;
+            if (HALF) sorig[k] = p.orig;
         }
     }
     // candidate runs: tile cell c, row r -> row cells c .. c + 2
@@ -254,7 +253,7 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         while (c + 1 < ncx && i >= rs[4][c + 2]) ++c;
         const double *di = srec + RW * own;
         const double xi = di[0], yi = di[1], zi = di[2];
-        const int32_t oi = HALF ? ((const int32_t *)(di + 3))[1] : 0;
+        const int32_t oi = HALF ? sorig[own] : 0;
         const int pb = nc[c], pe = nc[c + 1];
         const int64_t t = t0 + (i - ib);
         uint16_t *row16 = (uint16_t *)nbr_out + t * cap;
@@ -273,8 +272,8 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
             bool ha = (lane < rem) & (ka != own) & (ax * ax + ay * ay + az * az < rl2);
             bool hb = (lane + MDLJ_WAVE < rem) & (kb != own) & (bx * bx + by * by + bz * bz < rl2);
             if (HALF) {
-                ha &= ((const int32_t *)(da + 3))[1] > oi;
-                hb &= ((const int32_t *)(db + 3))[1] > oi;
+                ha &= sorig[ka] > oi;
+                hb &= sorig[kb] > oi;
             }
             const uint64_t ma = __builtin_amdgcn_ballot_w64(ha);
             const uint64_t mb = __builtin_amdgcn_ballot_w64(hb);
@@ -290,11 +289,11 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
                 if (ha) row16[qa] = (uint16_t)ka;
                 if (hb) row16[qb] = (uint16_t)kb;
             } else if (!ELL) {
-                if (ha) row32[qa] = ((const int32_t *)(da + 3))[0];
-                if (hb) row32[qb] = ((const int32_t *)(db + 3))[0];
+                if (ha) row32[qa] = sslot[ka];
+                if (hb) row32[qb] = sslot[kb];
             } else {
-                if (ha && qa < (uint32_t)cap) row32[(int64_t)qa * n] = ((const int32_t *)(da + 3))[0];
-                if (hb && qb < (uint32_t)cap) row32[(int64_t)qb * n] = ((const int32_t *)(db + 3))[0];
+                if (ha && qa < (uint32_t)cap) row32[(int64_t)qa * n] = sslot[ka];
+                if (hb && qb < (uint32_t)cap) row32[(int64_t)qb * n] = sslot[kb];
             }
             cnt += na + (uint32_t)__builtin_popcountll(mb);
         }
@@ -668,9 +667,10 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
     return MDLJ_OK;
 }
 
-size_t build_tile_lds(bool local, int cmax, int ccand)
+size_t build_tile_lds(bool local, bool half, int cmax, int ccand)
 {
-    return (size_t)cmax * (local ? 3 : 5) * sizeof(double) +
+    return (size_t)cmax * (3 * sizeof(double) + (local ? 0 : sizeof(int32_t)) +
+                           (half ? sizeof(int32_t) : 0)) +
            (size_t)(ccand + CAND_SLACK) * sizeof(uint16_t);
 }
 
@@ -680,7 +680,7 @@ mdlj_status launch_build_tile(mdlj_ctx *ctx, bool local, bool half, bool ell, do
     const Grid &g = ctx->grid;
     const int tiles_x = (int)ceil_div(g.n[0], STAGE_K);
     const int64_t nbt = (int64_t)tiles_x * g.n[1] * g.n[2];
-    const size_t lds = build_tile_lds(local, cmax, ccand);
+    const size_t lds = build_tile_lds(local, half, cmax, ccand);
     const PosT *rec = (const PosT *)ctx->b_sorted.p;
     const int32_t *start = (const int32_t *)ctx->b_start.p;
     const int32_t *ibase = (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1;
@@ -737,7 +737,7 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
     const int cmax = 9 * (STAGE_K + 2) * ctx->max_cell;
     const int ccand = STAGE_K * 27 * ctx->max_cell;
     bool tile_ok = ctx->max_cell > 0 &&
-                   build_tile_lds(local, cmax, ccand) <= (size_t)STAGE_LDS_BYTES;
+                   build_tile_lds(local, cfg.newton3 != 0, cmax, ccand) <= (size_t)STAGE_LDS_BYTES;
     // a row of the tiled build may run past its capacity before the host
     // sees it (it then rebuilds): slack of the longest possible row
     const int64_t slack = rowmajor ? 27 * (int64_t)ctx->max_cell + 8 : 0;

@@ -1,0 +1,115 @@
+"""Score a trained tuner network on held-out scenes with fresh GPU timings.
+
+For every held-out scene of the sweep (scene index >= --first), on the GPU:
+
+  * learned tuning: features -> network -> the predicted configuration is
+    timed (or, below the confidence threshold, the full search runs); the
+    wall time of the tuning call is recorded;
+  * both the learned choice and the sweep's fastest configuration are timed
+    again with --samples samples each (amortised step time, the tuner's own
+    objective), and regret = t(learned) / t(fastest) - 1;
+  * the fixed one-order baseline (linked cells, i-per-lane) is timed the
+    same way;
+  * on every --full-every-th scene the full search is run as well, for the
+    cost of tuning without the network.
+
+Writes a JSON summary.
+
+    python -m paper_2512_03565_amd.eval_tuner sweep_0.npz sweep_1000.npz \
+        --weights paper_2512_03565_amd/data/tuner_mlp.bin --out eval.json
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("sweeps", nargs="+")
+    ap.add_argument("--weights", required=True)
+    ap.add_argument("--first", type=int, default=1600, help="first held-out scene index")
+    ap.add_argument("--count", type=int, default=400)
+    ap.add_argument("--samples", type=int, default=10)
+    ap.add_argument("--tune-samples", type=int, default=4)
+    ap.add_argument("--full-every", type=int, default=4)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+
+    import torch  # noqa: F401  (one HIP runtime: torch's)
+    from paper_2512_03565_amd import mdlj, scenes
+    from paper_2512_03565_amd.train_tuner import load
+
+    F, T, meta, names = load(a.sweeps)
+    idx = [k for k in range(len(meta)) if meta[k, 0] >= a.first][: a.count]
+    rows = []
+    t0 = time.time()
+    for q, k in enumerate(idx):
+        sid = int(meta[k, 0])
+        s = scenes.tuning_scene(sid)
+        types = s["types"] if len(s["eps"]) > 1 else None
+        with mdlj.System(s["pos"], s["box"], s["rc"], s["eps"], s["sig"], types=types,
+                         skin=s["skin"], rebuild_every=s["rebuild_every"]) as sysm:
+            space = [mdlj.config_name(c) for c in sysm.configs()]
+            if space != names:
+                raise ValueError("sweep and library configuration spaces differ")
+            cfgs = sysm.configs()
+            sysm.mlp_load(a.weights)
+            _, fb0 = sysm.mlp_stats()
+            c0 = time.perf_counter()
+            chosen, _ = sysm.tune(mdlj.TUNE_LEARNED, a.tune_samples)
+            t_learn = time.perf_counter() - c0
+            conf, fb1 = sysm.mlp_stats()
+            ci = space.index(mdlj.config_name(chosen))
+            best = int(np.argmin(T[k]))
+
+            def timed(j):
+                sysm.set_config(cfgs[j])
+                return sysm.tune(mdlj.TUNE_FIXED, a.samples)[1]
+
+            us_l = timed(ci)
+            us_b = us_l if best == ci else timed(best)
+            us_f = timed(space.index("LC/i-per-lane/k1"))
+            t_full = None
+            if q % a.full_every == 0:
+                c0 = time.perf_counter()
+                sysm.tune(mdlj.TUNE_EXHAUSTIVE, a.tune_samples)
+                t_full = time.perf_counter() - c0
+        rows.append(dict(scene=sid, n=int(meta[k, 1]), chosen=space[ci], best=space[best],
+                         confidence=conf, fallback=bool(fb1 > fb0), us_learned=us_l,
+                         us_best=us_b, us_fixed=us_f, tune_s_learned=t_learn,
+                         tune_s_full=t_full))
+        if q % 20 == 0:
+            print(f"[eval] {q}/{len(idx)} scene {sid} {space[ci]} vs {space[best]} "
+                  f"ratio {us_l / us_b:.3f} elapsed {time.time() - t0:.0f}s", flush=True)
+    r = np.array([x["us_learned"] / x["us_best"] for x in rows])
+    fx = np.array([x["us_fixed"] / x["us_best"] for x in rows])
+    tl = np.array([x["tune_s_learned"] for x in rows])
+    full = [x for x in rows if x["tune_s_full"] is not None]
+    summary = {
+        "scenes": len(rows),
+        "samples": a.samples,
+        "regret_geomean": float(np.exp(np.log(r).mean()) - 1),
+        "regret_mean": float(r.mean() - 1),
+        "regret_p90": float(np.percentile(r, 90) - 1),
+        "regret_max": float(r.max() - 1),
+        "within_5pct": float((r <= 1.05).mean()),
+        "fallback_rate": float(np.mean([x["fallback"] for x in rows])),
+        "same_as_best": float(np.mean([x["chosen"] == x["best"] for x in rows])),
+        "fixed_over_best_geomean": float(np.exp(np.log(fx).mean())),
+        "tune_s_learned_mean": float(tl.mean()),
+        "tune_s_full_mean": float(np.mean([x["tune_s_full"] for x in full])) if full else None,
+        "tune_s_learned_on_full_scenes": float(np.mean([x["tune_s_learned"] for x in full]))
+        if full else None,
+    }
+    print(json.dumps(summary), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump({"summary": summary, "scenes": rows}, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,79 @@
+"""GPU checks of the trained tuner network shipped with the package.
+
+The network (paper_2512_03565_amd/data/tuner_mlp.bin) was trained on the GPU
+with the library's own kernels on the timing sweep stored beside it
+(tuner_sweep.npz: features and amortised step times of every configuration
+for seeded scenes).  Here, on held-out scenes of that sweep:
+
+  * what the network gains: learned tuning costs a fraction of the full
+    search's wall time, and its choice runs far faster than the fixed
+    one-order baseline (linked cells, i-per-lane);
+  * what it gives up: the re-measured step time of its choice stays close
+    to that of the sweep's fastest configuration.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                    "paper_2512_03565_amd", "data")
+WEIGHTS = os.path.join(DATA, "tuner_mlp.bin")
+SWEEP = os.path.join(DATA, "tuner_sweep.npz")
+
+
+@pytest.fixture(scope="module")
+def m():
+    from paper_2512_03565_amd import mdlj
+    return mdlj
+
+
+def held_out(n_max, count):
+    d = np.load(SWEEP, allow_pickle=False)
+    meta, table = d["meta"], d["table_us"]
+    rows = [k for k in range(len(meta)) if meta[k, 0] >= 1600 and meta[k, 1] <= n_max]
+    return [(int(meta[k, 0]), table[k]) for k in rows[:count]], list(d["names"])
+
+
+def test_learned_tuner_close_to_full_search_and_cheaper(m):
+    from paper_2512_03565_amd import scenes
+    cases, names = held_out(400_000, 12)
+    assert len(cases) >= 8
+    ratios, fixed_ratios, t_learn, t_full = [], [], [], []
+    for sid, table in cases:
+        s = scenes.tuning_scene(sid)
+        types = s["types"] if len(s["eps"]) > 1 else None
+        print(f"[learned] scene {sid} n={len(s['pos'])}", flush=True)
+        with m.System(s["pos"], s["box"], s["rc"], s["eps"], s["sig"], types=types,
+                      skin=s["skin"], rebuild_every=s["rebuild_every"]) as sysm:
+            cfgs = sysm.configs()
+            assert [m.config_name(c) for c in cfgs] == names
+            sysm.mlp_load(WEIGHTS)
+            t0 = time.perf_counter()
+            chosen, _ = sysm.tune(m.TUNE_LEARNED, 4)
+            t_learn.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            sysm.tune(m.TUNE_EXHAUSTIVE, 4)
+            t_full.append(time.perf_counter() - t0)
+
+            def timed(cfg):
+                sysm.set_config(cfg)
+                return sysm.tune(m.TUNE_FIXED, 10)[1]
+
+            us_l = timed(chosen)
+            us_b = timed(cfgs[int(np.argmin(table))])
+            us_f = timed(cfgs[names.index("LC/i-per-lane/k1")])
+        ratios.append(us_l / us_b)
+        fixed_ratios.append(us_f / us_l)
+    g = float(np.exp(np.mean(np.log(ratios))))
+    print(f"[learned] geomean t(learned)/t(best) = {g:.4f}, fixed/learned = "
+          f"{np.exp(np.mean(np.log(fixed_ratios))):.2f}, tuning s learned {np.mean(t_learn):.3f} "
+          f"full {np.mean(t_full):.3f}", flush=True)
+    # timing noise of a few percent per measurement: the bar here is loose;
+    # the 400-scene evaluation with 10 samples per time is the measurement
+    assert g <= 1.10
+    assert float(np.exp(np.mean(np.log(fixed_ratios)))) > 1.5
+    assert np.mean(t_learn) < 0.6 * np.mean(t_full)
