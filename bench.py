@@ -83,6 +83,40 @@ def run_mode(m, torch, sysm, vel, dt, steps, warmup, pairs):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vl_lds_16x4_headline_1M_traffic.json")
+
+
+def measured_traffic(config_name):
+    """HBM bytes per launch of the force kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters read
+    for a copy of known size); None unless it was taken for this
+    configuration and the kernel sources are unchanged since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("config") != config_name:
+        return None
+    h = hashlib.sha256()
+    for rel in t["source_files"]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return t["traffic_bytes_per_launch"] if h.hexdigest() == t["source_sha256"] else None
+
+
+def list_stream_bytes(sysm, n):
+    """Algorithmic bytes of one Verlet-list force launch: the stored list
+    entries (rows padded to 8), the list lengths (4 B per particle), the
+    x, y, z of every sorted record once (24 B) and the forces written
+    (24 B per particle).  None when the structure holds no Verlet lists."""
+    entries, esize, records = sysm.neighbor_stats()
+    if entries == 0:
+        return None
+    return entries * esize + 4 * n + 24 * records + 24 * n
+
+
 def cpu_baseline(scene, budget_s):
     import oracle
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -145,6 +179,10 @@ def main():
         tune_s = time.perf_counter() - t0
         r = run_mode(mdlj, torch, sysm, vel, s["dt"], args.steps, args.warmup, pairs)
         r["config"] = mdlj.config_name(cfg)
+        sb = list_stream_bytes(sysm, n)
+        if sb is not None:
+            r["list_stream_bytes"] = sb
+            r["list_stream_GBps"] = sb / (r["force_kernel_us"] * 1e-6) / 1e9
         r["tuned_step_us"] = tune_us
         r["tuning_s"] = tune_s
         results[mode] = r
@@ -191,11 +229,19 @@ def main():
             "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
-            "traffic": None,
+            "traffic": measured_traffic(head["config"]),
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE x 1, "
+                            "factors from a 1 GiB copy)",
             "kernel": head["config"],
             "flop_per_pair": FLOP_PER_PAIR,
         },
     }
+    if "list_stream_bytes" in head:
+        # the same launch read as list streaming: algorithmic bytes / time
+        line["hbm_list_stream"] = {
+            "achieved": head["list_stream_GBps"], "peak": 8000.0, "unit": "GB/s",
+            "frac": head["list_stream_GBps"] / 8000.0,
+            "bytes_per_launch": head["list_stream_bytes"]}
     if "exhaustive" in results:
         line["tuning_table_us"] = {name: (None if not np.isfinite(v) else round(float(v), 2))
                                    for name, v in zip(space, table)}

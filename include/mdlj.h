@@ -191,6 +191,19 @@ mdlj_status mdlj_compute_forces(mdlj_ctx *ctx, double *fx, double *fy, double *f
 mdlj_status mdlj_count_pairs(mdlj_ctx *ctx, int64_t *n_useful_pairs);
 
 /*
+ * Size of the current neighbour structure (section 2.1.1), for traffic
+ * accounting: *list_entries = stored Verlet-list entries including the
+ * padding of each row to a multiple of 8 (0 unless the structure is a
+ * Verlet list), *entry_bytes = bytes per entry (2 for the 16-bit lists of
+ * staged configurations, 4 otherwise, 0 without lists), *records = sorted
+ * records including halo images (0 before the first build).  Host
+ * pointers, all required.  Synchronises.  MDLJ_ERR_STATE before the first
+ * force call.
+ */
+mdlj_status mdlj_neighbor_stats(mdlj_ctx *ctx, int64_t *list_entries, int32_t *entry_bytes,
+                                int64_t *records);
+
+/*
  * Choose a configuration.  FIXED keeps the current one; EXHAUSTIVE times
  * every valid configuration `samples` times (first sample dropped as
  * warm-up, the rest averaged; the lower index wins ties) on the amortised

@@ -707,4 +707,20 @@ mdlj_status mdlj_count_pairs(mdlj_ctx *ctx, int64_t *n_useful_pairs)
     return count_pairs_dev(ctx, n_useful_pairs);
 }
 
+mdlj_status mdlj_neighbor_stats(mdlj_ctx *ctx, int64_t *list_entries, int32_t *entry_bytes,
+                                int64_t *records)
+{
+    if (!ctx || !list_entries || !entry_bytes || !records) return MDLJ_ERR_ARG;
+    if (!ctx->built) return set_err(ctx, MDLJ_ERR_STATE, "no neighbour structure built yet");
+    const mdlj_config &b = ctx->built_cfg;
+    *list_entries = 0;
+    *entry_bytes = 0;
+    *records = ctx->n_ext;
+    if (b.nbr_algo == MDLJ_NBR_VL) {
+        STCHK(vl_list_entries(ctx, list_entries));
+        *entry_bytes = b.staged ? 2 : 4;
+    }
+    return MDLJ_OK;
+}
+
 }  // extern "C"

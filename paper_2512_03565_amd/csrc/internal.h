@@ -225,6 +225,8 @@ mdlj_status lc_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceO
 mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg);
 mdlj_status vl_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
                       int64_t *nblocks);
+// Stored list entries (rows padded to a multiple of 8) of the current lists.
+mdlj_status vl_list_entries(mdlj_ctx *ctx, int64_t *entries);
 mdlj_status vcl_build(mdlj_ctx *ctx, const mdlj_config &cfg);
 mdlj_status vcl_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
                        int64_t *nblocks);

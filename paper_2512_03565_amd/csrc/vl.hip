@@ -713,7 +713,39 @@ mdlj_status launch_build_tile(mdlj_ctx *ctx, bool local, bool half, bool ell, do
     return MDLJ_OK;
 }
 
+// Sum over rows of the row length rounded up to a multiple of 8.
+__global__ __launch_bounds__(256) void k_list_entries(const int32_t *__restrict__ len, int64_t n,
+                                                      unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long red[256 / MDLJ_WAVE];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = t < n ? (unsigned long long)((len[t] + 7) & ~7) : 0ull;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0) red[threadIdx.x / MDLJ_WAVE] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)blockDim.x / MDLJ_WAVE; ++w) v += red[w];
+        atomicAdd(out, v);
+    }
+}
+
 }  // namespace
+
+mdlj_status vl_list_entries(mdlj_ctx *ctx, int64_t *entries)
+{
+    STCHK(ensure(ctx, ctx->b_misc, sizeof(unsigned long long)));
+    // b_misc is binning scratch, free between builds
+    unsigned long long *d = (unsigned long long *)ctx->b_misc.p;
+    HIPCHK(ctx, hipMemsetAsync(d, 0, sizeof *d, ctx->stream));
+    k_list_entries<<<ceil_div(ctx->n, 256), 256, 0, ctx->stream>>>((const int32_t *)ctx->b_nlen.p,
+                                                                  ctx->n, d);
+    HIPCHK(ctx, hipGetLastError());
+    unsigned long long h = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *entries = (int64_t)h;
+    return MDLJ_OK;
+}
 
 mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
 {

@@ -93,6 +93,8 @@ _SIGS = {
     "mdlj_rebuild_neighbors": [_ctxp],
     "mdlj_compute_forces": [_ctxp, _vp, _vp, _vp, C.c_int32, _d, _d],
     "mdlj_count_pairs": [_ctxp, C.POINTER(C.c_int64)],
+    "mdlj_neighbor_stats": [_ctxp, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                            C.POINTER(C.c_int64)],
     "mdlj_tune": [_ctxp, C.c_int32, C.c_int32, C.POINTER(mdlj_config), _d],
     "mdlj_tune_results": [_ctxp, _d, C.c_int32, C.POINTER(C.c_int32)],
     "mdlj_step_vv": [_ctxp, _vp, _vp, _vp, C.c_double, C.c_int32],
@@ -291,6 +293,13 @@ class System:
         else:
             f = out
         return f, U.value, W.value
+
+    def neighbor_stats(self):
+        """(stored list entries incl. row padding, bytes per entry, records)."""
+        e, r = C.c_int64(), C.c_int64()
+        b = C.c_int32()
+        check(lib.mdlj_neighbor_stats(self.ctx, C.byref(e), C.byref(b), C.byref(r)), self.ctx)
+        return e.value, b.value, r.value
 
     def count_pairs(self):
         n = C.c_int64()

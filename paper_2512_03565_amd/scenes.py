@@ -236,9 +236,15 @@ def config4(seed=1004, ncell=100):
 
 
 def config3(seed=1003, n_total=1_000_000, r_drop=40.0):
-    """Droplet of radius r_drop at rho 0.8 inside vapour at rho 0.05, periodic
-    cube, RSA with minimum spacing 0.9, rc 3.0, T = 0.9."""
-    pos, box = droplet_scene(n_total, r_drop, 0.8, 0.05, 0.9, seed)
+    """Droplet of radius r_drop at rho 0.8 inside vapour at rho 0.05 in a
+    periodic cube, about n_total particles, rc 3.0, T = 0.9.  The droplet is
+    a jittered FCC lattice cut to the sphere and the vapour a jittered simple
+    cubic lattice (minimum spacing above 0.9 in both); random sequential
+    addition at rho 0.8 with spacing 0.9 is too close to its jamming limit to
+    be practical at this size."""
+    n_drop = 0.8 * 4.0 / 3.0 * math.pi * r_drop ** 3
+    pos, box = lattice_droplet(n_total, 0.8, frac_drop=n_drop / n_total, rho_vap=0.05,
+                               jitter=0.05, seed=seed)
     return _scene(pos, box, rc=3.0, skin=0.3, rebuild_every=10, T=0.9, dt=0.002,
                   name=f"{len(pos)} droplet r{r_drop}")
 

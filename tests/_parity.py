@@ -62,3 +62,34 @@ def force_error(f, ref, slack=None, idx=None, scale=None):
 
 def total_error(val, ref, slack=0.0):
     return max(0.0, abs(val - ref) - slack) / max(abs(ref), 1e-300)
+
+
+def boundary_slack_subset(orc, pos, box, rc, eps, sig, types, shift, band, idx):
+    """Force slack of the particles idx only (for large scenes): their pairs
+    in the ambiguous band, found with a periodic k-d tree; r^2 is formed as
+    the oracle forms it (minimum image, then dx*dx + dy*dy + dz*dz)."""
+    from scipy.spatial import cKDTree
+    box = np.asarray(box, np.float64)
+    w = pos - box * np.floor(pos / box)
+    w = np.where(w >= box, w - box, w)
+    tree = cKDTree(w, boxsize=box)
+    eps = np.atleast_1d(eps)
+    sig = np.atleast_1d(sig)
+    slack = np.zeros(len(idx))
+    hits = tree.query_ball_point(w[idx], rc * np.sqrt(1.0 + 2 * band) * (1 + 1e-9))
+    for q, (a, js) in enumerate(zip(idx, hits)):
+        if not js:
+            continue
+        js = np.asarray(js)
+        js = js[js != a]
+        d = pos[a] - pos[js]
+        d -= box * np.rint(d / box)
+        r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        for b, r2b in zip(js[np.abs(r2 / (rc * rc) - 1.0) <= band],
+                          r2[np.abs(r2 / (rc * rc) - 1.0) <= band]):
+            ta = 0 if types is None else int(types[a])
+            tb = 0 if types is None else int(types[b])
+            e_ab, s_ab = orc.mix(eps[ta], sig[ta], eps[tb], sig[tb])
+            f, _, _ = orc.lj_pair(float(r2b), e_ab, s_ab, rc, shift)
+            slack[q] += abs(f) * np.sqrt(r2b) * (1 + 1e-6)
+    return slack
