@@ -128,7 +128,7 @@ __global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
     double *sx = stage, *sy = stage + cmax, *sz = stage + 2 * cmax;
     int *st = (int *)(stage + 3 * cmax);
     if (STAGED) {
-        stage_rows(rec, seg_b, seg_c, C, sx, sy, sz, st, MS, lane, MDLJ_WAVE);
+        stage_rows_simple(rec, seg_b, seg_c, C, sx, sy, sz, st, MS, lane, MDLJ_WAVE);
         __syncthreads();
     }
     // local index of the cell's own first particle in the staged order

@@ -180,9 +180,12 @@ constexpr double PAD_COORD = 1.0e7;
 // bytes of LDS per workgroup are used for it.
 constexpr int STAGE_LDS_BYTES = 64 * 1024;
 
-__device__ __forceinline__ void stage_rows(const PosT *__restrict__ rec, const int *seg_b,
-                                           const int *seg_c, int C, double *sx, double *sy,
-                                           double *sz, int *st, bool types, int lane, int nthr)
+// One record per lane and trip (the form the per-wavefront staging of the
+// linked-cell kernels runs fastest with).
+__device__ __forceinline__ void stage_rows_simple(const PosT *__restrict__ rec, const int *seg_b,
+                                                  const int *seg_c, int C, double *sx, double *sy,
+                                                  double *sz, int *st, bool types, int lane,
+                                                  int nthr)
 {
     int r = 0;
     for (int k = lane; k < C; k += nthr) {
@@ -192,5 +195,48 @@ __device__ __forceinline__ void stage_rows(const PosT *__restrict__ rec, const i
         sy[k] = p.y;
         sz[k] = p.z;
         if (types) st[k] = p.t;
+    }
+}
+
+// Record k goes to sx[SD * k], sy[SD * k], sz[SD * k]: SD = 1 for separate
+// arrays, SD = 3 with sy = sx + 1 and sz = sx + 2 for interleaved x, y, z.
+template <int SD = 1>
+__device__ __forceinline__ void stage_rows(const PosT *__restrict__ rec, const int *seg_b,
+                                           const int *seg_c, int C, double *sx, double *sy,
+                                           double *sz, int *st, bool types, int lane, int nthr)
+{
+    // four records per thread in flight: the row of staged index k is found
+    // without branches (the number of row starts <= k), so the loads of all
+    // four issue back to back before the stores
+    constexpr int U = 4;
+    int c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = seg_c[q + 1];
+    for (int k0 = lane; k0 < C; k0 += U * nthr) {
+        double x[U], y[U], z[U];
+        int t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // past the end, load record C - 1 again (not stored): no branch
+            const int k = min(k0 + u * nthr, C - 1);
+            int r = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r += k >= c[q];
+            const PosT *p = rec + seg_b[r] + (k - seg_c[r]);
+            x[u] = p->x;
+            y[u] = p->y;
+            z[u] = p->z;
+            t[u] = types ? p->t : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * nthr;
+            if (k < C) {
+                sx[SD * k] = x[u];
+                sy[SD * k] = y[u];
+                sz[SD * k] = z[u];
+                if (types) st[k] = t[u];
+            }
+        }
     }
 }

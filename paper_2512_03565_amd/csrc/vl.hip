@@ -323,16 +323,31 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
 // or 4-byte load) and the j-particles from LDS.
 constexpr int VL_LDS_TB = 256;
 
+// V list entries (16-bit) of a row from entry k0 (a multiple of V): one
+// 16-, 8- or 4-byte load, entries in the low halves first.
+template <int V>
+__device__ __forceinline__ uint4 list_words(const uint16_t *row, int32_t k0)
+{
+    if (V == 8) return ((const uint4 *)row)[k0 >> 3];
+    if (V == 4) {
+        const uint2 q = ((const uint2 *)row)[k0 >> 2];
+        return make_uint4(q.x, q.y, 0u, 0u);
+    }
+    return make_uint4(((const uint32_t *)row)[k0 >> 1], 0u, 0u, 0u);
+}
+
 template <typename T, bool E, bool MS, int G, int V>
 __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ rec,
                                                 const int32_t *__restrict__ start,
                                                 const int32_t *__restrict__ ibase, Grid g,
                                                 int tiles_x, const uint16_t *__restrict__ nbr,
                                                 const int32_t *__restrict__ len, int32_t cap,
-                                                int cmax, LJTable<T> tab, ForceOut fo, int remap)
+                                                int64_t n, int cmax, LJTable<T> tab, ForceOut fo,
+                                                int remap)
 {
     constexpr int SEG = MDLJ_WAVE / G;
     constexpr int NW = VL_LDS_TB / MDLJ_WAVE;
+    constexpr int KS = V * SEG;  // entries of one i per trip
     extern __shared__ double stage[];
     __shared__ int seg_b[9];
     __shared__ int seg_c[10];
@@ -359,6 +374,28 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
         seg_b[tid] = start[ej];
         seg_c[tid + 1] = start[ej + ncx + 2] - start[ej];
     }
+    // compact index of the tile's first particle (cells of a tile are consecutive)
+    const int64_t c0 = (int64_t)cx0 + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz);
+    const int64_t t0 = ibase[c0];
+    const int l = lane % SEG;
+    // The first i-group of this wavefront: its records, list lengths and the
+    // first two trips of list entries are requested before the staging, so
+    // their latency overlaps it.  The loads are unconditional (a branch
+    // around a load makes the compiler wait for it at the merge): inactive
+    // lanes read row n - 1, and trip starts are clamped to cap - V, which
+    // keeps every read inside its row (cap is a multiple of 8); what those
+    // reads return is never used.
+    int i0 = ib + wv * G;
+    int i = i0 + lane / SEG;
+    bool act = i < ie;
+    int64_t t = t0 + (act ? i - ib : 0);
+    PosT pi = rec[act ? i : ib];
+    const int64_t tr = min(t, n - 1);
+    int32_t L = len[tr];
+    L = act ? L : 0;
+    const uint16_t *row = nbr + tr * cap;
+    uint4 wa = list_words<V>(row, min(V * l, cap - V));
+    uint4 wb = list_words<V>(row, min(V * l + KS, cap - V));
     __syncthreads();
     if (tid == 0) {
         seg_c[0] = 0;
@@ -366,45 +403,51 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
     }
     __syncthreads();
     const int C = seg_c[9];
-    double *sx = stage, *sy = stage + cmax, *sz = stage + 2 * cmax;
+    // x, y, z of staged record k interleaved at sp[3k .. 3k+2]: one LDS
+    // address per candidate
+    double *sp = stage;
     int *st = (int *)(stage + 3 * cmax);
-    stage_rows(rec, seg_b, seg_c, C, sx, sy, sz, st, MS, tid, blockDim.x);
+    stage_rows<3>(rec, seg_b, seg_c, C, sp, sp + 1, sp + 2, st, MS, tid, blockDim.x);
     if (tid == 0) {
-        sx[C] = sy[C] = sz[C] = PAD_COORD;
+        sp[3 * C] = sp[3 * C + 1] = sp[3 * C + 2] = PAD_COORD;
         if (MS) st[C] = 0;
     }
     __syncthreads();
-    // compact index of the tile's first particle (cells of a tile are consecutive)
-    const int64_t c0 = (int64_t)cx0 + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz);
-    const int64_t t0 = ibase[c0];
-    const int l = lane % SEG;
     double bu = 0.0, bw = 0.0;
-    for (int i0 = ib + wv * G; i0 < ie; i0 += NW * G) {
-        const int i = i0 + lane / SEG;
-        const bool act = i < ie;
-        const PosT pi = rec[act ? i : ib];
-        const int64_t t = t0 + (act ? i - ib : 0);
-        const int32_t L = act ? len[t] : 0;
-        const uint16_t *row = nbr + t * cap;
+    for (bool first = true; i0 < ie; i0 += NW * G, first = false) {
+        if (!first) {
+            i = i0 + lane / SEG;
+            act = i < ie;
+            t = t0 + (act ? i - ib : 0);
+            pi = rec[act ? i : ib];
+            const int64_t tq = min(t, n - 1);
+            L = len[tq];
+            L = act ? L : 0;
+            row = nbr + tq * cap;
+            wa = list_words<V>(row, min(V * l, cap - V));
+            wb = list_words<V>(row, min(V * l + KS, cap - V));
+        }
         Acc a;
         acc_zero(a);
-        for (int32_t k0 = V * l; k0 < L; k0 += V * SEG) {
-            uint32_t w[4];
-            if (V == 8) {
-                const uint4 q = ((const uint4 *)row)[k0 >> 3];
-                w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
-            } else if (V == 4) {
-                const uint2 q = ((const uint2 *)row)[k0 >> 2];
-                w[0] = q.x; w[1] = q.y;
-            } else {
-                w[0] = ((const uint32_t *)row)[k0 >> 1];
-            }
+        auto trip = [&](const uint4 q) {
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
             for (int u = 0; u < V; ++u) {
                 const int k = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
                 const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, MS ? st[k] : 0);
                 double fxp, fyp, fzp;
-                lj_pair<T, E>(pi.x, pi.y, pi.z, sx[k], sy[k], sz[k], true, p, rc2, a, fxp, fyp, fzp);
+                const double *q = sp + 3 * k;
+                lj_pair<T, E>(pi.x, pi.y, pi.z, q[0], q[1], q[2], true, p, rc2, a, fxp, fyp, fzp);
+            }
+        };
+        // two trips in flight, alternating between two registers (no copy
+        // between them, so a load is only waited for when its trip runs)
+        for (int32_t k0 = V * l; k0 < L; k0 += 2 * KS) {
+            trip(wa);
+            wa = list_words<V>(row, min(k0 + 2 * KS, cap - V));
+            if (k0 + KS < L) {
+                trip(wb);
+                wb = list_words<V>(row, min(k0 + 3 * KS, cap - V));
             }
         }
         a.fx = seg_sum(a.fx, SEG);
@@ -603,7 +646,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         const int32_t *start = (const int32_t *)ctx->b_start.p;
 #define VL_LDS(GG, VV)                                                                        \
     k_vl_lds<T, E, MS, GG, VV><<<nbt, VL_LDS_TB, lds, s>>>(rec, start, ibase, g, tiles_x, nbr16, len, \
-                                                     cap, cmax, tab, fo, remap)
+                                                     cap, n, cmax, tab, fo, remap)
         const int key = cfg.tile_i * 100 + cfg.tile_j;
         switch (key) {
         case 802: VL_LDS(8, 2); break;
