@@ -222,17 +222,39 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     int32_t *sorig = sslot + (LOCAL ? 0 : cmax);
     uint16_t *cand = (uint16_t *)(sorig + (HALF ? cmax : 0));
     {
-        int r = 0;
-        for (int k = tid; k < C; k += BUILD_TB) {
-            while (k >= seg_c[r + 1]) ++r;
-            const int32_t slot = rs[r][0] + (k - seg_c[r]);
-            const PosT p = rec[slot];
-            double *d = srec + RW * k;
-            d[0] = p.x;
-            d[1] = p.y;
-            d[2] = p.z;
-            if (!LOCAL) sslot[k] = slot;
-            if (HALF) sorig[k] = p.orig;
+        // two records per thread in flight; rows found without branches and
+        // loads unconditional (past the end record C - 1 is read, not stored)
+        int cb[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cb[q] = seg_c[q + 1];
+        for (int k0 = tid; k0 < C; k0 += 2 * BUILD_TB) {
+            double x[2], y[2], z[2];
+            int32_t sl[2], org[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int k = min(k0 + u * BUILD_TB, C - 1);
+                int r = 0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) r += k >= cb[q];
+                sl[u] = rs[r][0] + (k - seg_c[r]);
+                const PosT *p = rec + sl[u];
+                x[u] = p->x;
+                y[u] = p->y;
+                z[u] = p->z;
+                org[u] = HALF ? p->orig : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int k = k0 + u * BUILD_TB;
+                if (k < C) {
+                    double *d = srec + RW * k;
+                    d[0] = x[u];
+                    d[1] = y[u];
+                    d[2] = z[u];
+                    if (!LOCAL) sslot[k] = sl[u];
+                    if (HALF) sorig[k] = org[u];
+                }
+            }
         }
     }
     // candidate runs: tile cell c, row r -> row cells c .. c + 2
