@@ -489,7 +489,7 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
                       &ctx->b_cpair,   &ctx->b_cstart,  &ctx->b_fold,
                       &ctx->b_pos,     &ctx->b_type,    &ctx->b_force,
                       &ctx->b_cnt_ext, &ctx->b_img,     &ctx->b_icnt,    &ctx->b_ilist,
-                      &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo};
+                      &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo,    &ctx->b_hstart};
     for (DevBuf *b : bufs) free_buf(*b);
     delete ctx;
     return MDLJ_OK;

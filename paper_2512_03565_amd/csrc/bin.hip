@@ -204,11 +204,14 @@ __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
 
 // One wavefront per extended cell: interior cells gather their records,
 // halo cells copy the records of their source cell shifted by +-L.  Within
-// a cell records are ordered by caller index (so the layout does not depend
-// on the order in which the counting atomics were served): element m of the
-// source cell's unordered list goes to slot b + (number of elements with a
-// smaller caller index).  Halo cells rank their source's list the same way,
-// so every image has the order of its source.
+// a cell records are ordered by the key (x half, caller index): first the
+// particles in the lower half of the cell along x, then the upper half,
+// each by caller index.  The order does not depend on the order in which
+// the counting atomics were served: element m of the source cell's
+// unordered list goes to slot b + (number of elements with a smaller key).
+// Halo cells rank their source's list the same way, so every image has the
+// order of its source.  hstart[e] = first slot of the upper half (the list
+// build uses the halves to drop candidates more than one cell away in x).
 __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict__ start,
                                               const int32_t *__restrict__ unordered,
                                               const double *__restrict__ x,
@@ -217,7 +220,8 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
                                               const int32_t *__restrict__ type,
                                               PosT *__restrict__ rec,
                                               int32_t *__restrict__ slot_of,
-                                              char4 *__restrict__ img)
+                                              char4 *__restrict__ img,
+                                              int32_t *__restrict__ hstart)
 {
     int64_t e = (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
     int lane = threadIdx.x & (MDLJ_WAVE - 1);
@@ -227,6 +231,7 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
     signed char code[3];
     int64_t src = 0;
     bool interior = true;
+    int sx_cell = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         int c = (int)((e / g.stride[a]) % g.e[a]) - g.h[a];
@@ -236,17 +241,27 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
         if (c < 0) { s = c + g.n[a]; sh[a] = -g.L[a]; code[a] = -1; interior = false; }
         if (c >= g.n[a]) { s = c - g.n[a]; sh[a] = g.L[a]; code[a] = 1; interior = false; }
         src += (int64_t)(s + g.h[a]) * g.stride[a];
+        if (a == 0) sx_cell = s;
     }
     const int32_t sb = start[src];
+    // caller indices are below 2^30: key = upper-half bit 31 | caller index
+    const double xmid = ((double)sx_cell + 0.5) * g.edge[0];
+    auto key_of = [&](int32_t i) {
+        return (uint32_t)i | (x[i] < xmid ? 0u : 0x80000000u);
+    };
+    int32_t nlow = 0;
     for (int32_t m0 = 0; m0 < cnt; m0 += MDLJ_WAVE) {
         const int32_t m = m0 + lane;
-        const int32_t i = m < cnt ? unordered[sb + m] : INT32_MAX;
+        const int32_t i = m < cnt ? unordered[sb + m] : 0;
+        const uint32_t ki = m < cnt ? key_of(i) : 0xffffffffu;
         int32_t rank = 0;
         for (int32_t q0 = 0; q0 < cnt; q0 += MDLJ_WAVE) {
-            const int32_t v = q0 + lane < cnt ? unordered[sb + q0 + lane] : INT32_MAX;
+            const int32_t vi = q0 + lane < cnt ? unordered[sb + q0 + lane] : 0;
+            const uint32_t v = q0 + lane < cnt ? key_of(vi) : 0xffffffffu;
             const int32_t nq = min(cnt - q0, MDLJ_WAVE);
-            for (int32_t q = 0; q < nq; ++q) rank += __builtin_amdgcn_readlane(v, q) < i;
+            for (int32_t q = 0; q < nq; ++q) rank += __builtin_amdgcn_readlane(v, q) < ki;
         }
+        nlow += __popcll(__ballot(m < cnt && ki < 0x80000000u));
         if (m < cnt) {
             const int32_t k = b + rank;
             PosT r;
@@ -260,6 +275,7 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
             if (interior) slot_of[i] = k;
         }
     }
+    if (lane == 0) hstart[e] = b + nlow;
 }
 
 // The padding record at slot n_ext: far outside the box, no particle.
@@ -497,9 +513,10 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     int32_t *unordered = (int32_t *)ctx->b_misc.p;
     k_scatter<<<ceil_div(n, TB), TB, 0, s>>>(n, (int32_t *)ctx->b_cell_of.p,
                                               (int32_t *)ctx->b_rank.p, start, unordered);
+    STCHK(ensure(ctx, ctx->b_hstart, sizeof(int32_t) * g.ncell_ext));
     k_fill<<<ceil_div(g.ncell_ext, TB / MDLJ_WAVE), TB, 0, s>>>(
         g, start, unordered, ctx->x, ctx->y, ctx->z, ctx->type, (PosT *)ctx->b_sorted.p,
-        (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p);
+        (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p, (int32_t *)ctx->b_hstart.p);
     k_pad_record<<<1, 64, 0, s>>>((PosT *)ctx->b_sorted.p, n_ext);
     HIPCHK(ctx, hipGetLastError());
     ctx->grid = g;

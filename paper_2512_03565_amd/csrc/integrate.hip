@@ -116,7 +116,8 @@ __global__ void k_kick_drift_fused(int64_t n, double *__restrict__ x, double *__
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t s = slot_of[i];
-    const double h = 0.5 * dt * im.v[type[i]];
+    const int32_t ti = type[i];
+    const double h = 0.5 * dt * im.v[ti];
     const double ux = (vx[i] + h * fx[s]) + h * fx[s];
     const double uy = (vy[i] + h * fy[s]) + h * fy[s];
     const double uz = (vz[i] + h * fz[s]) + h * fz[s];
@@ -127,9 +128,14 @@ __global__ void k_kick_drift_fused(int64_t n, double *__restrict__ x, double *__
     x[i] = px;
     y[i] = py;
     z[i] = pz;
-    rec[s].x = px;
-    rec[s].y = py;
-    rec[s].z = pz;
+    // the whole 32-byte record, so no partially written sectors
+    PosT r;
+    r.x = px;
+    r.y = py;
+    r.z = pz;
+    r.t = ti;
+    r.orig = (int32_t)i;
+    rec[s] = r;
     const double dx = px - xr[i], dy = py - xr[n + i], dz = pz - xr[2 * n + i];
     if (!(dx * dx + dy * dy + dz * dz <= thr2)) atomicOr(flag, 1);
 }
@@ -150,10 +156,11 @@ __global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__
     const int32_t b = start[p.x], cnt = start[p.x + 1] - b, sb = start[p.y];
     for (int32_t m = lane; m < cnt; m += MDLJ_WAVE) {
         const char4 c = img[b + m];
-        const PosT q = rec[sb + m];
-        rec[b + m].x = q.x + (double)c.x * lx;
-        rec[b + m].y = q.y + (double)c.y * ly;
-        rec[b + m].z = q.z + (double)c.z * lz;
+        PosT q = rec[sb + m];
+        q.x += (double)c.x * lx;
+        q.y += (double)c.y * ly;
+        q.z += (double)c.z * lz;
+        rec[b + m] = q;
     }
 }
 

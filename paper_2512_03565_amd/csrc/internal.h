@@ -101,6 +101,11 @@ struct mdlj_ctx {
     int64_t n_ext = 0;            // real + halo slots
     int32_t max_cell = 0;         // most particles in one cell of the last binning
     int32_t max_nbhd = 0;         // most particles in one 27-cell neighbourhood (VL build)
+    // largest staged neighbourhood and candidate-list total of one tile in the
+    // last tiled list build, and the grid (n, trim) they belong to: sizes
+    // the next build's LDS without a pre-pass
+    int32_t tile_c_hint = 0, tile_nc_hint = 0;
+    int tile_hint_key[4] = {0, 0, 0, -1};
     int64_t nbr_cap = 0;          // Verlet list capacity per particle
     int64_t vl_max = 0;           // longest list of the last build
     int64_t vcl_cap = 0;          // cluster-pair list capacity per cluster
@@ -109,7 +114,7 @@ struct mdlj_ctx {
     DevBuf b_pos, b_type, b_force;  // caller-order state above
     DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
-        b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo;
+        b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart;
     int64_t nhalo = 0;            // entries of b_halo
     int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 

@@ -13,6 +13,8 @@
 //     forces are then summed over the segment.
 // Lists index the sorted records, halo images included, so no minimum
 // image is applied in the force loop.
+#include <string.h>
+
 #include <algorithm>
 
 #include "pair.h"
@@ -156,12 +158,66 @@ constexpr int BUILD_TB = 512;
 // last list, into entries set to index 0
 constexpr int CAND_SLACK = 2 * MDLJ_WAVE;
 
+// Candidate runs of the tiled build.  Records in a cell are ordered lower x
+// half first (hstart = first upper-half slot).  With cells at least rl + a
+// margin wide along x, a particle in the lower half of its cell cannot
+// reach the upper half of the cell to its right (and an upper-half one the
+// lower half of the cell to its left): more than one cell edge apart in x.
+// So each tile cell has two candidate lists, one per half, each nine
+// contiguous runs:  lower: [start(c-1), hstart(c+1)),  upper:
+// [hstart(c-1), end(c+1)).  Without the margin both are the full runs.
+__device__ __forceinline__ void half_runs(const int (*rs)[STAGE_K + 3],
+                                          const int (*hs)[STAGE_K + 2], int r, int c, int h,
+                                          bool trim, int &b, int &e)
+{
+    // row cells c .. c + 2 are the left neighbour, the cell and the right one
+    b = (trim && h == 1) ? hs[r][c] : rs[r][c];
+    e = (trim && h == 0) ? hs[r][c + 2] : rs[r][c + 3];
+}
+
+// Staged records and candidate-list entries of the largest tile, for the
+// LDS size of the tiled build: one thread per tile.
+__global__ void k_tile_sizes(const int32_t *__restrict__ start,
+                             const int32_t *__restrict__ hstart, Grid g, int tiles_x,
+                             int64_t ntiles, int trim, int32_t *__restrict__ out)
+{
+    const int64_t tile = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t C = 0, NC = 0;
+    if (tile < ntiles) {
+        const int tx = (int)(tile % tiles_x);
+        const int64_t rr = tile / tiles_x;
+        const int cy = (int)(rr % g.n[1]);
+        const int cz = (int)(rr / g.n[1]);
+        const int cx0 = tx * STAGE_K;
+        const int ncx = min(STAGE_K, g.n[0] - cx0);
+        for (int r = 0; r < 9; ++r) {
+            const int dy = r % 3 - 1, dz = r / 3 - 1;
+            const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
+                               (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx0 - 1 + g.h[0];
+            C += start[ej + ncx + 2] - start[ej];
+            for (int c = 0; c < ncx; ++c) {
+                NC += (trim ? hstart[ej + c + 2] : start[ej + c + 3]) - start[ej + c];
+                NC += start[ej + c + 3] - (trim ? hstart[ej + c] : start[ej + c]);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        C = max(C, __shfl_xor(C, o));
+        NC = max(NC, __shfl_xor(NC, o));
+    }
+    if ((threadIdx.x & (MDLJ_WAVE - 1)) == 0) {
+        atomic_max_rare(out, C);
+        atomic_max_rare(out + 1, NC);
+    }
+}
+
 template <bool LOCAL, bool HALF, bool ELL>
 __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     const PosT *__restrict__ rec, const int32_t *__restrict__ start,
-    const int32_t *__restrict__ ibase, Grid g, int tiles_x, double rl2, int cmax, int ccand,
-    int64_t n, int32_t cap, int32_t pad, void *__restrict__ nbr_out, int32_t *__restrict__ len,
-    int32_t *__restrict__ maxlen, int32_t *__restrict__ maxnb, int remap)
+    const int32_t *__restrict__ hstart, const int32_t *__restrict__ ibase, Grid g, int tiles_x,
+    double rl2, int trim, int cmax, int ccand, int64_t n, int32_t cap, int32_t pad,
+    void *__restrict__ nbr_out, int32_t *__restrict__ len, int32_t *__restrict__ maxlen,
+    int32_t *__restrict__ maxnb, int32_t *__restrict__ maxnc, int remap)
 {
     constexpr int NW = BUILD_TB / MDLJ_WAVE;
     constexpr int RC = STAGE_K + 3;  // cell starts per row: STAGE_K + 2 cells and the end
@@ -170,9 +226,10 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     // each record's slot and caller index in arrays of their own
     constexpr int RW = 3;
     extern __shared__ double stage[];
-    __shared__ int rs[9][RC];        // start[] of the cells of each row
-    __shared__ int seg_c[10];        // staged offset of each row
-    __shared__ int nc[STAGE_K + 1];  // offsets of the tile cells' candidate lists
+    __shared__ int rs[9][RC];            // start[] of the cells of each row
+    __shared__ int hs[9][RC - 1];        // hstart[] of the cells of each row
+    __shared__ int seg_c[10];            // staged offset of each row
+    __shared__ int nc[2 * STAGE_K + 1];  // offsets of the (tile cell, half) candidate lists
     __shared__ int wmx[NW];
     const int tid = threadIdx.x;
     const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
@@ -190,17 +247,29 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
                            (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx0 - 1 + g.h[0];
         rs[r][c] = start[ej + c];
+    } else if (tid >= MDLJ_WAVE && tid < MDLJ_WAVE + 9 * (ncx + 2)) {
+        const int q = tid - MDLJ_WAVE;
+        const int r = q / (ncx + 2), c = q % (ncx + 2);
+        const int dy = r % 3 - 1, dz = r / 3 - 1;
+        const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
+                           (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx0 - 1 + g.h[0];
+        hs[r][c] = hstart[ej + c];
     }
     const int64_t c0 = (int64_t)cx0 + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz);
     const int64_t t0 = ibase[c0];
     __syncthreads();
     if (wv == 0) {
-        // lanes 0..8: row lengths; lanes 16..16+ncx-1: candidates of tile cell c
+        // lanes 0..8: row lengths; lanes 16..16+2ncx-1: candidates of list
+        // q = 2 * (tile cell) + half
         int v = 0;
         if (lane < 9) v = rs[lane][ncx + 2] - rs[lane][0];
-        const int c = lane - 16;
-        if (c >= 0 && c < ncx)
-            for (int r = 0; r < 9; ++r) v += rs[r][c + 3] - rs[r][c];
+        const int q = lane - 16;
+        if (q >= 0 && q < 2 * ncx)
+            for (int r = 0; r < 9; ++r) {
+                int b, e;
+                half_runs(rs, hs, r, q >> 1, q & 1, trim, b, e);
+                v += e - b;
+            }
         // inclusive scans over lanes 0..15 and 16..31
         for (int o = 1; o < 16; o <<= 1) {
             const int u = __shfl_up(v, o, 16);
@@ -208,13 +277,16 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         }
         if (lane < 9) seg_c[lane + 1] = v;
         if (lane == 0) seg_c[0] = 0;
-        if (c >= 0 && c < ncx) nc[c + 1] = v;
+        if (q >= 0 && q < 2 * ncx) nc[q + 1] = v;
         if (lane == 16) nc[0] = 0;
     }
     __syncthreads();
     const int C = seg_c[9];
-    if (C > cmax || nc[ncx] > ccand) {  // block-uniform
-        if (tid == 0) atomicMax(maxnb, max(C, cmax + 1));
+    if (C > cmax || nc[2 * ncx] > ccand) {  // block-uniform: report the sizes, build nothing
+        if (tid == 0) {
+            atomicMax(maxnb, max(C, cmax + 1));
+            atomicMax(maxnc, nc[2 * ncx]);
+        }
         return;
     }
     double *srec = stage;
@@ -257,15 +329,21 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
             }
         }
     }
-    // candidate runs: tile cell c, row r -> row cells c .. c + 2
-    for (int q = wv; q < 9 * ncx; q += NW) {
-        const int c = q / 9, r = q % 9;
-        int off = nc[c];
-        for (int r2 = 0; r2 < r; ++r2) off += rs[r2][c + 3] - rs[r2][c];
-        const int b = seg_c[r] + rs[r][c] - rs[r][0], m = rs[r][c + 3] - rs[r][c];
+    // candidate runs: list q (tile cell q / 2, half q % 2), row r
+    for (int w = wv; w < 9 * 2 * ncx; w += NW) {
+        const int q = w / 9, r = w % 9;
+        int off = nc[q];
+        for (int r2 = 0; r2 < r; ++r2) {
+            int b2, e2;
+            half_runs(rs, hs, r2, q >> 1, q & 1, trim, b2, e2);
+            off += e2 - b2;
+        }
+        int rb, re;
+        half_runs(rs, hs, r, q >> 1, q & 1, trim, rb, re);
+        const int b = seg_c[r] + rb - rs[r][0], m = re - rb;
         for (int u = lane; u < m; u += MDLJ_WAVE) cand[off + u] = (uint16_t)(b + u);
     }
-    if (tid < CAND_SLACK) cand[nc[ncx] + tid] = 0;
+    if (tid < CAND_SLACK) cand[nc[2 * ncx] + tid] = 0;
     __syncthreads();
     const int ib = rs[4][1], ie = rs[4][ncx + 1];
     int32_t wmax = 0;
@@ -273,10 +351,12 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         const int own = seg_c[4] + (i - rs[4][0]);
         int c = 0;
         while (c + 1 < ncx && i >= rs[4][c + 2]) ++c;
+        // i's half of its cell (row 4, row cell c + 1)
+        const int hq = 2 * c + ((trim && i >= hs[4][c + 1]) ? 1 : 0);
         const double *di = srec + RW * own;
         const double xi = di[0], yi = di[1], zi = di[2];
         const int32_t oi = HALF ? sorig[own] : 0;
-        const int pb = nc[c], pe = nc[c + 1];
+        const int pb = nc[hq], pe = nc[hq + 1];
         const int64_t t = t0 + (i - ib);
         uint16_t *row16 = (uint16_t *)nbr_out + t * cap;
         int32_t *row32 = (int32_t *)nbr_out + (ELL ? t : t * cap);
@@ -335,6 +415,7 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         for (int w = 1; w < NW; ++w) wmax = max(wmax, wmx[w]);
         if (wmax > 0) atomic_max_rare(maxlen, wmax);
         atomic_max_rare(maxnb, C);
+        atomic_max_rare(maxnc, nc[2 * ncx]);
     }
 }
 
@@ -740,7 +821,7 @@ size_t build_tile_lds(bool local, bool half, int cmax, int ccand)
 }
 
 mdlj_status launch_build_tile(mdlj_ctx *ctx, bool local, bool half, bool ell, double rl2,
-                              int cmax, int ccand, int32_t cap)
+                              bool trim, int cmax, int ccand, int32_t cap)
 {
     const Grid &g = ctx->grid;
     const int tiles_x = (int)ceil_div(g.n[0], STAGE_K);
@@ -748,18 +829,20 @@ mdlj_status launch_build_tile(mdlj_ctx *ctx, bool local, bool half, bool ell, do
     const size_t lds = build_tile_lds(local, half, cmax, ccand);
     const PosT *rec = (const PosT *)ctx->b_sorted.p;
     const int32_t *start = (const int32_t *)ctx->b_start.p;
+    const int32_t *hstart = (const int32_t *)ctx->b_hstart.p;
     const int32_t *ibase = (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1;
     int32_t *maxlen = (int32_t *)ctx->b_flags.p + 12;
     int32_t *maxnb = (int32_t *)ctx->b_flags.p + 14;
+    int32_t *maxnc = (int32_t *)ctx->b_flags.p + 15;
     int32_t *len = (int32_t *)ctx->b_nlen.p;
     void *nbr = ctx->b_nbr.p;
     const int32_t pad = (int32_t)ctx->n_ext;
     const int64_t n = ctx->n;
     hipStream_t s = ctx->stream;
 #define VL_BT(L, H, E)                                                                          \
-    k_vl_build_tile<L, H, E><<<nbt, BUILD_TB, lds, s>>>(rec, start, ibase, g, tiles_x, rl2, cmax, \
-                                                        ccand, n, cap, pad, nbr, len, maxlen,   \
-                                                        maxnb, 1)
+    k_vl_build_tile<L, H, E><<<nbt, BUILD_TB, lds, s>>>(rec, start, hstart, ibase, g, tiles_x,   \
+                                                        rl2, trim ? 1 : 0, cmax, ccand, n, cap, \
+                                                        pad, nbr, len, maxlen, maxnb, maxnc, 1)
     if (local) {
         if (half || ell) return set_err(ctx, MDLJ_ERR_ARG, "local lists are full row-major lists");
         VL_BT(true, false, false);
@@ -830,10 +913,39 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
     const bool local = cfg.staged != 0;
     const size_t esize = local ? sizeof(uint16_t) : sizeof(int32_t);
     // LDS of the tiled build: staged records (x, y, z; slot unless local;
-    // caller index for half lists) and the tile cells' candidate lists
-    const int cmax = 9 * (STAGE_K + 2) * ctx->max_cell;
-    const int ccand = STAGE_K * 27 * ctx->max_cell;
-    bool tile_ok = ctx->max_cell > 0 &&
+    // caller index for half lists) and the candidate lists.  Sized from the
+    // maxima of the last tiled build on this grid (+1/8, the particles have
+    // moved little since), else from a pre-pass over the tiles; a tile that
+    // does not fit reports its sizes and the build is repeated with exact
+    // ones.  Candidates are trimmed by cell halves only when cells are wider
+    // than rc + skin by a margin far above rounding.
+    const bool trim = g.edge[0] >= rl + 1e-9 * ctx->box[0];
+    const int key[4] = {g.n[0], g.n[1], g.n[2], trim ? 1 : 0};
+    bool hinted = ctx->tile_c_hint > 0 && memcmp(key, ctx->tile_hint_key, sizeof key) == 0;
+    int cmax = 0, ccand = 0;
+    auto exact_sizes = [&]() -> mdlj_status {
+        int32_t *sz = (int32_t *)ctx->b_flags.p + 24;
+        const int tiles_x = (int)ceil_div(g.n[0], STAGE_K);
+        const int64_t nbt = (int64_t)tiles_x * g.n[1] * g.n[2];
+        HIPCHK(ctx, hipMemsetAsync(sz, 0, 2 * sizeof(int32_t), ctx->stream));
+        k_tile_sizes<<<ceil_div(nbt, 256), 256, 0, ctx->stream>>>(
+            (const int32_t *)ctx->b_start.p, (const int32_t *)ctx->b_hstart.p, g, tiles_x, nbt,
+            trim ? 1 : 0, sz);
+        HIPCHK(ctx, hipGetLastError());
+        int32_t h[2] = {0, 0};
+        HIPCHK(ctx, hipMemcpyAsync(h, sz, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        cmax = h[0];
+        ccand = h[1];
+        return MDLJ_OK;
+    };
+    if (hinted) {
+        cmax = ctx->tile_c_hint + ctx->tile_c_hint / 8 + 16;
+        ccand = ctx->tile_nc_hint + ctx->tile_nc_hint / 8 + 64;
+    } else {
+        STCHK(exact_sizes());
+    }
+    bool tile_ok = cmax > 0 &&
                    build_tile_lds(local, cfg.newton3 != 0, cmax, ccand) <= (size_t)STAGE_LDS_BYTES;
     // a row of the tiled build may run past its capacity before the host
     // sees it (it then rebuilds): slack of the longest possible row
@@ -847,8 +959,8 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         const int64_t st = rowmajor ? cap : 1;
         const bool tiled = tile_ok;
         if (tiled) {
-            STCHK(launch_build_tile(ctx, local, cfg.newton3 != 0, !rowmajor, rl * rl, cmax, ccand,
-                                    (int32_t)cap));
+            STCHK(launch_build_tile(ctx, local, cfg.newton3 != 0, !rowmajor, rl * rl, trim, cmax,
+                                    ccand, (int32_t)cap));
         } else if (local) {
             k_vl_build_local<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
                 (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
@@ -862,15 +974,28 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
                 (int32_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen);
         }
         HIPCHK(ctx, hipGetLastError());
-        int32_t hmax[3] = {0, 0, 0};
-        HIPCHK(ctx, hipMemcpyAsync(hmax, maxlen, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
+        int32_t hmax[4] = {0, 0, 0, 0};
+        HIPCHK(ctx, hipMemcpyAsync(hmax, maxlen, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
                                    ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        if (tiled && hmax[2] > cmax) {
-            // a tile over the staging limit built nothing: per-particle build
-            tile_ok = false;
+        if (tiled && (hmax[2] > cmax || hmax[3] > ccand)) {
+            // a tile over the sizes built nothing: exact sizes, or (if those
+            // do not fit the LDS budget) the per-particle build
+            if (hinted) {
+                hinted = false;
+                STCHK(exact_sizes());
+                tile_ok = build_tile_lds(local, cfg.newton3 != 0, cmax, ccand) <=
+                          (size_t)STAGE_LDS_BYTES;
+            } else {
+                tile_ok = false;
+            }
             --attempt;
             continue;
+        }
+        if (tiled) {
+            ctx->tile_c_hint = hmax[2];
+            ctx->tile_nc_hint = hmax[3];
+            memcpy(ctx->tile_hint_key, key, sizeof key);
         }
         ctx->vl_max = hmax[0];
         ctx->max_nbhd = hmax[2];
