@@ -41,20 +41,6 @@ __global__ void k_kick_drift(int64_t n, double *__restrict__ x, double *__restri
     z[i] += dt * uz;
 }
 
-// v += F dt / (2m)
-__global__ void k_kick(int64_t n, double *__restrict__ vx, double *__restrict__ vy,
-                       double *__restrict__ vz, const double *__restrict__ fx,
-                       const double *__restrict__ fy, const double *__restrict__ fz,
-                       const int32_t *__restrict__ type, InvMass im, double dt)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double h = 0.5 * dt * im.v[type[i]];
-    vx[i] += h * fx[i];
-    vy[i] += h * fy[i];
-    vz[i] += h * fz[i];
-}
-
 // Sorted records from current positions: rec[k] = x[orig] + image * L.
 // Padding records (orig < 0) are left as they are.
 __global__ void k_refresh(int64_t n_ext, PosT *__restrict__ rec, const char4 *__restrict__ img,

@@ -154,3 +154,39 @@ def test_velocity_verlet_fast_particles_force_early_rebuilds(m, orc, cfg):
     d -= s["box"] * np.rint(d / s["box"])
     assert np.abs(d).max() < 1e-10, cfg
     assert np.abs(v - v_ref).max() < 1e-8, cfg
+
+
+def test_vl_cells_exactly_list_range_wide(m, orc):
+    # box 16 x 1.75 = 28 = 10 x (rc + skin): cells exactly rc + skin wide, so
+    # the list build may not drop candidates by cell halves
+    pos, box = scenes.fcc_lattice(16, 16, 16, 4.0 / 1.75 ** 3, 0.05, seed=43)
+    assert abs(box[0] - 28.0) < 1e-9
+    s = dict(pos=pos, box=box, rc=2.5, eps=[1.0], sig=[1.0], types=None)
+    cfgs = [(m.NBR_VL, m.ORD_WAVE_PER_I, 16, 4, 0, 0, 1), (m.NBR_VL, m.ORD_WAVE_PER_I, 8, 8, 0, 0),
+            (m.NBR_VL, m.ORD_WAVE_PER_I, 8, 8, 0, 1), (m.NBR_VL, m.ORD_I_PER_LANE, 0, 0, 0, 0)]
+    check(m, orc, s, cfgs, "edge=rl", skin=0.3)
+
+
+def test_vl_rebuild_after_density_change_on_same_grid(m, orc):
+    # the second build runs on the same grid with 25% denser cells on one
+    # side, beyond the staging sizes remembered from the first build
+    pos, box = scenes.fcc_lattice(14, 14, 14, 0.75, 0.05, seed=44)
+    L = box[0]
+    squeezed = pos.copy()
+    x = squeezed[:, 0]
+    left = x < 0.5 * L
+    squeezed[left, 0] = 0.8 * x[left]
+    squeezed[~left, 0] = 0.4 * L + 1.2 * (x[~left] - 0.5 * L)
+    for cfg in ((m.NBR_VL, m.ORD_WAVE_PER_I, 16, 4, 0, 0, 1),
+                (m.NBR_VL, m.ORD_WAVE_PER_I, 4, 16, 0, 1)):
+        with m.System(pos, box, 2.5, skin=0.3, precision=1) as sysm:
+            sysm.set_config(cfg)
+            f, U, W = sysm.forces()
+            ref = orc.forces(pos, box, 2.5)
+            assert P.force_error(f, ref["f"]) <= 1e-12, cfg
+            sysm.set_positions(squeezed)
+            sysm.rebuild()
+            f, U, W = sysm.forces()
+            ref = orc.forces(squeezed, box, 2.5)
+            assert P.force_error(f, ref["f"]) <= 1e-12, cfg
+            assert U == pytest.approx(ref["U"], rel=1e-12), cfg
