@@ -1,0 +1,107 @@
+"""Timing tables beside the benchmark.
+
+orders: the 100,000-particle FCC scene (rho 0.75, rc 2.5, skin 0.3, lists
+rebuilt every 10 steps, FP32 pair arithmetic): every configuration of the
+search space runs --steps velocity-Verlet steps; ms per step, force-kernel
+and rebuild times from the library's events.
+
+precision: the 4,000,000-particle two-species scene (rho 0.7, rc 3.0,
+Lorentz-Berthelot): Verlet cluster lists with clusters of 4 and 8, FP32 pair
+arithmetic with FP64 accumulation against the all-FP64 kernels; force-kernel
+time over --reps evaluations.
+
+Prints one JSON line per row.
+
+    python -m paper_2512_03565_amd.orders_table orders --steps 200
+    python -m paper_2512_03565_amd.orders_table precision --reps 20
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def orders(steps):
+    import torch
+    from paper_2512_03565_amd import mdlj, scenes
+    s = scenes.config2()
+    n = len(s["pos"])
+    vel0 = scenes.mb_velocities(n, s["T"], 1.0, seed=1012)
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    with mdlj.System(pos, s["box"], s["rc"], skin=s["skin"], rebuild_every=s["rebuild_every"],
+                     stream=stream) as sysm:
+        pairs = sysm.count_pairs()
+        for cfg in sysm.configs():
+            sysm.set_positions(pos)
+            sysm.set_config(cfg)
+            vel = [torch.tensor(np.ascontiguousarray(vel0[:, k]), device="cuda") for k in range(3)]
+            sysm.step_vv(vel, s["dt"], 10)
+            torch.cuda.synchronize()
+            sysm.set_timing(True)
+            t0 = time.perf_counter()
+            sysm.step_vv(vel, s["dt"], steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            f_us, b_us, nf, nb = sysm.get_timing()
+            sysm.set_timing(False)
+            print(json.dumps({"table": "orders", "workload": "100k FCC rho0.75 rc2.5 skin0.3",
+                              "config": mdlj.config_name(cfg), "steps": steps,
+                              "ms_per_step": 1e3 * wall / steps,
+                              "mpairs_per_s": pairs * steps / wall / 1e6,
+                              "force_us": f_us / max(nf, 1),
+                              "rebuild_us": b_us / max(nb, 1), "rebuilds": nb}), flush=True)
+
+
+def precision(reps):
+    import torch
+    from paper_2512_03565_amd import mdlj, scenes
+    s = scenes.config4()
+    pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
+    types = torch.tensor(s["types"], dtype=torch.int32, device="cuda")
+    n = len(s["pos"])
+    out = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    stream = torch.cuda.current_stream()
+    names = ["VCL4/cluster-tile/4x16", "VCL4/i-per-lane", "VCL8/cluster-tile/8x8",
+             "VCL8/i-per-lane", "VCL4/cluster-tile/4x16/n3", "VL/wave-per-i/16x4",
+             "VL/wave-per-i/16x4/lds"]
+    with mdlj.System(pos, s["box"], s["rc"], s["eps"], s["sig"], types=types, skin=s["skin"],
+                     rebuild_every=1000, stream=stream) as sysm:
+        pairs = sysm.count_pairs()
+        space = {mdlj.config_name(c): c for c in sysm.configs()}
+        for name in names:
+            for prec in (mdlj.PREC_F32PAIR_F64ACC, mdlj.PREC_F64):
+                sysm.set_precision(prec)
+                try:
+                    sysm.set_config(space[name])
+                    sysm.forces(out=out, energy=False)
+                except mdlj.MdljError as e:
+                    print(json.dumps({"table": "precision", "config": name, "error": str(e)}),
+                          flush=True)
+                    break
+                sysm.set_timing(True)
+                for _ in range(reps):
+                    sysm.forces(out=out, energy=False)
+                f_us, _, nf, _ = sysm.get_timing()
+                sysm.set_timing(False)
+                us = f_us / max(nf, 1)
+                print(json.dumps({"table": "precision",
+                                  "workload": "4M two-species FCC rho0.7 rc3.0",
+                                  "config": name, "precision": "f32pair" if prec == 0 else "f64",
+                                  "force_us": us, "mpairs_per_s": pairs / us}), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("table", choices=["orders", "precision"])
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--reps", type=int, default=20)
+    a = ap.parse_args(argv)
+    orders(a.steps) if a.table == "orders" else precision(a.reps)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
