@@ -85,8 +85,9 @@ __device__ __forceinline__ PairP<T> pair_params(const LJTable<T> &t, const LdsTa
 // on the FP64 r^2.  The pair law (reciprocal, s6, force factor, energy) runs
 // in T.  The force factor is widened once and the force accumulated as
 // F += fs * d with FP64 fused multiply-adds, which on this hardware issue
-// at the FP32 rate.  Returns the force on i in (fxp, fyp, fzp) (zero when
-// masked or outside the cutoff) and whether the pair is inside the cutoff.
+// at the FP32 rate.  Returns the force on i in (fxp, fyp, fzp) (zero, up to
+// its sign, when masked or outside the cutoff) and whether the pair is
+// inside the cutoff.
 template <typename T, bool E>
 __device__ __forceinline__ bool lj_pair(double pxi, double pyi, double pzi, double pxj,
                                         double pyj, double pzj, bool valid, const PairP<T> &p,
@@ -98,12 +99,14 @@ __device__ __forceinline__ bool lj_pair(double pxi, double pyi, double pzi, doub
     const double r2d = dx * dx + dy * dy + dz * dz;
     const bool in = valid && (r2d < rc2);
     const T r2 = (T)r2d;
-    const T ir2 = rcp_t<T>(r2);
+    // outside the cutoff 1/r^2 is taken as 0, which makes s6, the force
+    // factor and the force exactly zero (one select instead of one per
+    // result, and no inf or NaN for masked self pairs)
+    const T ir2 = in ? rcp_t<T>(r2) : T(0);
     const T sr2 = p.sig2 * ir2;
     const T s6 = sr2 * sr2 * sr2;
     const T rf = p.eps24 * s6 * (T(2) * s6 - T(1));
-    const T fsT = in ? rf * ir2 : T(0);
-    const double fs = (double)fsT;
+    const double fs = (double)(rf * ir2);
     fxp = fs * dx;
     fyp = fs * dy;
     fzp = fs * dz;
