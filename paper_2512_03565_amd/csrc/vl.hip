@@ -230,6 +230,7 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     __shared__ int hs[9][RC - 1];        // hstart[] of the cells of each row
     __shared__ int seg_c[10];            // staged offset of each row
     __shared__ int nc[2 * STAGE_K + 1];  // offsets of the (tile cell, half) candidate lists
+    __shared__ int roff[2 * STAGE_K][9]; // offset of row r's run inside list q
     __shared__ int wmx[NW];
     const int tid = threadIdx.x;
     const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
@@ -268,6 +269,7 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
             for (int r = 0; r < 9; ++r) {
                 int b, e;
                 half_runs(rs, hs, r, q >> 1, q & 1, trim, b, e);
+                roff[q][r] = v;
                 v += e - b;
             }
         // inclusive scans over lanes 0..15 and 16..31
@@ -332,12 +334,7 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     // candidate runs: list q (tile cell q / 2, half q % 2), row r
     for (int w = wv; w < 9 * 2 * ncx; w += NW) {
         const int q = w / 9, r = w % 9;
-        int off = nc[q];
-        for (int r2 = 0; r2 < r; ++r2) {
-            int b2, e2;
-            half_runs(rs, hs, r2, q >> 1, q & 1, trim, b2, e2);
-            off += e2 - b2;
-        }
+        const int off = nc[q] + roff[q][r];
         int rb, re;
         half_runs(rs, hs, r, q >> 1, q & 1, trim, rb, re);
         const int b = seg_c[r] + rb - rs[r][0], m = re - rb;
