@@ -126,15 +126,33 @@ __global__ void k_kick_drift_fused(int64_t n, double *__restrict__ x, double *__
     if (!(dx * dx + dy * dy + dz * dz <= thr2)) atomicOr(flag, 1);
 }
 
+// The displacement flag of the last integrator step goes to the host word
+// (system scope, so the host sees it once the kernel has finished) and is
+// cleared for the next step.  The integrator kernel that set it has
+// finished: it ran before on the same stream.
+__device__ __forceinline__ void publish_flag(int32_t *flag, int32_t *host)
+{
+    const int32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(host, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_publish_flag(int32_t *flag, int32_t *host)
+{
+    if (threadIdx.x == 0) publish_flag(flag, host);
+}
+
 // Halo records from their source records, one wavefront per halo cell:
 // rec = source + image * L (the same sum the full refresh forms from the
-// caller-order positions).  hl holds (halo cell, source cell) pairs.
+// caller-order positions).  hl holds (halo cell, source cell) pairs.  The
+// first thread also publishes the displacement flag.
 __global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__restrict__ hl,
                                                       const int32_t *__restrict__ start,
                                                       const char4 *__restrict__ img,
                                                       PosT *__restrict__ rec, double lx, double ly,
-                                                      double lz)
+                                                      double lz, int32_t *flag, int32_t *host)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish_flag(flag, host);
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
     const int lane = threadIdx.x & (MDLJ_WAVE - 1);
     if (w >= nh) return;
@@ -198,23 +216,32 @@ mdlj_status save_reference(mdlj_ctx *ctx)
     return MDLJ_OK;
 }
 
+static mdlj_status ensure_host_flag(mdlj_ctx *ctx)
+{
+    if (ctx->h_flag) return MDLJ_OK;
+    // coherent: the kernel's store reaches host memory without a cache
+    // write-back
+    HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocCoherent));
+    HIPCHK(ctx, hipHostGetDevicePointer((void **)&ctx->d_hflag, ctx->h_flag, 0));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_flag, hipEventDisableTiming));
+    return MDLJ_OK;
+}
+
 mdlj_status launch_displacement_check(mdlj_ctx *ctx)
 {
     const int64_t n = ctx->n;
-    if (!ctx->h_flag) {
-        HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocDefault));
-        HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_flag, hipEventDisableTiming));
-    }
+    STCHK(ensure_host_flag(ctx));
     int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
-    HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+    if (!ctx->dflag_zero) HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
     const double h = 0.5 * ctx->skin;
     k_displacement<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z,
                                                              (const double *)ctx->b_xref.p, h * h,
                                                              flag);
     HIPCHK(ctx, hipGetLastError());
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_flag, flag, sizeof(int32_t), hipMemcpyDeviceToHost,
-                               ctx->stream));
+    k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag);
+    HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev_flag, ctx->stream));
+    ctx->dflag_zero = true;
     return MDLJ_OK;
 }
 
@@ -234,16 +261,17 @@ mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far)
 mdlj_status finish_fused_upkeep(mdlj_ctx *ctx)
 {
     int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_flag, flag, sizeof(int32_t), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPCHK(ctx, hipEventRecord(ctx->ev_flag, ctx->stream));
     if (ctx->nhalo > 0) {
         k_refresh_halo<<<ceil_div(ctx->nhalo, 4), 256, 0, ctx->stream>>>(
             ctx->nhalo, (const int2 *)ctx->b_halo.p, (const int32_t *)ctx->b_start.p,
             (const char4 *)ctx->b_img.p, (PosT *)ctx->b_sorted.p, ctx->box[0], ctx->box[1],
-            ctx->box[2]);
-        HIPCHK(ctx, hipGetLastError());
+            ctx->box[2], flag, ctx->d_hflag);
+    } else {
+        k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag);
     }
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipEventRecord(ctx->ev_flag, ctx->stream));
+    ctx->dflag_zero = true;
     return MDLJ_OK;
 }
 
@@ -324,7 +352,8 @@ mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double d
         if (s + 1 < nsteps && fuse) {
             int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
             const double h = 0.5 * ctx->skin;
-            HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+            if (!ctx->dflag_zero) HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+            ctx->dflag_zero = false;
             k_kick_drift_fused<<<nb, TB, 0, ctx->stream>>>(
                 n, ctx->x, ctx->y, ctx->z, vx, vy, vz, fo.fx, fo.fy, fo.fz, slot_of, ctx->type, im,
                 dt, (PosT *)ctx->b_sorted.p, (const double *)ctx->b_xref.p, h * h, flag);

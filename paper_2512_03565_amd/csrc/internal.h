@@ -143,9 +143,13 @@ struct mdlj_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<Timed> ev_pending;
-    // displacement check result (pinned host memory) and its event
+    // displacement check result (pinned host memory, d_hflag its device
+    // address) and its event; dflag_zero: the device-side flag is known to
+    // hold 0
     int32_t *h_flag = nullptr;
+    int32_t *d_hflag = nullptr;
     hipEvent_t ev_flag = nullptr;
+    bool dflag_zero = false;
     double t_force_us = 0, t_build_us = 0;
     int64_t t_nforce = 0, t_nbuild = 0;
     double last_force_us = 0, last_build_us = 0;
@@ -197,8 +201,9 @@ mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far);
 mdlj_status launch_displacement_check(mdlj_ctx *ctx);
 mdlj_status check_result(mdlj_ctx *ctx, bool *too_far);
 mdlj_status refresh_records(mdlj_ctx *ctx);
-// After a fused integrator step: copy the displacement flag to the host
-// (behind ctx->ev_flag) and refresh the halo records from their sources.
+// After a fused integrator step: refresh the halo records from their
+// sources; the same kernel hands the displacement flag to the host (behind
+// ctx->ev_flag) and clears it for the next step.
 mdlj_status finish_fused_upkeep(mdlj_ctx *ctx);
 // (halo cell, source cell) pairs of the current grid, for the halo refresh.
 mdlj_status build_halo_list(mdlj_ctx *ctx);

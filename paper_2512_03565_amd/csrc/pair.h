@@ -105,7 +105,10 @@ __device__ __forceinline__ bool lj_pair(double pxi, double pyi, double pzi, doub
     const T ir2 = in ? rcp_t<T>(r2) : T(0);
     const T sr2 = p.sig2 * ir2;
     const T s6 = sr2 * sr2 * sr2;
-    const T rf = p.eps24 * s6 * (T(2) * s6 - T(1));
+    // 24 eps s6 (2 s6 - 1) as s6 (48 eps s6 - 24 eps): one fused multiply-add
+    // and one product (48 eps = eps24 + eps24 is exact, and loop-invariant
+    // for one species)
+    const T rf = s6 * (((p.eps24 + p.eps24) * s6) - p.eps24);
     const double fs = (double)(rf * ir2);
     fxp = fs * dx;
     fyp = fs * dy;

@@ -13,6 +13,7 @@
 //     forces are then summed over the segment.
 // Lists index the sorted records, halo images included, so no minimum
 // image is applied in the force loop.
+#include <limits.h>
 #include <string.h>
 
 #include <algorithm>
@@ -211,6 +212,13 @@ __global__ void k_tile_sizes(const int32_t *__restrict__ start,
     }
 }
 
+// the tiled build's set-up: cell starts of the nine rows by threads
+// 0 .. 9 (STAGE_K + 3) - 1, half starts by the third wavefront on, and the
+// (cell, half) list offsets scanned over 16 lanes of the first wavefront
+static_assert(9 * (STAGE_K + 3) <= 2 * MDLJ_WAVE, "tile too wide for the set-up");
+static_assert(2 * MDLJ_WAVE + 9 * (STAGE_K + 2) <= BUILD_TB, "tile too wide for the set-up");
+static_assert(2 * STAGE_K <= 16, "tile too wide for the set-up");
+
 template <bool LOCAL, bool HALF, bool ELL>
 __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     const PosT *__restrict__ rec, const int32_t *__restrict__ start,
@@ -248,8 +256,8 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
                            (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx0 - 1 + g.h[0];
         rs[r][c] = start[ej + c];
-    } else if (tid >= MDLJ_WAVE && tid < MDLJ_WAVE + 9 * (ncx + 2)) {
-        const int q = tid - MDLJ_WAVE;
+    } else if (tid >= 2 * MDLJ_WAVE && tid < 2 * MDLJ_WAVE + 9 * (ncx + 2)) {
+        const int q = tid - 2 * MDLJ_WAVE;
         const int r = q / (ncx + 2), c = q % (ncx + 2);
         const int dy = r % 3 - 1, dz = r / 3 - 1;
         const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
@@ -343,11 +351,17 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     if (tid < CAND_SLACK) cand[nc[2 * ncx] + tid] = 0;
     __syncthreads();
     const int ib = rs[4][1], ie = rs[4][ncx + 1];
+    // starts of tile cells 1 .. STAGE_K - 1 (row 4, row cells 2 ..), for a
+    // branch-free search of i's cell
+    int cs[STAGE_K - 1];
+#pragma unroll
+    for (int q = 0; q < STAGE_K - 1; ++q) cs[q] = q + 1 < ncx ? rs[4][q + 2] : INT_MAX;
     int32_t wmax = 0;
     for (int i = ib + wv; i < ie; i += NW) {
         const int own = seg_c[4] + (i - rs[4][0]);
         int c = 0;
-        while (c + 1 < ncx && i >= rs[4][c + 2]) ++c;
+#pragma unroll
+        for (int q = 0; q < STAGE_K - 1; ++q) c += i >= cs[q];
         // i's half of its cell (row 4, row cell c + 1)
         const int hq = 2 * c + ((trim && i >= hs[4][c + 1]) ? 1 : 0);
         const double *di = srec + RW * own;
@@ -396,8 +410,10 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
             }
             cnt += na + (uint32_t)__builtin_popcountll(mb);
         }
+        // padding up to a multiple of 8 entries: at most 7, one per lane
         const int32_t pe8 = min((int32_t)((cnt + 7) & ~7u), cap);
-        for (int32_t q = (int32_t)cnt + lane; q < pe8; q += MDLJ_WAVE) {
+        const int32_t q = (int32_t)cnt + lane;
+        if (q < pe8) {
             if (LOCAL)
                 row16[q] = (uint16_t)C;
             else
@@ -423,18 +439,44 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
 // or 4-byte load) and the j-particles from LDS.
 constexpr int VL_LDS_TB = 256;
 
-// V list entries (16-bit) of a row from entry k0 (a multiple of V): one
-// 16-, 8- or 4-byte load, entries in the low halves first.
+// V list entries (16-bit) at byte offset vo of the tile's list rows: one
+// 16-, 8- or 4-byte buffer load, entries in the low halves first.  The
+// resource's range check returns zeros for reads past the end of the list
+// array, so the prefetch of trips beyond a row needs no clamp.
 template <int V>
-__device__ __forceinline__ uint4 list_words(const uint16_t *row, int32_t k0)
+__device__ __forceinline__ uint4 list_words(__amdgpu_buffer_rsrc_t r, uint32_t vo)
 {
-    if (V == 8) return ((const uint4 *)row)[k0 >> 3];
-    if (V == 4) {
-        const uint2 q = ((const uint2 *)row)[k0 >> 2];
-        return make_uint4(q.x, q.y, 0u, 0u);
+    if (V == 8) {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, vo, 0, 0);
+        return make_uint4(q[0], q[1], q[2], q[3]);
     }
-    return make_uint4(((const uint32_t *)row)[k0 >> 1], 0u, 0u, 0u);
+    if (V == 4) {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b64(r, vo, 0, 0);
+        return make_uint4(q[0], q[1], 0u, 0u);
+    }
+    return make_uint4(__builtin_amdgcn_raw_buffer_load_b32(r, vo, 0, 0), 0u, 0u, 0u);
 }
+
+// Word 3 of a raw buffer resource on this architecture (32-bit dwords,
+// range-checked against num_records bytes).
+constexpr int BUF_RSRC_W3 = 0x00020000;
+
+// base + S * (low or high 16 bits of w) in one v_mad_u32_u16: the LDS
+// address of a staged record (S = 24) or of its species (S = 4) straight
+// from a packed pair of 16-bit list entries.
+template <bool HI, int S>
+__device__ __forceinline__ uint32_t mad16(uint32_t w, uint32_t base)
+{
+    uint32_t a;
+    if (HI)
+        asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(a) : "v"(w), "i"(S), "v"(base));
+    else
+        asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(a) : "v"(w), "i"(S), "v"(base));
+    return a;
+}
+
+typedef __attribute__((address_space(3))) const double lds_cdouble;
+typedef __attribute__((address_space(3))) const int lds_cint;
 
 template <typename T, bool E, bool MS, int G, int V>
 __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ rec,
@@ -478,24 +520,27 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
     const int64_t c0 = (int64_t)cx0 + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz);
     const int64_t t0 = ibase[c0];
     const int l = lane % SEG;
+    // list rows of the tile's particles (t0 onwards) through one buffer
+    // resource; lane offsets in bytes
+    const __amdgpu_buffer_rsrc_t lr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(nbr + min(t0, n - 1) * cap), (short)0,
+        (int)min((n - min(t0, n - 1)) * cap * 2, (int64_t)0x7fffffff), BUF_RSRC_W3);
     // The first i-group of this wavefront: its records, list lengths and the
     // first two trips of list entries are requested before the staging, so
     // their latency overlaps it.  The loads are unconditional (a branch
     // around a load makes the compiler wait for it at the merge): inactive
-    // lanes read row n - 1, and trip starts are clamped to cap - V, which
-    // keeps every read inside its row (cap is a multiple of 8); what those
-    // reads return is never used.
+    // lanes read the tile's first row and list length; what those reads
+    // return is never used.
     int i0 = ib + wv * G;
     int i = i0 + lane / SEG;
     bool act = i < ie;
     int64_t t = t0 + (act ? i - ib : 0);
     PosT pi = rec[act ? i : ib];
-    const int64_t tr = min(t, n - 1);
-    int32_t L = len[tr];
+    int32_t L = len[min(t, n - 1)];
     L = act ? L : 0;
-    const uint16_t *row = nbr + tr * cap;
-    uint4 wa = list_words<V>(row, min(V * l, cap - V));
-    uint4 wb = list_words<V>(row, min(V * l + KS, cap - V));
+    uint32_t vo = (uint32_t)(((t - t0) * cap + V * l) * 2);
+    uint4 wa = list_words<V>(lr, vo);
+    uint4 wb = list_words<V>(lr, vo + 2 * KS);
     __syncthreads();
     if (tid == 0) {
         seg_c[0] = 0;
@@ -513,6 +558,9 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
         if (MS) st[C] = 0;
     }
     __syncthreads();
+    // LDS byte addresses of the staged coordinates and species
+    const uint32_t xb = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) double *)sp;
+    const uint32_t tb = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) int *)st;
     double bu = 0.0, bw = 0.0;
     for (bool first = true; i0 < ie; i0 += NW * G, first = false) {
         if (!first) {
@@ -520,12 +568,11 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
             act = i < ie;
             t = t0 + (act ? i - ib : 0);
             pi = rec[act ? i : ib];
-            const int64_t tq = min(t, n - 1);
-            L = len[tq];
+            L = len[min(t, n - 1)];
             L = act ? L : 0;
-            row = nbr + tq * cap;
-            wa = list_words<V>(row, min(V * l, cap - V));
-            wb = list_words<V>(row, min(V * l + KS, cap - V));
+            vo = (uint32_t)(((t - t0) * cap + V * l) * 2);
+            wa = list_words<V>(lr, vo);
+            wb = list_words<V>(lr, vo + 2 * KS);
         }
         Acc a;
         acc_zero(a);
@@ -533,22 +580,29 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
             const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
             for (int u = 0; u < V; ++u) {
-                const int k = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
-                const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, MS ? st[k] : 0);
+                const uint32_t ad = (u & 1) ? mad16<true, 24>(w[u >> 1], xb)
+                                            : mad16<false, 24>(w[u >> 1], xb);
+                int tj = 0;
+                if (MS) {
+                    const uint32_t at = (u & 1) ? mad16<true, 4>(w[u >> 1], tb)
+                                                : mad16<false, 4>(w[u >> 1], tb);
+                    tj = *(lds_cint *)(uintptr_t)at;
+                }
+                const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, tj);
                 double fxp, fyp, fzp;
-                const double *q = sp + 3 * k;
+                lds_cdouble *q = (lds_cdouble *)(uintptr_t)ad;
                 lj_pair<T, E>(pi.x, pi.y, pi.z, q[0], q[1], q[2], true, p, rc2, a, fxp, fyp, fzp);
             }
         };
-        // two trips in flight, alternating between two registers (no copy
-        // between them, so a load is only waited for when its trip runs)
-        for (int32_t k0 = V * l; k0 < L; k0 += 2 * KS) {
+        // two trips in flight.  Both reloads are unconditional, so every
+        // path through the loop issues the same loads in the same order and
+        // each wait covers only the load its trip needs (a load inside the
+        // branch would make the loop head wait for all of them).
+        for (int32_t k0 = V * l; k0 < L; k0 += 2 * KS, vo += 4 * KS) {
             trip(wa);
-            wa = list_words<V>(row, min(k0 + 2 * KS, cap - V));
-            if (k0 + KS < L) {
-                trip(wb);
-                wb = list_words<V>(row, min(k0 + 3 * KS, cap - V));
-            }
+            wa = list_words<V>(lr, vo + 4 * KS);
+            if (k0 + KS < L) trip(wb);
+            wb = list_words<V>(lr, vo + 6 * KS);
         }
         a.fx = seg_sum(a.fx, SEG);
         a.fy = seg_sum(a.fy, SEG);
