@@ -184,6 +184,8 @@ static void invalidate(mdlj_ctx *ctx)
 // (Re)build the neighbour structure of configuration c.
 static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
 {
+    // binning reads the caller-order positions
+    STCHK(leave_sorted(ctx));
     STCHK(check_geometry(ctx, c));
     if (c.nbr_algo == MDLJ_NBR_VCL) {
         STCHK(vcl_build(ctx, c));
@@ -489,7 +491,8 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
                       &ctx->b_cpair,   &ctx->b_cstart,  &ctx->b_fold,
                       &ctx->b_pos,     &ctx->b_type,    &ctx->b_force,
                       &ctx->b_cnt_ext, &ctx->b_img,     &ctx->b_icnt,    &ctx->b_ilist,
-                      &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo,    &ctx->b_hstart};
+                      &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo,    &ctx->b_hstart,
+                      &ctx->b_vsort,   &ctx->b_xrsort};
     for (DevBuf *b : bufs) free_buf(*b);
     delete ctx;
     return MDLJ_OK;

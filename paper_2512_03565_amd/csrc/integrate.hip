@@ -85,45 +85,78 @@ __global__ void k_kick_drift_sorted(int64_t n, double *__restrict__ x, double *_
     z[i] += dt * uz;
 }
 
-// The same step for Verlet lists between rebuilds, with the list upkeep of
-// the next force call folded in: the new position also goes to the
-// particle's sorted record, and a particle that has now moved more than
-// sqrt(thr2) since the list build sets *flag.
-__global__ void k_kick_drift_fused(int64_t n, double *__restrict__ x, double *__restrict__ y,
-                                   double *__restrict__ z, double *__restrict__ vx,
-                                   double *__restrict__ vy, double *__restrict__ vz,
-                                   const double *__restrict__ fx, const double *__restrict__ fy,
-                                   const double *__restrict__ fz,
-                                   const int32_t *__restrict__ slot_of,
-                                   const int32_t *__restrict__ type, InvMass im, double dt,
-                                   PosT *__restrict__ rec, const double *__restrict__ xr,
-                                   double thr2, int32_t *__restrict__ flag)
+// The same step for Verlet lists between rebuilds, in sorted order: thread
+// t takes the t-th interior record (ilist), its sorted force and its
+// velocity and list-build reference position by compact index, so every
+// access is coalesced.  The new position goes to the record (the list
+// upkeep of the next force call), and a particle that has now moved more
+// than sqrt(thr2) since the list build sets *flag.  Same arithmetic as
+// k_kick_drift_sorted.
+__global__ void k_kick_drift_compact(int64_t n, const int32_t *__restrict__ ilist,
+                                     PosT *__restrict__ rec, double *__restrict__ vs,
+                                     const double *__restrict__ fx,
+                                     const double *__restrict__ fy,
+                                     const double *__restrict__ fz, InvMass im, double dt,
+                                     const double *__restrict__ xrs, double thr2,
+                                     int32_t *__restrict__ flag)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t s = slot_of[i];
-    const int32_t ti = type[i];
-    const double h = 0.5 * dt * im.v[ti];
-    const double ux = (vx[i] + h * fx[s]) + h * fx[s];
-    const double uy = (vy[i] + h * fy[s]) + h * fy[s];
-    const double uz = (vz[i] + h * fz[s]) + h * fz[s];
-    vx[i] = ux;
-    vy[i] = uy;
-    vz[i] = uz;
-    const double px = x[i] + dt * ux, py = y[i] + dt * uy, pz = z[i] + dt * uz;
-    x[i] = px;
-    y[i] = py;
-    z[i] = pz;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t s = ilist[t];
+    PosT r = rec[s];
+    const double h = 0.5 * dt * im.v[r.t];
+    const double ux = (vs[t] + h * fx[s]) + h * fx[s];
+    const double uy = (vs[n + t] + h * fy[s]) + h * fy[s];
+    const double uz = (vs[2 * n + t] + h * fz[s]) + h * fz[s];
+    vs[t] = ux;
+    vs[n + t] = uy;
+    vs[2 * n + t] = uz;
+    r.x += dt * ux;
+    r.y += dt * uy;
+    r.z += dt * uz;
     // the whole 32-byte record, so no partially written sectors
-    PosT r;
-    r.x = px;
-    r.y = py;
-    r.z = pz;
-    r.t = ti;
-    r.orig = (int32_t)i;
     rec[s] = r;
-    const double dx = px - xr[i], dy = py - xr[n + i], dz = pz - xr[2 * n + i];
+    const double dx = r.x - xrs[t], dy = r.y - xrs[n + t], dz = r.z - xrs[2 * n + t];
     if (!(dx * dx + dy * dy + dz * dz <= thr2)) atomicOr(flag, 1);
+}
+
+// Into sorted order: velocities and list-build reference positions of the
+// interior records by compact index.
+__global__ void k_enter_sorted(int64_t n, const int32_t *__restrict__ ilist,
+                               const PosT *__restrict__ rec, const double *__restrict__ vx,
+                               const double *__restrict__ vy, const double *__restrict__ vz,
+                               const double *__restrict__ xr, double *__restrict__ vs,
+                               double *__restrict__ xrs)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t o = rec[ilist[t]].orig;
+    vs[t] = vx[o];
+    vs[n + t] = vy[o];
+    vs[2 * n + t] = vz[o];
+    xrs[t] = xr[o];
+    xrs[n + t] = xr[n + o];
+    xrs[2 * n + t] = xr[2 * n + o];
+}
+
+// Back to caller order: positions from the interior records, velocities
+// from their compact-index copies.
+__global__ void k_leave_sorted(int64_t n, const int32_t *__restrict__ ilist,
+                               const PosT *__restrict__ rec, const double *__restrict__ vs,
+                               double *__restrict__ x, double *__restrict__ y,
+                               double *__restrict__ z, double *__restrict__ vx,
+                               double *__restrict__ vy, double *__restrict__ vz)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const PosT r = rec[ilist[t]];
+    const int32_t o = r.orig;
+    x[o] = r.x;
+    y[o] = r.y;
+    z[o] = r.z;
+    vx[o] = vs[t];
+    vy[o] = vs[n + t];
+    vz[o] = vs[2 * n + t];
 }
 
 // The displacement flag of the last integrator step goes to the host word
@@ -324,7 +357,50 @@ static InvMass inv_mass(const mdlj_ctx *ctx)
     return im;
 }
 
+static mdlj_status enter_sorted(mdlj_ctx *ctx)
+{
+    const int64_t n = ctx->n;
+    STCHK(ensure(ctx, ctx->b_vsort, sizeof(double) * 3 * n));
+    STCHK(ensure(ctx, ctx->b_xrsort, sizeof(double) * 3 * n));
+    k_enter_sorted<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
+        n, (const int32_t *)ctx->b_ilist.p, (const PosT *)ctx->b_sorted.p, ctx->vv_v[0],
+        ctx->vv_v[1], ctx->vv_v[2], (const double *)ctx->b_xref.p, (double *)ctx->b_vsort.p,
+        (double *)ctx->b_xrsort.p);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->sorted_active = true;
+    return MDLJ_OK;
+}
+
+mdlj_status leave_sorted(mdlj_ctx *ctx)
+{
+    if (!ctx->sorted_active) return MDLJ_OK;
+    ctx->sorted_active = false;
+    const int64_t n = ctx->n;
+    k_leave_sorted<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
+        n, (const int32_t *)ctx->b_ilist.p, (const PosT *)ctx->b_sorted.p,
+        (const double *)ctx->b_vsort.p, ctx->x, ctx->y, ctx->z, ctx->vv_v[0], ctx->vv_v[1],
+        ctx->vv_v[2]);
+    HIPCHK(ctx, hipGetLastError());
+    return MDLJ_OK;
+}
+
+static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt,
+                           int nsteps);
+
 mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt, int nsteps)
+{
+    ctx->vv_v[0] = vx;
+    ctx->vv_v[1] = vy;
+    ctx->vv_v[2] = vz;
+    const mdlj_status st = vv_loop(ctx, vx, vy, vz, dt, nsteps);
+    // on an error mid-loop the caller-order state is still made whole
+    const mdlj_status st2 = leave_sorted(ctx);
+    ctx->vv_v[0] = ctx->vv_v[1] = ctx->vv_v[2] = nullptr;
+    return st != MDLJ_OK ? st : st2;
+}
+
+static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt,
+                           int nsteps)
 {
     const int64_t n = ctx->n;
     const InvMass im = inv_mass(ctx);
@@ -350,15 +426,21 @@ mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double d
                           ctx->steps_since_build < ctx->rebuild_every && ctx->h_flag &&
                           ctx->b_xref.bytes >= sizeof(double) * 3 * n;
         if (s + 1 < nsteps && fuse) {
+            if (!ctx->sorted_active) STCHK(enter_sorted(ctx));
             int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
             const double h = 0.5 * ctx->skin;
             if (!ctx->dflag_zero) HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
             ctx->dflag_zero = false;
-            k_kick_drift_fused<<<nb, TB, 0, ctx->stream>>>(
-                n, ctx->x, ctx->y, ctx->z, vx, vy, vz, fo.fx, fo.fy, fo.fz, slot_of, ctx->type, im,
-                dt, (PosT *)ctx->b_sorted.p, (const double *)ctx->b_xref.p, h * h, flag);
+            k_kick_drift_compact<<<nb, TB, 0, ctx->stream>>>(
+                n, (const int32_t *)ctx->b_ilist.p, (PosT *)ctx->b_sorted.p,
+                (double *)ctx->b_vsort.p, fo.fx, fo.fy, fo.fz, im, dt,
+                (const double *)ctx->b_xrsort.p, h * h, flag);
             ctx->upkeep_fused = true;
-        } else if (s + 1 < nsteps) {
+            HIPCHK(ctx, hipGetLastError());
+            continue;
+        }
+        STCHK(leave_sorted(ctx));
+        if (s + 1 < nsteps) {
             k_kick_drift_sorted<<<nb, TB, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z, vx, vy, vz,
                                                             fo.fx, fo.fy, fo.fz, slot_of,
                                                             ctx->type, im, dt);

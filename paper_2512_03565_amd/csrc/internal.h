@@ -90,6 +90,14 @@ struct mdlj_ctx {
     // the integrator already wrote the interior sorted records and the skin/2
     // displacement flag for the current positions (Verlet lists only)
     bool upkeep_fused = false;
+    // Between Verlet-list rebuilds the integrator keeps its state in sorted
+    // order: positions in the interior sorted records, velocities and the
+    // list-build reference positions by compact sorted index (b_vsort,
+    // b_xrsort, SoA).  While sorted_active the caller-order positions and
+    // the velocity arrays of the running step call (vv_v) are behind; they
+    // are written back before a rebuild and when the call returns.
+    bool sorted_active = false;
+    double *vv_v[3] = {nullptr, nullptr, nullptr};
 
     // neighbour structure state
     bool built = false;           // structure matches cfg/positions
@@ -114,7 +122,8 @@ struct mdlj_ctx {
     DevBuf b_pos, b_type, b_force;  // caller-order state above
     DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
-        b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart;
+        b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart, b_vsort,
+        b_xrsort;
     int64_t nhalo = 0;            // entries of b_halo
     int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 
@@ -208,6 +217,9 @@ mdlj_status finish_fused_upkeep(mdlj_ctx *ctx);
 // (halo cell, source cell) pairs of the current grid, for the halo refresh.
 mdlj_status build_halo_list(mdlj_ctx *ctx);
 mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt, int nsteps);
+// Write the sorted-order integrator state back to the caller-order
+// positions and velocities (no-op unless ctx->sorted_active).
+mdlj_status leave_sorted(mdlj_ctx *ctx);
 
 // --- force evaluation (api.cpp) ---------------------------------------------
 // Bring the neighbour structure of c up to date for the current positions.
