@@ -203,6 +203,7 @@ static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
         }
     }
     if (c.nbr_algo != MDLJ_NBR_LC) STCHK(save_reference(ctx));
+    ctx->rec_at_build = c.nbr_algo == MDLJ_NBR_VL;
     ctx->built = true;
     ctx->built_cfg = c;
     ctx->steps_since_build = 0;

@@ -121,22 +121,24 @@ __global__ void k_kick_drift_compact(int64_t n, const int32_t *__restrict__ ilis
 }
 
 // Into sorted order: velocities and list-build reference positions of the
-// interior records by compact index.
+// interior records by compact index.  from_rec: the records still hold the
+// build positions, which then serve as the reference (no gather).
 __global__ void k_enter_sorted(int64_t n, const int32_t *__restrict__ ilist,
                                const PosT *__restrict__ rec, const double *__restrict__ vx,
                                const double *__restrict__ vy, const double *__restrict__ vz,
-                               const double *__restrict__ xr, double *__restrict__ vs,
-                               double *__restrict__ xrs)
+                               const double *__restrict__ xr, int from_rec,
+                               double *__restrict__ vs, double *__restrict__ xrs)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const int32_t o = rec[ilist[t]].orig;
+    const PosT r = rec[ilist[t]];
+    const int32_t o = r.orig;
     vs[t] = vx[o];
     vs[n + t] = vy[o];
     vs[2 * n + t] = vz[o];
-    xrs[t] = xr[o];
-    xrs[n + t] = xr[n + o];
-    xrs[2 * n + t] = xr[2 * n + o];
+    xrs[t] = from_rec ? r.x : xr[o];
+    xrs[n + t] = from_rec ? r.y : xr[n + o];
+    xrs[2 * n + t] = from_rec ? r.z : xr[2 * n + o];
 }
 
 // Back to caller order: positions from the interior records, velocities
@@ -343,6 +345,7 @@ mdlj_status build_halo_list(mdlj_ctx *ctx)
 
 mdlj_status refresh_records(mdlj_ctx *ctx)
 {
+    ctx->rec_at_build = false;
     k_refresh<<<ceil_div(ctx->n_ext, 256), 256, 0, ctx->stream>>>(
         ctx->n_ext, (PosT *)ctx->b_sorted.p, (const char4 *)ctx->b_img.p, ctx->x, ctx->y, ctx->z,
         ctx->box[0], ctx->box[1], ctx->box[2]);
@@ -364,8 +367,8 @@ static mdlj_status enter_sorted(mdlj_ctx *ctx)
     STCHK(ensure(ctx, ctx->b_xrsort, sizeof(double) * 3 * n));
     k_enter_sorted<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
         n, (const int32_t *)ctx->b_ilist.p, (const PosT *)ctx->b_sorted.p, ctx->vv_v[0],
-        ctx->vv_v[1], ctx->vv_v[2], (const double *)ctx->b_xref.p, (double *)ctx->b_vsort.p,
-        (double *)ctx->b_xrsort.p);
+        ctx->vv_v[1], ctx->vv_v[2], (const double *)ctx->b_xref.p, ctx->rec_at_build ? 1 : 0,
+        (double *)ctx->b_vsort.p, (double *)ctx->b_xrsort.p);
     HIPCHK(ctx, hipGetLastError());
     ctx->sorted_active = true;
     return MDLJ_OK;
@@ -436,6 +439,7 @@ static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, do
                 (double *)ctx->b_vsort.p, fo.fx, fo.fy, fo.fz, im, dt,
                 (const double *)ctx->b_xrsort.p, h * h, flag);
             ctx->upkeep_fused = true;
+            ctx->rec_at_build = false;
             HIPCHK(ctx, hipGetLastError());
             continue;
         }

@@ -98,6 +98,9 @@ struct mdlj_ctx {
     // are written back before a rebuild and when the call returns.
     bool sorted_active = false;
     double *vv_v[3] = {nullptr, nullptr, nullptr};
+    // the interior sorted records still hold the positions of the last list
+    // build (equal to the saved reference positions)
+    bool rec_at_build = false;
 
     // neighbour structure state
     bool built = false;           // structure matches cfg/positions
