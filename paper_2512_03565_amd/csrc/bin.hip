@@ -385,6 +385,18 @@ __global__ void k_int_counts(Grid g, const int32_t *__restrict__ count, int32_t 
     icnt[c] = count[e];
 }
 
+// host[0] = non-finite flag, host[1] = records with halo images,
+// host[2] = largest cell occupancy (system-scope stores to pinned memory)
+__global__ void k_publish_bin(const int32_t *__restrict__ flags, const int32_t *__restrict__ total,
+                              int32_t *host)
+{
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(host, flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(host + 1, *total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(host + 2, flags[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 __global__ void k_ilist(Grid g, const int32_t *__restrict__ start, const int32_t *__restrict__ ibase,
                         int32_t *__restrict__ ilist)
 {
@@ -497,12 +509,13 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     HIPCHK(ctx, hipGetLastError());
     STCHK(exclusive_scan(ctx, (const int32_t *)ctx->b_cnt_ext.p, start, g.ncell_ext));
     HIPCHK(ctx, hipGetLastError());
-    int32_t host[3] = {0, 0, 0};
-    HIPCHK(ctx, hipMemcpyAsync(&host[0], flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipMemcpyAsync(&host[2], flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipMemcpyAsync(&host[1], start + g.ncell_ext, sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
+    // non-finite flag, record total and largest occupancy to the host in
+    // one small kernel
+    STCHK(ensure_host_flag(ctx));
+    k_publish_bin<<<1, 64, 0, s>>>(flags, start + g.ncell_ext, ctx->d_hflag + 4);
+    HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
+    const int32_t host[3] = {ctx->h_flag[4], ctx->h_flag[5], ctx->h_flag[6]};
     if (host[0]) return set_err(ctx, MDLJ_ERR_NONFINITE, "non-finite particle position");
     const int64_t n_ext = host[1];
     if (n_ext < n) return set_err(ctx, MDLJ_ERR_HIP, "binning lost particles");

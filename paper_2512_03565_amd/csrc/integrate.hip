@@ -120,6 +120,47 @@ __global__ void k_kick_drift_compact(int64_t n, const int32_t *__restrict__ ilis
     if (!(dx * dx + dy * dy + dz * dz <= thr2)) atomicOr(flag, 1);
 }
 
+// The step before a list rebuild, from the sorted-order state: the same
+// kick and drift as k_kick_drift_compact, with positions and velocities
+// written straight to caller order (the rebuild bins from there) instead of
+// to the records.
+__global__ void k_kick_leave(int64_t n, const int32_t *__restrict__ ilist,
+                             const PosT *__restrict__ rec, const double *__restrict__ vs,
+                             const double *__restrict__ fx, const double *__restrict__ fy,
+                             const double *__restrict__ fz, InvMass im, double dt,
+                             double *__restrict__ x, double *__restrict__ y,
+                             double *__restrict__ z, double *__restrict__ vx,
+                             double *__restrict__ vy, double *__restrict__ vz)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t s = ilist[t];
+    const PosT r = rec[s];
+    const double h = 0.5 * dt * im.v[r.t];
+    const double ux = (vs[t] + h * fx[s]) + h * fx[s];
+    const double uy = (vs[n + t] + h * fy[s]) + h * fy[s];
+    const double uz = (vs[2 * n + t] + h * fz[s]) + h * fz[s];
+    const int32_t o = r.orig;
+    vx[o] = ux;
+    vy[o] = uy;
+    vz[o] = uz;
+    x[o] = r.x + dt * ux;
+    y[o] = r.y + dt * uy;
+    z[o] = r.z + dt * uz;
+}
+
+// Reference positions of a list build: xr = (x, y, z) in one pass.
+__global__ void k_save_reference(int64_t n, const double *__restrict__ x,
+                                 const double *__restrict__ y, const double *__restrict__ z,
+                                 double *__restrict__ xr)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    xr[i] = x[i];
+    xr[n + i] = y[i];
+    xr[2 * n + i] = z[i];
+}
+
 // Into sorted order: velocities and list-build reference positions of the
 // interior records by compact index.  from_rec: the records still hold the
 // build positions, which then serve as the reference (no gather).
@@ -244,14 +285,12 @@ mdlj_status save_reference(mdlj_ctx *ctx)
     const int64_t n = ctx->n;
     STCHK(ensure(ctx, ctx->b_xref, sizeof(double) * 3 * n));
     double *xr = (double *)ctx->b_xref.p;
-    HIPCHK(ctx, hipMemcpyAsync(xr, ctx->x, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(xr + n, ctx->y, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(xr + 2 * n, ctx->z, sizeof(double) * n, hipMemcpyDeviceToDevice,
-                               ctx->stream));
+    k_save_reference<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z, xr);
+    HIPCHK(ctx, hipGetLastError());
     return MDLJ_OK;
 }
 
-static mdlj_status ensure_host_flag(mdlj_ctx *ctx)
+mdlj_status ensure_host_flag(mdlj_ctx *ctx)
 {
     if (ctx->h_flag) return MDLJ_OK;
     // coherent: the kernel's store reaches host memory without a cache
@@ -440,6 +479,16 @@ static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, do
                 (const double *)ctx->b_xrsort.p, h * h, flag);
             ctx->upkeep_fused = true;
             ctx->rec_at_build = false;
+            HIPCHK(ctx, hipGetLastError());
+            continue;
+        }
+        if (s + 1 < nsteps && ctx->sorted_active) {
+            // the next force call rebuilds the lists from caller order
+            ctx->sorted_active = false;
+            k_kick_leave<<<nb, TB, 0, ctx->stream>>>(
+                n, (const int32_t *)ctx->b_ilist.p, (const PosT *)ctx->b_sorted.p,
+                (const double *)ctx->b_vsort.p, fo.fx, fo.fy, fo.fz, im, dt, ctx->x, ctx->y,
+                ctx->z, vx, vy, vz);
             HIPCHK(ctx, hipGetLastError());
             continue;
         }
