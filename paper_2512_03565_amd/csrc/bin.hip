@@ -128,30 +128,36 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(int64_t n,
 }
 
 // Exclusive scan of the per-tile sums in one workgroup; writes the total.
+// Each thread sums a run of consecutive tiles; the 1024 run sums are
+// scanned in parallel (lane prefix sums, then the 16 wavefront totals).
 __global__ __launch_bounds__(1024) void k_scan_parts(int64_t nparts, int32_t *__restrict__ part,
                                                      int32_t *__restrict__ total)
 {
-    __shared__ int32_t sums[1024];
-    int64_t per = ceil_div(nparts, 1024);
-    int64_t b = threadIdx.x * per;
-    int64_t e = b + per < nparts ? b + per : nparts;
+    constexpr int NWV = 1024 / MDLJ_WAVE;
+    __shared__ int32_t wsum[NWV];
+    const int64_t per = ceil_div(nparts, 1024);
+    const int64_t b = threadIdx.x * per;
+    const int64_t e = b + per < nparts ? b + per : nparts;
     int32_t s = 0;
     for (int64_t k = b; k < e; ++k) s += part[k];
-    sums[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int t = 0; t < 1024; ++t) {
-            int32_t v = sums[t];
-            sums[t] = run;
-            run += v;
-        }
-        *total = run;
+    const int lane = threadIdx.x & (MDLJ_WAVE - 1), wv = threadIdx.x / MDLJ_WAVE;
+    int32_t inc = s;
+    for (int o = 1; o < MDLJ_WAVE; o <<= 1) {
+        const int32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
     }
+    if (lane == MDLJ_WAVE - 1) wsum[wv] = inc;
     __syncthreads();
-    int32_t run = sums[threadIdx.x];
+    int32_t woff = 0, all = 0;
+    for (int w = 0; w < NWV; ++w) {
+        const int32_t v = wsum[w];
+        woff += w < wv ? v : 0;
+        all += v;
+    }
+    if (threadIdx.x == 0) *total = all;
+    int32_t run = woff + inc - s;
     for (int64_t k = b; k < e; ++k) {
-        int32_t v = part[k];
+        const int32_t v = part[k];
         part[k] = run;
         run += v;
     }

@@ -208,7 +208,8 @@ mdlj_status check_finite(mdlj_ctx *ctx, const double *x, const double *y, const 
 // --- integrator and record upkeep (integrate.hip) ---------------------------
 mdlj_status save_reference(mdlj_ctx *ctx);
 // Pinned host words ctx->h_flag (16 int32) and their device address
-// ctx->d_hflag: [0] the displacement flag, [4..7] binning results.
+// ctx->d_hflag: [0] the displacement flag, [4..7] binning results, [8..11]
+// Verlet-list build maxima.
 mdlj_status ensure_host_flag(mdlj_ctx *ctx);
 mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far);
 // Enqueue the skin/2 displacement check; its result lands in pinned host

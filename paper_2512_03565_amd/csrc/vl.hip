@@ -176,6 +176,14 @@ __device__ __forceinline__ void half_runs(const int (*rs)[STAGE_K + 3],
     e = (trim && h == 0) ? hs[r][c + 2] : rs[r][c + 3];
 }
 
+// host[0..3] = src[0..3] (system-scope stores to pinned memory)
+__global__ void k_publish4(const int32_t *__restrict__ src, int32_t *host)
+{
+    if (threadIdx.x < 4)
+        __hip_atomic_store(host + threadIdx.x, src[threadIdx.x], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Staged records and candidate-list entries of the largest tile, for the
 // LDS size of the tiled build: one thread per tile.
 __global__ void k_tile_sizes(const int32_t *__restrict__ start,
@@ -1025,10 +1033,12 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
                 (int32_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen);
         }
         HIPCHK(ctx, hipGetLastError());
-        int32_t hmax[4] = {0, 0, 0, 0};
-        HIPCHK(ctx, hipMemcpyAsync(hmax, maxlen, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                   ctx->stream));
+        // the four maxima to pinned host words in one small kernel
+        STCHK(ensure_host_flag(ctx));
+        k_publish4<<<1, 64, 0, ctx->stream>>>(maxlen, ctx->d_hflag + 8);
+        HIPCHK(ctx, hipGetLastError());
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        const int32_t hmax[4] = {ctx->h_flag[8], ctx->h_flag[9], ctx->h_flag[10], ctx->h_flag[11]};
         if (tiled && (hmax[2] > cmax || hmax[3] > ccand)) {
             // a tile over the sizes built nothing: exact sizes, or (if those
             // do not fit the LDS budget) the per-particle build
