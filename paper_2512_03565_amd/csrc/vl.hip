@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "pair.h"
 
@@ -485,6 +486,75 @@ __device__ __forceinline__ uint32_t mad16(uint32_t w, uint32_t base)
 
 typedef __attribute__((address_space(3))) const double lds_cdouble;
 typedef __attribute__((address_space(3))) const int lds_cint;
+typedef __attribute__((address_space(3))) const unsigned lds_cuint;
+
+// Fixed-point frame of the FP32-pair staged kernel.  A staged record is
+// {x, y, z, species} in 32 bits: the coordinate relative to the tile centre
+// times s (a power of two), rounded, plus 2^31.  Paired with the high word
+// 0x43300000 such a word is the binary64 number 2^52 + word, so the
+// difference of two of them is the exact integer separation, formed by the
+// same FP64 subtraction as for FP64 coordinates and with no conversion
+// instruction.  What is given up is the rounding of each coordinate to the
+// grid 1/s (s is chosen so that the staged neighbourhood reaches less than
+// 2^30 steps from the tile centre: 1/s is 1.5e-8 for cells of 2.8 sigma),
+// far below the FP32 pair law's own rounding.  A record takes 12 bytes of
+// LDS instead of 24, so more workgroups fit on a compute unit.
+__device__ __forceinline__ unsigned to_fx(double v, double o, double s)
+{
+    // the clamp keeps the conversion defined for a particle that has run
+    // far off (the force call is then repeated after a rebuild)
+    const double q = fmin(fmax(rint((v - o) * s), -2.0e9), 2.0e9);
+    return (unsigned)(int)q ^ 0x80000000u;
+}
+
+__device__ __forceinline__ double fx_value(unsigned w)
+{
+    return __hiloint2double(0x43300000, (int)w);
+}
+
+// the padding record: word 0 on every axis (coordinate -2^31), at least
+// sqrt(3) 2^30 / s from any staged particle (whose coordinates stay within
+// +-2^30), beyond the cutoff
+constexpr unsigned FX_PAD = 0u;
+
+// Staging of the fixed-point layout: record k of the nine concatenated rows
+// (four per thread in flight, rows found without branches as in stage_rows).
+__device__ __forceinline__ void stage_rows_fx(const PosT *__restrict__ rec, const int *seg_b,
+                                              const int *seg_c, int C, unsigned *sd, int *st,
+                                              bool types, double ox, double oy, double oz,
+                                              double s, int tid, int nthr)
+{
+    constexpr int U = 4;
+    int c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = seg_c[q + 1];
+    for (int k0 = tid; k0 < C; k0 += U * nthr) {
+        unsigned x[U], y[U], z[U];
+        int t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = min(k0 + u * nthr, C - 1);
+            int r = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r += k >= c[q];
+            const PosT *p = rec + seg_b[r] + (k - seg_c[r]);
+            x[u] = to_fx(p->x, ox, s);
+            y[u] = to_fx(p->y, oy, s);
+            z[u] = to_fx(p->z, oz, s);
+            t[u] = types ? p->t : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * nthr;
+            if (k < C) {
+                sd[3 * k] = x[u];
+                sd[3 * k + 1] = y[u];
+                sd[3 * k + 2] = z[u];
+                if (types) st[k] = t[u];
+            }
+        }
+    }
+}
 
 template <typename T, bool E, bool MS, int G, int V>
 __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ rec,
@@ -493,12 +563,16 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
                                                 int tiles_x, const uint16_t *__restrict__ nbr,
                                                 const int32_t *__restrict__ len, int32_t cap,
                                                 int64_t n, int cmax, LJTable<T> tab, ForceOut fo,
-                                                int remap)
+                                                int remap, double fxs)
 {
+    // FP32 pair law: fixed-point staged records; fxs is their scale and tab
+    // holds sig^2 fxs^2, 24 eps fxs and rc^2 fxs^2, so that every pair
+    // quantity comes out in its own units.  FP64 law: FP64 coordinates.
+    constexpr bool FX = sizeof(T) == sizeof(float);
     constexpr int SEG = MDLJ_WAVE / G;
     constexpr int NW = VL_LDS_TB / MDLJ_WAVE;
     constexpr int KS = V * SEG;  // entries of one i per trip
-    extern __shared__ double stage[];
+    extern __shared__ __attribute__((aligned(16))) double stage[];
     __shared__ int seg_b[9];
     __shared__ int seg_c[10];
     __shared__ LdsTable<T> lt;
@@ -556,19 +630,50 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
     }
     __syncthreads();
     const int C = seg_c[9];
-    // x, y, z of staged record k interleaved at sp[3k .. 3k+2]: one LDS
-    // address per candidate
+    // FP64 layout: x, y, z of staged record k interleaved at sp[3k .. 3k+2]
+    // (one LDS address per candidate), species in st[k]
     double *sp = stage;
     int *st = (int *)(stage + 3 * cmax);
-    stage_rows<3>(rec, seg_b, seg_c, C, sp, sp + 1, sp + 2, st, MS, tid, blockDim.x);
-    if (tid == 0) {
-        sp[3 * C] = sp[3 * C + 1] = sp[3 * C + 2] = PAD_COORD;
-        if (MS) st[C] = 0;
+    // fixed-point layout: x, y, z words of record k at sd[3k .. 3k+2] (a
+    // 12-byte stride spreads random records over all LDS banks), species in
+    // st2[k]
+    unsigned *sd = (unsigned *)stage;
+    int *st2 = (int *)(sd + 3 * cmax);
+    // tile centre of the fixed-point frame
+    const double ox = (cx0 + 0.5 * STAGE_K) * g.edge[0];
+    const double oy = (cy + 0.5) * g.edge[1];
+    const double oz = (cz + 0.5) * g.edge[2];
+    if constexpr (FX) {
+        stage_rows_fx(rec, seg_b, seg_c, C, sd, st2, MS, ox, oy, oz, fxs, tid, blockDim.x);
+        if (tid == 0) {
+            sd[3 * C] = sd[3 * C + 1] = sd[3 * C + 2] = FX_PAD;
+            if (MS) st2[C] = 0;
+        }
+    } else {
+        stage_rows<3>(rec, seg_b, seg_c, C, sp, sp + 1, sp + 2, st, MS, tid, blockDim.x);
+        if (tid == 0) {
+            sp[3 * C] = sp[3 * C + 1] = sp[3 * C + 2] = PAD_COORD;
+            if (MS) st[C] = 0;
+        }
     }
     __syncthreads();
     // LDS byte addresses of the staged coordinates and species
     const uint32_t xb = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) double *)sp;
-    const uint32_t tb = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) int *)st;
+    const uint32_t tb = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) int *)(FX ? st2 : st);
+    // i's coordinates in the frame of its staged partners
+    auto frame = [&](const PosT &q, double &x, double &y, double &z) {
+        if constexpr (FX) {
+            x = fx_value(to_fx(q.x, ox, fxs));
+            y = fx_value(to_fx(q.y, oy, fxs));
+            z = fx_value(to_fx(q.z, oz, fxs));
+        } else {
+            x = q.x;
+            y = q.y;
+            z = q.z;
+        }
+    };
+    double xi, yi, zi;
+    frame(pi, xi, yi, zi);
     double bu = 0.0, bw = 0.0;
     for (bool first = true; i0 < ie; i0 += NW * G, first = false) {
         if (!first) {
@@ -576,6 +681,7 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
             act = i < ie;
             t = t0 + (act ? i - ib : 0);
             pi = rec[act ? i : ib];
+            frame(pi, xi, yi, zi);
             L = len[min(t, n - 1)];
             L = act ? L : 0;
             vo = (uint32_t)(((t - t0) * cap + V * l) * 2);
@@ -588,18 +694,33 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
             const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
             for (int u = 0; u < V; ++u) {
-                const uint32_t ad = (u & 1) ? mad16<true, 24>(w[u >> 1], xb)
-                                            : mad16<false, 24>(w[u >> 1], xb);
-                int tj = 0;
-                if (MS) {
-                    const uint32_t at = (u & 1) ? mad16<true, 4>(w[u >> 1], tb)
-                                                : mad16<false, 4>(w[u >> 1], tb);
-                    tj = *(lds_cint *)(uintptr_t)at;
-                }
-                const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, tj);
                 double fxp, fyp, fzp;
-                lds_cdouble *q = (lds_cdouble *)(uintptr_t)ad;
-                lj_pair<T, E>(pi.x, pi.y, pi.z, q[0], q[1], q[2], true, p, rc2, a, fxp, fyp, fzp);
+                if constexpr (FX) {
+                    const uint32_t ad = (u & 1) ? mad16<true, 12>(w[u >> 1], xb)
+                                                : mad16<false, 12>(w[u >> 1], xb);
+                    int tj = 0;
+                    if (MS) {
+                        const uint32_t at = (u & 1) ? mad16<true, 4>(w[u >> 1], tb)
+                                                    : mad16<false, 4>(w[u >> 1], tb);
+                        tj = *(lds_cint *)(uintptr_t)at;
+                    }
+                    lds_cuint *q = (lds_cuint *)(uintptr_t)ad;
+                    const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, tj);
+                    lj_pair<T, E>(xi, yi, zi, fx_value(q[0]), fx_value(q[1]), fx_value(q[2]),
+                                  true, p, rc2, a, fxp, fyp, fzp);
+                } else {
+                    const uint32_t ad = (u & 1) ? mad16<true, 24>(w[u >> 1], xb)
+                                                : mad16<false, 24>(w[u >> 1], xb);
+                    int tj = 0;
+                    if (MS) {
+                        const uint32_t at = (u & 1) ? mad16<true, 4>(w[u >> 1], tb)
+                                                    : mad16<false, 4>(w[u >> 1], tb);
+                        tj = *(lds_cint *)(uintptr_t)at;
+                    }
+                    const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, tj);
+                    lds_cdouble *q = (lds_cdouble *)(uintptr_t)ad;
+                    lj_pair<T, E>(xi, yi, zi, q[0], q[1], q[2], true, p, rc2, a, fxp, fyp, fzp);
+                }
             }
         };
         // two trips in flight.  Both reloads are unconditional, so every
@@ -622,7 +743,8 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
         }
         if (E) {
             bu += a.u;
-            bw += a.w;
+            // the fixed-point path sums 24 eps s6 (2 s6 - 1) fxs
+            bw += FX ? a.w * (1.0 / fxs) : a.w;
         }
     }
     if (E) {
@@ -799,8 +921,27 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
     if (cfg.staged) {
         const Grid &g = ctx->grid;
         const int cmax = ctx->max_nbhd + 1;  // + the padding entry
-        const size_t lds = (size_t)cmax * (3 * sizeof(double) + (MS ? sizeof(int) : 0));
+        constexpr bool FX = sizeof(T) == sizeof(float);
+        const size_t lds = (size_t)cmax * ((FX ? 3 * sizeof(unsigned) : 3 * sizeof(double)) +
+                                           (MS ? sizeof(int) : 0));
         if (lds > (size_t)STAGE_LDS_BYTES || N3) return -2;
+        // fixed-point scale: the staged neighbourhood of a tile reaches
+        // STAGE_K / 2 + 1 cells from its centre along x and 3/2 cells along y
+        // and z; with rc + skin more for particles that drift before a
+        // rebuild, it must stay within 2^30 steps
+        const double reach = std::max({0.5 * (STAGE_K + 2) * g.edge[0], 1.5 * g.edge[1],
+                                       1.5 * g.edge[2]}) +
+                             ctx->rc + ctx->skin;
+        const double fxs = FX ? std::exp2(std::floor(std::log2(1073741824.0 / reach))) : 1.0;
+        LJTable<T> tx = tab;
+        if (FX) {
+            for (int k = 0; k < tab.ns * tab.ns; ++k) {
+                tx.sig2[k] = (T)((double)tab.sig2[k] * fxs * fxs);
+                tx.eps24[k] = (T)((double)tab.eps24[k] * fxs);
+            }
+            tx.rc2d = tab.rc2d * fxs * fxs;
+            tx.rc2 = (T)tx.rc2d;
+        }
         const int tiles_x = (int)ceil_div(g.n[0], STAGE_K);
         const int64_t nbt = (int64_t)tiles_x * g.n[1] * g.n[2];
         const int32_t *ibase = (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1;
@@ -808,7 +949,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         const int32_t *start = (const int32_t *)ctx->b_start.p;
 #define VL_LDS(GG, VV)                                                                        \
     k_vl_lds<T, E, MS, GG, VV><<<nbt, VL_LDS_TB, lds, s>>>(rec, start, ibase, g, tiles_x, nbr16, len, \
-                                                     cap, n, cmax, tab, fo, remap)
+                                                     cap, n, cmax, tx, fo, remap, fxs)
         const int key = cfg.tile_i * 100 + cfg.tile_j;
         switch (key) {
         case 802: VL_LDS(8, 2); break;

@@ -43,6 +43,7 @@ def check(m, orc, s, configs, label, precs=(0, 1), skin=0.3):
                 sysm.set_config(cfg)
                 f, U, W = sysm.forces()
                 e = P.force_error(f, ref["f"], slack)
+                print(f"[vl parity]   err_F {e:.3e}", flush=True)
                 assert e <= TOL[prec], (cfg, prec, e, namb)
                 assert P.total_error(U, ref["U"], su) <= TOL[prec], (cfg, prec, U, ref["U"])
                 assert P.total_error(W, ref["W"], sw) <= TOL[prec], (cfg, prec, W, ref["W"])
@@ -61,20 +62,23 @@ def test_vl_config2_100k(m, orc):
 
 
 def test_vl_dense_large_cells_fall_back(m, orc):
-    # rc = 4: about 70 particles per cell, too many to stage a tile's
-    # neighbourhood in LDS, so the lists come from the per-particle build and
-    # staged configurations are refused with MDLJ_ERR_ARG
+    # rc = 4: about 70 particles per cell.  The tiled list build cannot stage
+    # a tile's neighbourhood in LDS, so the lists come from the per-particle
+    # build.  The FP32-pair staged kernel still fits it (16-byte fixed-point
+    # records, ~54 KB); the all-FP64 one (24 bytes and the species) does not
+    # and is refused with MDLJ_ERR_ARG
     pos, box = scenes.fcc_lattice(8, 8, 8, 0.9, 0.05, seed=41)
     s = dict(pos=pos, box=box, rc=4.0, eps=[1.0], sig=[1.0], types=None)
     plain = [c for c in vl_configs(m) if len(c) < 7]
+    staged = [c for c in vl_configs(m) if len(c) == 7]
     check(m, orc, s, plain, "dense")
-    with m.System(pos, box, 4.0, skin=0.3) as sysm:
-        for cfg in vl_configs(m):
-            if len(cfg) == 7:
-                with pytest.raises(m.MdljError) as ei:
-                    sysm.set_config(cfg)
-                    sysm.forces()
-                assert ei.value.status == -1, cfg
+    check(m, orc, s, staged, "dense", precs=(0,))
+    with m.System(pos, box, 4.0, skin=0.3, precision=1) as sysm:
+        for cfg in staged:
+            with pytest.raises(m.MdljError) as ei:
+                sysm.set_config(cfg)
+                sysm.forces()
+            assert ei.value.status == -1, cfg
 
 
 def test_vl_zero_skin_equals_cutoff_lists(m, orc):
