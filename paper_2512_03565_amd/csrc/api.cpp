@@ -182,8 +182,15 @@ static void invalidate(mdlj_ctx *ctx)
 // ------------------------------------------------------------------ build
 
 // (Re)build the neighbour structure of configuration c.
+static mdlj_status take_event(mdlj_ctx *ctx, hipEvent_t *e);
+
 static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
 {
+    // a timed force call marks where its rebuild starts (its build time)
+    if (ctx->want_build_mark && !ctx->build_mark) {
+        STCHK(take_event(ctx, &ctx->build_mark));
+        HIPCHK(ctx, hipEventRecord(ctx->build_mark, ctx->stream));
+    }
     // binning reads the caller-order positions
     STCHK(leave_sorted(ctx));
     STCHK(check_geometry(ctx, c));
@@ -280,10 +287,41 @@ mdlj_status prepare(mdlj_ctx *ctx, const mdlj_config &c, bool positions_changed,
     return MDLJ_OK;
 }
 
+// Add one timed force call to the totals and return its events to the pool.
+static mdlj_status account(mdlj_ctx *ctx, const mdlj_ctx::Timed &t)
+{
+    float tf = 0;
+    HIPCHK(ctx, hipEventElapsedTime(&tf, t.e1, t.e2));
+    ctx->last_force_us = 1e3 * tf;
+    ctx->t_force_us += 1e3 * tf;
+    ctx->t_nforce++;
+    if (t.e0) {
+        float tb = 0;
+        HIPCHK(ctx, hipEventElapsedTime(&tb, t.e0, t.e1));
+        ctx->t_build_us += 1e3 * tb;
+        ctx->t_nbuild++;
+        ctx->ev_pool.push_back(t.e0);
+    }
+    ctx->ev_pool.push_back(t.e1);
+    ctx->ev_pool.push_back(t.e2);
+    return MDLJ_OK;
+}
+
+// An event for a timed force call: from the pool, refilled first from
+// timed calls at least 64 calls old, which the device finished long ago (the
+// wait on them returns at once), so a long timed run cycles a few hundred
+// events instead of creating three per call.
 static mdlj_status take_event(mdlj_ctx *ctx, hipEvent_t *e)
 {
+    while (ctx->ev_pool.empty() && ctx->ev_pending.size() > 64) {
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev_pending.front().e2));
+        STCHK(account(ctx, ctx->ev_pending.front()));
+        ctx->ev_pending.pop_front();
+    }
     if (ctx->ev_pool.empty()) {
-        HIPCHK(ctx, hipEventCreate(e));
+        // timing only: no system-scope fence when recorded (no cache
+        // write-back between the timed kernels)
+        HIPCHK(ctx, hipEventCreateWithFlags(e, hipEventDisableSystemFence));
     } else {
         *e = ctx->ev_pool.back();
         ctx->ev_pool.pop_back();
@@ -295,21 +333,7 @@ mdlj_status collect_timing(mdlj_ctx *ctx)
 {
     if (ctx->ev_pending.empty()) return MDLJ_OK;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    for (const auto &t : ctx->ev_pending) {
-        float tb = 0, tf = 0;
-        HIPCHK(ctx, hipEventElapsedTime(&tb, t.e0, t.e1));
-        HIPCHK(ctx, hipEventElapsedTime(&tf, t.e1, t.e2));
-        ctx->last_force_us = 1e3 * tf;
-        ctx->t_force_us += 1e3 * tf;
-        ctx->t_nforce++;
-        if (t.rebuilt) {
-            ctx->t_build_us += 1e3 * tb;
-            ctx->t_nbuild++;
-        }
-        ctx->ev_pool.push_back(t.e0);
-        ctx->ev_pool.push_back(t.e1);
-        ctx->ev_pool.push_back(t.e2);
-    }
+    for (const auto &t : ctx->ev_pending) STCHK(account(ctx, t));
     ctx->ev_pending.clear();
     return MDLJ_OK;
 }
@@ -353,10 +377,13 @@ mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW, F
     bool rebuilt = false, pending = false;
     mdlj_ctx::Timed tm = {nullptr, nullptr, nullptr, false};
     if (ctx->timing) {
-        STCHK(take_event(ctx, &tm.e0));
+        // e0 only when the call rebuilds (recorded by rebuild()); a mark
+        // left by a call that failed goes back to the pool
+        if (ctx->build_mark) ctx->ev_pool.push_back(ctx->build_mark);
+        ctx->build_mark = nullptr;
         STCHK(take_event(ctx, &tm.e1));
         STCHK(take_event(ctx, &tm.e2));
-        HIPCHK(ctx, hipEventRecord(tm.e0, ctx->stream));
+        ctx->want_build_mark = true;
     }
     STCHK(prepare(ctx, c, positions_changed, &rebuilt, &pending));
     ForceOut fo;
@@ -380,6 +407,9 @@ mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW, F
     }
     if (ctx->timing) {
         tm.rebuilt = rebuilt;
+        tm.e0 = ctx->build_mark;
+        ctx->build_mark = nullptr;
+        ctx->want_build_mark = false;
         ctx->ev_pending.push_back(tm);
     }
     if (needs_fold(c)) STCHK(fold_forces(ctx, fo));
@@ -478,10 +508,11 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
     if (!ctx) return MDLJ_OK;
     (void)hipStreamSynchronize(ctx->stream);
     for (const auto &t : ctx->ev_pending) {
-        ctx->ev_pool.push_back(t.e0);
+        if (t.e0) ctx->ev_pool.push_back(t.e0);
         ctx->ev_pool.push_back(t.e1);
         ctx->ev_pool.push_back(t.e2);
     }
+    if (ctx->build_mark) ctx->ev_pool.push_back(ctx->build_mark);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->ev_flag) (void)hipEventDestroy(ctx->ev_flag);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);

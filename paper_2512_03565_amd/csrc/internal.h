@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -153,8 +154,11 @@ struct mdlj_ctx {
         bool rebuilt;
     };
     bool timing = false;
+    // inside a timed force call: rebuild() records build_mark at its start
+    bool want_build_mark = false;
+    hipEvent_t build_mark = nullptr;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<Timed> ev_pending;
+    std::deque<Timed> ev_pending;
     // displacement check result (pinned host memory, d_hflag its device
     // address) and its event; dflag_zero: the device-side flag is known to
     // hold 0
