@@ -99,10 +99,13 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2 };
  * read from LDS.  LC cluster-tile / wave-per-i: a workgroup owns one cell
  * and stages its 27-cell neighbourhood.  VL wave-per-i: a workgroup owns 4
  * consecutive cells along x and stages the 9 rows of 6 cells around them;
- * the Verlet list then holds 16-bit indices into that staged set.  A scene
- * whose neighbourhoods do not fit the 64 KB staging budget rejects staged
- * configurations with MDLJ_ERR_ARG.  staged = 0 reads every j-particle
- * from global memory.
+ * the Verlet list then holds 16-bit indices into that staged set; with
+ * FP32 pair arithmetic its records are staged as 32-bit fixed point
+ * relative to the tile centre (12 bytes, exact separations to within the
+ * grid 1/s, 1.5e-8 sigma for cells of 2.8 sigma), with all-FP64 as FP64
+ * (24 bytes).  A scene whose neighbourhoods do not fit the 64 KB staging
+ * budget rejects staged configurations with MDLJ_ERR_ARG.  staged = 0 reads
+ * every j-particle from global memory.
  */
 typedef struct {
     int32_t nbr_algo;
@@ -245,16 +248,21 @@ mdlj_status mdlj_retune_needed(const float *before8, const float *now8, double t
  * v += F dt/2m; x += v dt; wrap; F = F(x); v += F dt/2m.  vx, vy, vz are
  * device float64 arrays in caller order, updated in place.  The forces of
  * the current positions must have been computed once before (they are kept
- * in the context).
+ * in the context).  With Verlet lists the steps between rebuilds keep
+ * positions and velocities in the context in sorted order; the caller's
+ * arrays and the context's positions are brought up to date before each
+ * rebuild and before the call returns (also when it returns an error).
  */
 mdlj_status mdlj_step_vv(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt,
                          int32_t nsteps);
 mdlj_status mdlj_set_mass(mdlj_ctx *ctx, int32_t s, double mass);
 
 /* Kernel timing with HIP events on the context's stream.  on = 1 enables
- * and resets the totals.  Events are recorded around the neighbour upkeep
- * and the force kernel of every force evaluation and read only when
- * get_timing is called (which synchronises the stream).  get_timing returns
+ * and resets the totals.  Events (timing only: no system-scope fence) are
+ * recorded around the force kernel of every force evaluation and, when it
+ * rebuilds, from the start of the rebuild; they are read when get_timing is
+ * called (which synchronises the stream) or recycled once they are 64
+ * evaluations old.  get_timing returns
  * the summed force-kernel and rebuild (binning + list build, or the
  * per-step re-binning of linked cells) microseconds and how many of each
  * were timed.  Outputs may be NULL. */

@@ -160,6 +160,39 @@ def test_velocity_verlet_fast_particles_force_early_rebuilds(m, orc, cfg):
     assert np.abs(v - v_ref).max() < 1e-8, cfg
 
 
+@pytest.mark.parametrize("prec,cfg", [(0, (1, 2, 16, 4, 0, 0, 1)), (1, (1, 2, 8, 8, 0, 0)),
+                                      (1, (1, 0, 0, 0, 0, 0))])
+def test_velocity_verlet_one_call_equals_single_steps(m, prec, cfg):
+    # Between Verlet-list rebuilds a multi-step call keeps the integrator
+    # state in sorted order and writes it back before each rebuild and on
+    # return; one-step calls never enter that state.  The arithmetic is the
+    # same, so 60 steps in one call and 60 calls of one step must agree bit
+    # for bit, over six scheduled rebuilds and the displacement tests.
+    import torch
+    s = scenes.config2()
+    n = len(s["pos"])
+    v0 = scenes.mb_velocities(n, 1.0, 1.0, seed=77)
+    out = []
+    for single in (False, True):
+        with m.System(s["pos"], s["box"], s["rc"], skin=0.3, rebuild_every=10,
+                      precision=prec) as sysm:
+            sysm.set_config(cfg)
+            vel = [torch.tensor(np.ascontiguousarray(v0[:, k]), device="cuda") for k in range(3)]
+            sysm.set_timing(True)
+            if single:
+                for _ in range(60):
+                    sysm.step_vv(vel, s["dt"], 1)
+            else:
+                sysm.step_vv(vel, s["dt"], 60)
+            _, _, nf, nb = sysm.get_timing()
+            out.append((sysm.get_positions(), torch.stack(vel, 1).cpu().numpy(), nb))
+    print(f"[vv one call vs single steps] prec={prec} cfg={cfg} rebuilds {out[0][2]} / {out[1][2]}",
+          flush=True)
+    assert out[0][2] == out[1][2] >= 6, (cfg, out[0][2], out[1][2])
+    assert np.array_equal(out[0][0], out[1][0]), cfg
+    assert np.array_equal(out[0][1], out[1][1]), cfg
+
+
 def test_vl_cells_exactly_list_range_wide(m, orc):
     # box 16 x 1.75 = 28 = 10 x (rc + skin): cells exactly rc + skin wide, so
     # the list build may not drop candidates by cell halves
