@@ -218,10 +218,12 @@ __global__ void k_publish_flag(int32_t *flag, int32_t *host)
     if (threadIdx.x == 0) publish_flag(flag, host);
 }
 
-// Halo records from their source records, one wavefront per halo cell:
+// Halo records from their source records, a group of lanes per halo cell:
 // rec = source + image * L (the same sum the full refresh forms from the
 // caller-order positions).  hl holds (halo cell, source cell) pairs.  The
 // first thread also publishes the displacement flag.
+constexpr int HALO_LANES = 16;
+
 __global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__restrict__ hl,
                                                       const int32_t *__restrict__ start,
                                                       const char4 *__restrict__ img,
@@ -229,12 +231,14 @@ __global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__
                                                       double lz, int32_t *flag, int32_t *host)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_flag(flag, host);
-    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
-    const int lane = threadIdx.x & (MDLJ_WAVE - 1);
+    // HALO_LANES lanes per halo cell (cells hold ~17 records at liquid
+    // densities, so a whole wavefront per cell would idle most lanes)
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / HALO_LANES;
+    const int sub = threadIdx.x & (HALO_LANES - 1);
     if (w >= nh) return;
     const int2 p = hl[w];
     const int32_t b = start[p.x], cnt = start[p.x + 1] - b, sb = start[p.y];
-    for (int32_t m = lane; m < cnt; m += MDLJ_WAVE) {
+    for (int32_t m = sub; m < cnt; m += HALO_LANES) {
         const char4 c = img[b + m];
         PosT q = rec[sb + m];
         q.x += (double)c.x * lx;
@@ -336,7 +340,7 @@ mdlj_status finish_fused_upkeep(mdlj_ctx *ctx)
 {
     int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
     if (ctx->nhalo > 0) {
-        k_refresh_halo<<<ceil_div(ctx->nhalo, 4), 256, 0, ctx->stream>>>(
+        k_refresh_halo<<<ceil_div(ctx->nhalo, 256 / HALO_LANES), 256, 0, ctx->stream>>>(
             ctx->nhalo, (const int2 *)ctx->b_halo.p, (const int32_t *)ctx->b_start.p,
             (const char4 *)ctx->b_img.p, (PosT *)ctx->b_sorted.p, ctx->box[0], ctx->box[1],
             ctx->box[2], flag, ctx->d_hflag);
