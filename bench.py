@@ -117,6 +117,18 @@ def list_stream_bytes(sysm, n):
     return entries * esize + 4 * n + 24 * records + 24 * n
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(scene, budget_s):
     import oracle
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -260,6 +272,8 @@ def main():
                       f"(FP64 linked-cell oracle, {t_step:.2f} s each)",
             "one_core": {"value": pairs / t_one / 1e6, "unit": "Mpairs/s", "cores": 1,
                          "sample": f"1 full force evaluation ({t_one:.2f} s)"},
+            "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
         }
     sysm.close()
     print(json.dumps(line), flush=True)
