@@ -46,7 +46,7 @@ __device__ __forceinline__ int64_t source_cell(int64_t e, const Grid &g)
     int64_t src = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int c = (int)((e / g.stride[a]) % g.e[a]) - g.h[a];
+        int c = (int)(((uint32_t)e / (uint32_t)g.stride[a]) % (uint32_t)g.e[a]) - g.h[a];
         int s = c % g.n[a];
         s = s < 0 ? s + g.n[a] : s;
         src += (int64_t)(s + g.h[a]) * g.stride[a];
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
     int sx_cell = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int c = (int)((e / g.stride[a]) % g.e[a]) - g.h[a];
+        int c = (int)(((uint32_t)e / (uint32_t)g.stride[a]) % (uint32_t)g.e[a]) - g.h[a];
         int s = c;
         sh[a] = 0.0;
         code[a] = 0;
@@ -383,9 +383,9 @@ __global__ void k_int_counts(Grid g, const int32_t *__restrict__ count, int32_t 
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell_int) return;
-    int cx = (int)(c % g.n[0]);
-    int cy = (int)((c / g.n[0]) % g.n[1]);
-    int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    int cx = (int)((uint32_t)c % (uint32_t)g.n[0]);
+    int cy = (int)(((uint32_t)c / (uint32_t)g.n[0]) % (uint32_t)g.n[1]);
+    int cz = (int)((uint32_t)c / ((uint32_t)g.n[0] * (uint32_t)g.n[1]));
     int64_t e = (int64_t)(cx + g.h[0]) * g.stride[0] + (int64_t)(cy + g.h[1]) * g.stride[1] +
                 (int64_t)(cz + g.h[2]) * g.stride[2];
     icnt[c] = count[e];
@@ -408,9 +408,9 @@ __global__ void k_ilist(Grid g, const int32_t *__restrict__ start, const int32_t
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell_int) return;
-    int cx = (int)(c % g.n[0]);
-    int cy = (int)((c / g.n[0]) % g.n[1]);
-    int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    int cx = (int)((uint32_t)c % (uint32_t)g.n[0]);
+    int cy = (int)(((uint32_t)c / (uint32_t)g.n[0]) % (uint32_t)g.n[1]);
+    int cz = (int)((uint32_t)c / ((uint32_t)g.n[0] * (uint32_t)g.n[1]));
     int64_t e = (int64_t)(cx + g.h[0]) * g.stride[0] + (int64_t)(cy + g.h[1]) * g.stride[1] +
                 (int64_t)(cz + g.h[2]) * g.stride[2];
     int32_t b = start[e], en = start[e + 1], o = ibase[c];

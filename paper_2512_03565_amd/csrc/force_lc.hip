@@ -40,10 +40,10 @@ __global__ __launch_bounds__(64) void k_lc_ipl(const PosT *__restrict__ rec,
     if (MS) lds_table_load(lt, tab, lane, MDLJ_WAVE);
     const int64_t nb = gridDim.x;
     const int64_t t = remap ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
-    const int tx = (int)(t % tiles_x);
-    const int64_t rr = t / tiles_x;
-    const int cy = (int)(rr % g.n[1]);
-    const int cz = (int)(rr / g.n[1]);
+    const int tx = (int)((uint32_t)t % (uint32_t)tiles_x);
+    const uint32_t rr = (uint32_t)t / (uint32_t)tiles_x;
+    const int cy = (int)(rr % (uint32_t)g.n[1]);
+    const int cz = (int)(rr / (uint32_t)g.n[1]);
     const int cx0 = tx * K;
     const int ncx = min(K, g.n[0] - cx0);
     const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
@@ -105,9 +105,9 @@ __global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
     if (MS) lds_table_load(lt, tab, lane, MDLJ_WAVE);
     const int64_t nb = gridDim.x;
     const int64_t c = remap ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
-    const int cx = (int)(c % g.n[0]);
-    const int cy = (int)((c / g.n[0]) % g.n[1]);
-    const int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    const int cx = (int)((uint32_t)c % (uint32_t)g.n[0]);
+    const int cy = (int)(((uint32_t)c / (uint32_t)g.n[0]) % (uint32_t)g.n[1]);
+    const int cz = (int)((uint32_t)c / ((uint32_t)g.n[0] * (uint32_t)g.n[1]));
     const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
                        cx + g.h[0];
     const int ib = start[ei], ie = start[ei + 1];
@@ -208,9 +208,9 @@ __global__ __launch_bounds__(64) void k_lc_count(const PosT *__restrict__ rec,
     __shared__ int seg_c[10];
     const int lane = threadIdx.x;
     const int64_t c = blockIdx.x;
-    const int cx = (int)(c % g.n[0]);
-    const int cy = (int)((c / g.n[0]) % g.n[1]);
-    const int cz = (int)(c / ((int64_t)g.n[0] * g.n[1]));
+    const int cx = (int)((uint32_t)c % (uint32_t)g.n[0]);
+    const int cy = (int)(((uint32_t)c / (uint32_t)g.n[0]) % (uint32_t)g.n[1]);
+    const int cz = (int)((uint32_t)c / ((uint32_t)g.n[0] * (uint32_t)g.n[1]));
     const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
                        cx + g.h[0];
     const int ib = start[ei], ie = start[ei + 1];

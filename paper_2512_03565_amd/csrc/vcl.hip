@@ -56,7 +56,7 @@ __global__ void k_col_counts(Grid g, const int32_t *__restrict__ start, int M,
 {
     int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= (int64_t)g.n[0] * g.n[1]) return;
-    int cx = (int)(col % g.n[0]), cy = (int)(col / g.n[0]);
+    int cx = (int)((uint32_t)col % (uint32_t)g.n[0]), cy = (int)((uint32_t)col / (uint32_t)g.n[0]);
     int64_t e0 = (int64_t)cx * g.stride[0] + (int64_t)cy * g.stride[1];
     int32_t cnt = start[e0 + g.n[2]] - start[e0];
     ccount[col] = (cnt + M - 1) / M;
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(64) void k_make_clusters(
 {
     const int64_t col = blockIdx.x;
     const int lane = threadIdx.x;
-    const int cx = (int)(col % g.n[0]), cy = (int)(col / g.n[0]);
+    const int cx = (int)((uint32_t)col % (uint32_t)g.n[0]), cy = (int)((uint32_t)col / (uint32_t)g.n[0]);
     const int64_t e0 = (int64_t)cx * g.stride[0] + (int64_t)cy * g.stride[1];
     const int32_t b = start[e0], en = start[e0 + g.n[2]];
     const int32_t q0 = cbase[col], q1 = cbase[col + 1];

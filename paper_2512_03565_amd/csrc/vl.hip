@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
         const PosT pi = rec[i];
         const int64_t e = cell_of[pi.orig];
         // x-tile of i's cell
-        const int cx = (int)(e % g.stride[1]) - g.h[0];
+        const int cx = (int)((uint32_t)e % (uint32_t)g.stride[1]) - g.h[0];
         const int cx0 = (cx / STAGE_K) * STAGE_K;
         const int ncx = min(STAGE_K, g.n[0] - cx0);
         const int64_t erow = e - (cx + g.h[0]);  // first cell of i's x-row
@@ -194,10 +194,10 @@ __global__ void k_tile_sizes(const int32_t *__restrict__ start,
     const int64_t tile = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t C = 0, NC = 0;
     if (tile < ntiles) {
-        const int tx = (int)(tile % tiles_x);
-        const int64_t rr = tile / tiles_x;
-        const int cy = (int)(rr % g.n[1]);
-        const int cz = (int)(rr / g.n[1]);
+        const int tx = (int)((uint32_t)tile % (uint32_t)tiles_x);
+        const uint32_t rr = (uint32_t)tile / (uint32_t)tiles_x;
+        const int cy = (int)(rr % (uint32_t)g.n[1]);
+        const int cz = (int)(rr / (uint32_t)g.n[1]);
         const int cx0 = tx * STAGE_K;
         const int ncx = min(STAGE_K, g.n[0] - cx0);
         for (int r = 0; r < 9; ++r) {
@@ -252,10 +252,10 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     const int tid = threadIdx.x;
     const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
     const int64_t tile = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int tx = (int)(tile % tiles_x);
-    const int64_t rr = tile / tiles_x;
-    const int cy = (int)(rr % g.n[1]);
-    const int cz = (int)(rr / g.n[1]);
+    const int tx = (int)((uint32_t)tile % (uint32_t)tiles_x);
+    const uint32_t rr = (uint32_t)tile / (uint32_t)tiles_x;
+    const int cy = (int)(rr % (uint32_t)g.n[1]);
+    const int cz = (int)(rr / (uint32_t)g.n[1]);
     const int cx0 = tx * STAGE_K;
     const int ncx = min(STAGE_K, g.n[0] - cx0);
     // all cell starts of the nine rows in one round of loads
@@ -582,10 +582,10 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
     const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
     if (MS) lds_table_load(lt, tab, tid, blockDim.x);
     const int64_t tile = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int tx = (int)(tile % tiles_x);
-    const int64_t rr = tile / tiles_x;
-    const int cy = (int)(rr % g.n[1]);
-    const int cz = (int)(rr / g.n[1]);
+    const int tx = (int)((uint32_t)tile % (uint32_t)tiles_x);
+    const uint32_t rr = (uint32_t)tile / (uint32_t)tiles_x;
+    const int cy = (int)(rr % (uint32_t)g.n[1]);
+    const int cz = (int)(rr / (uint32_t)g.n[1]);
     const int cx0 = tx * STAGE_K;
     const int ncx = min(STAGE_K, g.n[0] - cx0);
     const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
