@@ -248,10 +248,11 @@ mdlj_status mdlj_retune_needed(const float *before8, const float *now8, double t
  * v += F dt/2m; x += v dt; wrap; F = F(x); v += F dt/2m.  vx, vy, vz are
  * device float64 arrays in caller order, updated in place.  The forces of
  * the current positions must have been computed once before (they are kept
- * in the context).  With Verlet lists the steps between rebuilds keep
- * positions and velocities in the context in sorted order; the caller's
- * arrays and the context's positions are brought up to date before each
- * rebuild and before the call returns (also when it returns an error).
+ * in the context).  With Verlet lists the steps keep positions and
+ * velocities in the context in sorted order (the velocities also across
+ * list rebuilds); the caller's arrays and the context's positions are
+ * brought up to date before the call returns (also when it returns an
+ * error).
  */
 mdlj_status mdlj_step_vv(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt,
                          int32_t nsteps);

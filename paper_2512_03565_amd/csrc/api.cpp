@@ -192,7 +192,7 @@ static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
         HIPCHK(ctx, hipEventRecord(ctx->build_mark, ctx->stream));
     }
     // binning reads the caller-order positions
-    STCHK(leave_sorted(ctx));
+    STCHK(positions_for_rebuild(ctx));
     STCHK(check_geometry(ctx, c));
     if (c.nbr_algo == MDLJ_NBR_VCL) {
         STCHK(vcl_build(ctx, c));
@@ -524,7 +524,7 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
                       &ctx->b_pos,     &ctx->b_type,    &ctx->b_force,
                       &ctx->b_cnt_ext, &ctx->b_img,     &ctx->b_icnt,    &ctx->b_ilist,
                       &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo,    &ctx->b_hstart,
-                      &ctx->b_vsort,   &ctx->b_xrsort};
+                      &ctx->b_vsort,   &ctx->b_vsort2,  &ctx->b_xrsort,  &ctx->b_tinv};
     for (DevBuf *b : bufs) free_buf(*b);
     delete ctx;
     return MDLJ_OK;

@@ -9,6 +9,7 @@
 // at build time.  Positions are left unwrapped until the next rebuild.
 #include <string.h>
 
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -105,12 +106,12 @@ __global__ void k_kick_drift_compact(int64_t n, const int32_t *__restrict__ ilis
     const int32_t s = ilist[t];
     PosT r = rec[s];
     const double h = 0.5 * dt * im.v[r.t];
-    const double ux = (vs[t] + h * fx[s]) + h * fx[s];
-    const double uy = (vs[n + t] + h * fy[s]) + h * fy[s];
-    const double uz = (vs[2 * n + t] + h * fz[s]) + h * fz[s];
-    vs[t] = ux;
-    vs[n + t] = uy;
-    vs[2 * n + t] = uz;
+    const double ux = (vs[3 * t] + h * fx[s]) + h * fx[s];
+    const double uy = (vs[3 * t + 1] + h * fy[s]) + h * fy[s];
+    const double uz = (vs[3 * t + 2] + h * fz[s]) + h * fz[s];
+    vs[3 * t] = ux;
+    vs[3 * t + 1] = uy;
+    vs[3 * t + 2] = uz;
     r.x += dt * ux;
     r.y += dt * uy;
     r.z += dt * uz;
@@ -121,32 +122,50 @@ __global__ void k_kick_drift_compact(int64_t n, const int32_t *__restrict__ ilis
 }
 
 // The step before a list rebuild, from the sorted-order state: the same
-// kick and drift as k_kick_drift_compact, with positions and velocities
-// written straight to caller order (the rebuild bins from there) instead of
-// to the records.
+// kick and drift as k_kick_drift_compact.  Positions go to caller order (the
+// rebuild bins from there); velocities stay by compact index, and
+// tinv[caller index] = compact index lets the first sorted step after the
+// rebuild carry them into the new order.
 __global__ void k_kick_leave(int64_t n, const int32_t *__restrict__ ilist,
-                             const PosT *__restrict__ rec, const double *__restrict__ vs,
+                             const PosT *__restrict__ rec, double *__restrict__ vs,
                              const double *__restrict__ fx, const double *__restrict__ fy,
                              const double *__restrict__ fz, InvMass im, double dt,
                              double *__restrict__ x, double *__restrict__ y,
-                             double *__restrict__ z, double *__restrict__ vx,
-                             double *__restrict__ vy, double *__restrict__ vz)
+                             double *__restrict__ z, int32_t *__restrict__ tinv)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int32_t s = ilist[t];
     const PosT r = rec[s];
     const double h = 0.5 * dt * im.v[r.t];
-    const double ux = (vs[t] + h * fx[s]) + h * fx[s];
-    const double uy = (vs[n + t] + h * fy[s]) + h * fy[s];
-    const double uz = (vs[2 * n + t] + h * fz[s]) + h * fz[s];
+    const double ux = (vs[3 * t] + h * fx[s]) + h * fx[s];
+    const double uy = (vs[3 * t + 1] + h * fy[s]) + h * fy[s];
+    const double uz = (vs[3 * t + 2] + h * fz[s]) + h * fz[s];
+    vs[3 * t] = ux;
+    vs[3 * t + 1] = uy;
+    vs[3 * t + 2] = uz;
     const int32_t o = r.orig;
-    vx[o] = ux;
-    vy[o] = uy;
-    vz[o] = uz;
     x[o] = r.x + dt * ux;
     y[o] = r.y + dt * uy;
     z[o] = r.z + dt * uz;
+    tinv[o] = (int32_t)t;
+}
+
+// For a rebuild while the sorted-order state is current: caller-order
+// positions from the records and tinv as in k_kick_leave.
+__global__ void k_leave_positions(int64_t n, const int32_t *__restrict__ ilist,
+                                  const PosT *__restrict__ rec, double *__restrict__ x,
+                                  double *__restrict__ y, double *__restrict__ z,
+                                  int32_t *__restrict__ tinv)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const PosT r = rec[ilist[t]];
+    const int32_t o = r.orig;
+    x[o] = r.x;
+    y[o] = r.y;
+    z[o] = r.z;
+    tinv[o] = (int32_t)t;
 }
 
 // Reference positions of a list build: xr = (x, y, z) in one pass.
@@ -162,21 +181,32 @@ __global__ void k_save_reference(int64_t n, const double *__restrict__ x,
 }
 
 // Into sorted order: velocities and list-build reference positions of the
-// interior records by compact index.  from_rec: the records still hold the
-// build positions, which then serve as the reference (no gather).
+// interior records by compact index (velocities as x, y, z triples).
+// Velocities come from caller order (vx, vy, vz) or, after a rebuild, from
+// the previous compact order through tinv (vprev).  from_rec: the records
+// still hold the build positions, which then serve as the reference (no
+// gather).
 __global__ void k_enter_sorted(int64_t n, const int32_t *__restrict__ ilist,
                                const PosT *__restrict__ rec, const double *__restrict__ vx,
                                const double *__restrict__ vy, const double *__restrict__ vz,
-                               const double *__restrict__ xr, int from_rec,
-                               double *__restrict__ vs, double *__restrict__ xrs)
+                               const int32_t *__restrict__ tinv,
+                               const double *__restrict__ vprev, const double *__restrict__ xr,
+                               int from_rec, double *__restrict__ vs, double *__restrict__ xrs)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const PosT r = rec[ilist[t]];
     const int32_t o = r.orig;
-    vs[t] = vx[o];
-    vs[n + t] = vy[o];
-    vs[2 * n + t] = vz[o];
+    if (vprev) {
+        const int64_t q = tinv[o];
+        vs[3 * t] = vprev[3 * q];
+        vs[3 * t + 1] = vprev[3 * q + 1];
+        vs[3 * t + 2] = vprev[3 * q + 2];
+    } else {
+        vs[3 * t] = vx[o];
+        vs[3 * t + 1] = vy[o];
+        vs[3 * t + 2] = vz[o];
+    }
     xrs[t] = from_rec ? r.x : xr[o];
     xrs[n + t] = from_rec ? r.y : xr[n + o];
     xrs[2 * n + t] = from_rec ? r.z : xr[2 * n + o];
@@ -197,9 +227,23 @@ __global__ void k_leave_sorted(int64_t n, const int32_t *__restrict__ ilist,
     x[o] = r.x;
     y[o] = r.y;
     z[o] = r.z;
-    vx[o] = vs[t];
-    vy[o] = vs[n + t];
-    vz[o] = vs[2 * n + t];
+    vx[o] = vs[3 * t];
+    vy[o] = vs[3 * t + 1];
+    vz[o] = vs[3 * t + 2];
+}
+
+// Back to caller order from the previous compact order (the positions are
+// there already): v[o] = vs[tinv[o]].
+__global__ void k_leave_velocities(int64_t n, const int32_t *__restrict__ tinv,
+                                   const double *__restrict__ vs, double *__restrict__ vx,
+                                   double *__restrict__ vy, double *__restrict__ vz)
+{
+    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    const int64_t q = tinv[o];
+    vx[o] = vs[3 * q];
+    vy[o] = vs[3 * q + 1];
+    vz[o] = vs[3 * q + 2];
 }
 
 // The displacement flag of the last integrator step goes to the host word
@@ -407,26 +451,52 @@ static mdlj_status enter_sorted(mdlj_ctx *ctx)
 {
     const int64_t n = ctx->n;
     STCHK(ensure(ctx, ctx->b_vsort, sizeof(double) * 3 * n));
+    STCHK(ensure(ctx, ctx->b_vsort2, sizeof(double) * 3 * n));
     STCHK(ensure(ctx, ctx->b_xrsort, sizeof(double) * 3 * n));
+    const bool carry = ctx->vs_old_order;
     k_enter_sorted<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
         n, (const int32_t *)ctx->b_ilist.p, (const PosT *)ctx->b_sorted.p, ctx->vv_v[0],
-        ctx->vv_v[1], ctx->vv_v[2], (const double *)ctx->b_xref.p, ctx->rec_at_build ? 1 : 0,
-        (double *)ctx->b_vsort.p, (double *)ctx->b_xrsort.p);
+        ctx->vv_v[1], ctx->vv_v[2], (const int32_t *)ctx->b_tinv.p,
+        carry ? (const double *)ctx->b_vsort.p : nullptr, (const double *)ctx->b_xref.p,
+        ctx->rec_at_build ? 1 : 0, (double *)ctx->b_vsort2.p, (double *)ctx->b_xrsort.p);
     HIPCHK(ctx, hipGetLastError());
+    std::swap(ctx->b_vsort, ctx->b_vsort2);
+    ctx->vs_old_order = false;
     ctx->sorted_active = true;
     return MDLJ_OK;
 }
 
 mdlj_status leave_sorted(mdlj_ctx *ctx)
 {
-    if (!ctx->sorted_active) return MDLJ_OK;
-    ctx->sorted_active = false;
     const int64_t n = ctx->n;
-    k_leave_sorted<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
-        n, (const int32_t *)ctx->b_ilist.p, (const PosT *)ctx->b_sorted.p,
-        (const double *)ctx->b_vsort.p, ctx->x, ctx->y, ctx->z, ctx->vv_v[0], ctx->vv_v[1],
-        ctx->vv_v[2]);
+    if (ctx->sorted_active) {
+        ctx->sorted_active = false;
+        k_leave_sorted<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
+            n, (const int32_t *)ctx->b_ilist.p, (const PosT *)ctx->b_sorted.p,
+            (const double *)ctx->b_vsort.p, ctx->x, ctx->y, ctx->z, ctx->vv_v[0], ctx->vv_v[1],
+            ctx->vv_v[2]);
+        HIPCHK(ctx, hipGetLastError());
+    } else if (ctx->vs_old_order) {
+        ctx->vs_old_order = false;
+        k_leave_velocities<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
+            n, (const int32_t *)ctx->b_tinv.p, (const double *)ctx->b_vsort.p, ctx->vv_v[0],
+            ctx->vv_v[1], ctx->vv_v[2]);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    return MDLJ_OK;
+}
+
+mdlj_status positions_for_rebuild(mdlj_ctx *ctx)
+{
+    if (!ctx->sorted_active) return MDLJ_OK;
+    const int64_t n = ctx->n;
+    STCHK(ensure(ctx, ctx->b_tinv, sizeof(int32_t) * n));
+    ctx->sorted_active = false;
+    k_leave_positions<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
+        n, (const int32_t *)ctx->b_ilist.p, (const PosT *)ctx->b_sorted.p, ctx->x, ctx->y, ctx->z,
+        (int32_t *)ctx->b_tinv.p);
     HIPCHK(ctx, hipGetLastError());
+    ctx->vs_old_order = true;
     return MDLJ_OK;
 }
 
@@ -487,13 +557,16 @@ static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, do
             continue;
         }
         if (s + 1 < nsteps && ctx->sorted_active) {
-            // the next force call rebuilds the lists from caller order
+            // the next force call rebuilds the lists from caller-order
+            // positions; the velocities wait in the old compact order
+            STCHK(ensure(ctx, ctx->b_tinv, sizeof(int32_t) * n));
             ctx->sorted_active = false;
             k_kick_leave<<<nb, TB, 0, ctx->stream>>>(
                 n, (const int32_t *)ctx->b_ilist.p, (const PosT *)ctx->b_sorted.p,
-                (const double *)ctx->b_vsort.p, fo.fx, fo.fy, fo.fz, im, dt, ctx->x, ctx->y,
-                ctx->z, vx, vy, vz);
+                (double *)ctx->b_vsort.p, fo.fx, fo.fy, fo.fz, im, dt, ctx->x, ctx->y, ctx->z,
+                (int32_t *)ctx->b_tinv.p);
             HIPCHK(ctx, hipGetLastError());
+            ctx->vs_old_order = true;
             continue;
         }
         STCHK(leave_sorted(ctx));

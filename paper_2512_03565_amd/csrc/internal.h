@@ -92,12 +92,17 @@ struct mdlj_ctx {
     // displacement flag for the current positions (Verlet lists only)
     bool upkeep_fused = false;
     // Between Verlet-list rebuilds the integrator keeps its state in sorted
-    // order: positions in the interior sorted records, velocities and the
-    // list-build reference positions by compact sorted index (b_vsort,
-    // b_xrsort, SoA).  While sorted_active the caller-order positions and
-    // the velocity arrays of the running step call (vv_v) are behind; they
-    // are written back before a rebuild and when the call returns.
+    // order: positions in the interior sorted records, velocities (x, y, z
+    // triples) and the list-build reference positions (SoA) by compact
+    // sorted index (b_vsort, b_xrsort).  While sorted_active the
+    // caller-order positions and the velocity arrays of the running step
+    // call (vv_v) are behind.  A rebuild gets caller-order positions and
+    // tinv (caller index -> compact index); the velocities stay in the old
+    // compact order (vs_old_order) until the next sorted step carries them
+    // into the new one.  The call brings the caller's arrays up to date
+    // before it returns.
     bool sorted_active = false;
+    bool vs_old_order = false;
     double *vv_v[3] = {nullptr, nullptr, nullptr};
     // the interior sorted records still hold the positions of the last list
     // build (equal to the saved reference positions)
@@ -127,7 +132,7 @@ struct mdlj_ctx {
     DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
         b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart, b_vsort,
-        b_xrsort;
+        b_vsort2, b_xrsort, b_tinv;
     int64_t nhalo = 0;            // entries of b_halo
     int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 
@@ -229,8 +234,11 @@ mdlj_status finish_fused_upkeep(mdlj_ctx *ctx);
 mdlj_status build_halo_list(mdlj_ctx *ctx);
 mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt, int nsteps);
 // Write the sorted-order integrator state back to the caller-order
-// positions and velocities (no-op unless ctx->sorted_active).
+// positions and velocities (no-op without such state).
 mdlj_status leave_sorted(mdlj_ctx *ctx);
+// Before a rebuild: caller-order positions from the sorted state, the
+// velocities kept for the next sorted step (no-op without such state).
+mdlj_status positions_for_rebuild(mdlj_ctx *ctx);
 
 // --- force evaluation (api.cpp) ---------------------------------------------
 // Bring the neighbour structure of c up to date for the current positions.
