@@ -366,70 +366,94 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
 #pragma unroll
     for (int q = 0; q < STAGE_K - 1; ++q) cs[q] = q + 1 < ncx ? rs[4][q + 2] : INT_MAX;
     int32_t wmax = 0;
-    for (int i = ib + wv; i < ie; i += NW) {
-        const int own = seg_c[4] + (i - rs[4][0]);
-        int c = 0;
+    // The wavefront's i's are ib + wv + NW k.  Their set-up (staged index,
+    // candidate list, coordinates) is done for up to 64 of them at once, one
+    // per lane, and read back one i at a time with readlane.
+    for (int i0 = ib + wv; i0 < ie; i0 += NW * MDLJ_WAVE) {
+        const int il = i0 + NW * lane;
+        int own_l = 0, pb_l = 0, pe_l = 0, oi_l = 0;
+        double xl = 0.0, yl = 0.0, zl = 0.0;
+        if (il < ie) {
+            own_l = seg_c[4] + (il - rs[4][0]);
+            int c = 0;
 #pragma unroll
-        for (int q = 0; q < STAGE_K - 1; ++q) c += i >= cs[q];
-        // i's half of its cell (row 4, row cell c + 1)
-        const int hq = 2 * c + ((trim && i >= hs[4][c + 1]) ? 1 : 0);
-        const double *di = srec + RW * own;
-        const double xi = di[0], yi = di[1], zi = di[2];
-        const int32_t oi = HALF ? sorig[own] : 0;
-        const int pb = nc[hq], pe = nc[hq + 1];
-        const int64_t t = t0 + (i - ib);
-        uint16_t *row16 = (uint16_t *)nbr_out + t * cap;
-        int32_t *row32 = (int32_t *)nbr_out + (ELL ? t : t * cap);
-        uint32_t cnt = 0;
-        // two trips of 64 candidates in flight; every lane reads a valid
-        // index (slack entries are 0), lanes past the list are masked
-        for (int p0 = pb; p0 < pe; p0 += 2 * MDLJ_WAVE) {
-            const int rem = pe - p0;
-            const int ka = cand[p0 + lane];
-            const int kb = cand[p0 + MDLJ_WAVE + lane];
-            const double *da = srec + RW * ka;
-            const double *db = srec + RW * kb;
-            const double ax = xi - da[0], ay = yi - da[1], az = zi - da[2];
-            const double bx = xi - db[0], by = yi - db[1], bz = zi - db[2];
-            bool ha = (lane < rem) & (ka != own) & (ax * ax + ay * ay + az * az < rl2);
-            bool hb = (lane + MDLJ_WAVE < rem) & (kb != own) & (bx * bx + by * by + bz * bz < rl2);
-            if (HALF) {
-                ha &= sorig[ka] > oi;
-                hb &= sorig[kb] > oi;
-            }
-            const uint64_t ma = __builtin_amdgcn_ballot_w64(ha);
-            const uint64_t mb = __builtin_amdgcn_ballot_w64(hb);
-            const uint32_t na = (uint32_t)__builtin_popcountll(ma);
-            const uint32_t qa = __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)ma, cnt));
-            const uint32_t qb = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, cnt + na));
-            // row-major rows have slack after the last row, so an overlong row
-            // only spills into its neighbours (the host then rebuilds with a
-            // larger capacity); column-major rows must stop at cap
-            if (LOCAL) {
-                if (ha) row16[qa] = (uint16_t)ka;
-                if (hb) row16[qb] = (uint16_t)kb;
-            } else if (!ELL) {
-                if (ha) row32[qa] = sslot[ka];
-                if (hb) row32[qb] = sslot[kb];
-            } else {
-                if (ha && qa < (uint32_t)cap) row32[(int64_t)qa * n] = sslot[ka];
-                if (hb && qb < (uint32_t)cap) row32[(int64_t)qb * n] = sslot[kb];
-            }
-            cnt += na + (uint32_t)__builtin_popcountll(mb);
+            for (int q = 0; q < STAGE_K - 1; ++q) c += il >= cs[q];
+            // i's half of its cell (row 4, row cell c + 1)
+            const int hq = 2 * c + ((trim && il >= hs[4][c + 1]) ? 1 : 0);
+            const double *di = srec + RW * own_l;
+            xl = di[0];
+            yl = di[1];
+            zl = di[2];
+            oi_l = HALF ? sorig[own_l] : 0;
+            pb_l = nc[hq];
+            pe_l = nc[hq + 1];
         }
-        // padding up to a multiple of 8 entries: at most 7, one per lane
-        const int32_t pe8 = min((int32_t)((cnt + 7) & ~7u), cap);
-        const int32_t q = (int32_t)cnt + lane;
-        if (q < pe8) {
-            if (LOCAL)
-                row16[q] = (uint16_t)C;
-            else
-                row32[ELL ? (int64_t)q * n : q] = pad;
+        auto bcast = [](double v, int k) {
+            return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), k),
+                                    __builtin_amdgcn_readlane(__double2loint(v), k));
+        };
+        const int mi = min(MDLJ_WAVE, (ie - i0 + NW - 1) / NW);
+        for (int k = 0; k < mi; ++k) {
+            const int i = i0 + NW * k;
+            const int own = __builtin_amdgcn_readlane(own_l, k);
+            const double xi = bcast(xl, k), yi = bcast(yl, k), zi = bcast(zl, k);
+            const int32_t oi = HALF ? __builtin_amdgcn_readlane(oi_l, k) : 0;
+            const int pb = __builtin_amdgcn_readlane(pb_l, k);
+            const int pe = __builtin_amdgcn_readlane(pe_l, k);
+            const int64_t t = t0 + (i - ib);
+            uint16_t *row16 = (uint16_t *)nbr_out + t * cap;
+            int32_t *row32 = (int32_t *)nbr_out + (ELL ? t : t * cap);
+            uint32_t cnt = 0;
+            // two trips of 64 candidates in flight; every lane reads a valid
+            // index (slack entries are 0), lanes past the list are masked
+            for (int p0 = pb; p0 < pe; p0 += 2 * MDLJ_WAVE) {
+                const int rem = pe - p0;
+                const int ka = cand[p0 + lane];
+                const int kb = cand[p0 + MDLJ_WAVE + lane];
+                const double *da = srec + RW * ka;
+                const double *db = srec + RW * kb;
+                const double ax = xi - da[0], ay = yi - da[1], az = zi - da[2];
+                const double bx = xi - db[0], by = yi - db[1], bz = zi - db[2];
+                bool ha = (lane < rem) & (ka != own) & (ax * ax + ay * ay + az * az < rl2);
+                bool hb = (lane + MDLJ_WAVE < rem) & (kb != own) & (bx * bx + by * by + bz * bz < rl2);
+                if (HALF) {
+                    ha &= sorig[ka] > oi;
+                    hb &= sorig[kb] > oi;
+                }
+                const uint64_t ma = __builtin_amdgcn_ballot_w64(ha);
+                const uint64_t mb = __builtin_amdgcn_ballot_w64(hb);
+                const uint32_t na = (uint32_t)__builtin_popcountll(ma);
+                const uint32_t qa = __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)ma, cnt));
+                const uint32_t qb = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, cnt + na));
+                // row-major rows have slack after the last row, so an overlong row
+                // only spills into its neighbours (the host then rebuilds with a
+                // larger capacity); column-major rows must stop at cap
+                if (LOCAL) {
+                    if (ha) row16[qa] = (uint16_t)ka;
+                    if (hb) row16[qb] = (uint16_t)kb;
+                } else if (!ELL) {
+                    if (ha) row32[qa] = sslot[ka];
+                    if (hb) row32[qb] = sslot[kb];
+                } else {
+                    if (ha && qa < (uint32_t)cap) row32[(int64_t)qa * n] = sslot[ka];
+                    if (hb && qb < (uint32_t)cap) row32[(int64_t)qb * n] = sslot[kb];
+                }
+                cnt += na + (uint32_t)__builtin_popcountll(mb);
+            }
+            // padding up to a multiple of 8 entries: at most 7, one per lane
+            const int32_t pe8 = min((int32_t)((cnt + 7) & ~7u), cap);
+            const int32_t q = (int32_t)cnt + lane;
+            if (q < pe8) {
+                if (LOCAL)
+                    row16[q] = (uint16_t)C;
+                else
+                    row32[ELL ? (int64_t)q * n : q] = pad;
+            }
+            if (lane == 0) len[t] = (int32_t)cnt;
+            wmax = max(wmax, (int32_t)cnt);
         }
-        if (lane == 0) len[t] = (int32_t)cnt;
-        wmax = max(wmax, (int32_t)cnt);
     }
     if (lane == 0) wmx[wv] = wmax;
     __syncthreads();
