@@ -345,6 +345,7 @@ mdlj_status run_force_kernel(mdlj_ctx *ctx, const mdlj_config &c, bool energy, F
     // one slot per record plus the padding record (Newton-3 kernels add
     // zero to it); the padding slot is never read back
     const int64_t stride = ctx->n_ext + 1;
+    ctx->kd_done = false;
     STCHK(ensure(ctx, ctx->b_fsorted, sizeof(double) * 3 * stride));
     double *f = (double *)ctx->b_fsorted.p;
     fo.fx = f;
@@ -389,6 +390,7 @@ mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW, F
     ForceOut fo;
     int64_t nb = 0;
     const bool energy = UW != nullptr;
+    STCHK(kd_prepare(ctx, c, energy));
     if (ctx->timing) HIPCHK(ctx, hipEventRecord(tm.e1, ctx->stream));
     STCHK(run_force_kernel(ctx, c, energy, fo, &nb));
     if (ctx->timing) HIPCHK(ctx, hipEventRecord(tm.e2, ctx->stream));
@@ -398,8 +400,11 @@ mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW, F
         bool far = false;
         STCHK(check_result(ctx, &far));
         if (far) {
+            // a fused integrator step wrote only the second record and
+            // velocity buffers, which are not taken: the step is redone
             STCHK(rebuild(ctx, c));
             rebuilt = true;
+            STCHK(kd_prepare(ctx, c, energy));
             if (ctx->timing) HIPCHK(ctx, hipEventRecord(tm.e1, ctx->stream));
             STCHK(run_force_kernel(ctx, c, energy, fo, &nb));
             if (ctx->timing) HIPCHK(ctx, hipEventRecord(tm.e2, ctx->stream));
@@ -524,7 +529,8 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
                       &ctx->b_pos,     &ctx->b_type,    &ctx->b_force,
                       &ctx->b_cnt_ext, &ctx->b_img,     &ctx->b_icnt,    &ctx->b_ilist,
                       &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo,    &ctx->b_hstart,
-                      &ctx->b_vsort,   &ctx->b_vsort2,  &ctx->b_xrsort,  &ctx->b_tinv};
+                      &ctx->b_vsort,   &ctx->b_vsort2,  &ctx->b_xrsort,  &ctx->b_tinv,
+                      &ctx->b_sorted2};
     for (DevBuf *b : bufs) free_buf(*b);
     delete ctx;
     return MDLJ_OK;

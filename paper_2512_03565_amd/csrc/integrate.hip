@@ -500,6 +500,44 @@ mdlj_status positions_for_rebuild(mdlj_ctx *ctx)
     return MDLJ_OK;
 }
 
+mdlj_status kd_prepare(mdlj_ctx *ctx, const mdlj_config &c, bool energy)
+{
+    const int64_t n = ctx->n;
+    // as for the separate sorted-order step: lists kept for the next step
+    // (the force call counts as a step since the build), and the forces
+    // alone are asked for
+    ctx->kd_go = ctx->kd_req && !energy && c.nbr_algo == MDLJ_NBR_VL && c.staged &&
+                 !c.newton3 && ctx->built && ctx->built_cfg.nbr_algo == MDLJ_NBR_VL &&
+                 ctx->built_cfg.staged && ctx->steps_since_build + 1 < ctx->rebuild_every &&
+                 ctx->b_xref.bytes >= sizeof(double) * 3 * n;
+    if (!ctx->kd_go) return MDLJ_OK;
+    STCHK(ensure_host_flag(ctx));
+    if (!ctx->sorted_active) STCHK(enter_sorted(ctx));
+    return MDLJ_OK;
+}
+
+mdlj_status kd_args(mdlj_ctx *ctx, KickArgs *ka)
+{
+    const int64_t n = ctx->n;
+    STCHK(ensure(ctx, ctx->b_sorted2, sizeof(PosT) * (ctx->n_ext + 1)));
+    int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
+    if (!ctx->dflag_zero) HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+    ctx->dflag_zero = false;
+    ka->rec_out = (PosT *)ctx->b_sorted2.p;
+    ka->vs_in = (const double *)ctx->b_vsort.p;
+    ka->vs_out = (double *)ctx->b_vsort2.p;
+    ka->xrs = (const double *)ctx->b_xrsort.p;
+    ka->flag = flag;
+    const InvMass im = inv_mass(ctx);
+    for (int s = 0; s < MDLJ_MAX_SPECIES; ++s) ka->im[s] = im.v[s];
+    ka->dt = ctx->kd_dt;
+    const double h = 0.5 * ctx->skin;
+    ka->thr2 = h * h;
+    ka->pad_slot = ctx->n_ext;
+    (void)n;
+    return MDLJ_OK;
+}
+
 static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt,
                            int nsteps);
 
@@ -509,6 +547,7 @@ mdlj_status vv_steps(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double d
     ctx->vv_v[1] = vy;
     ctx->vv_v[2] = vz;
     const mdlj_status st = vv_loop(ctx, vx, vy, vz, dt, nsteps);
+    ctx->kd_req = ctx->kd_go = ctx->kd_done = false;
     // on an error mid-loop the caller-order state is still made whole
     const mdlj_status st2 = leave_sorted(ctx);
     ctx->vv_v[0] = ctx->vv_v[1] = ctx->vv_v[2] = nullptr;
@@ -532,7 +571,20 @@ static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, do
     ctx->forces_valid = false;
     for (int s = 0; s < nsteps; ++s) {
         ForceOut fo;
+        // all but the last step may continue in sorted order; the staged
+        // Verlet-list kernel then takes the integrator step itself
+        ctx->kd_req = s + 1 < nsteps;
+        ctx->kd_dt = dt;
         STCHK(forces_internal(ctx, true, nullptr, &fo, false));
+        ctx->kd_req = ctx->kd_go = false;
+        if (ctx->kd_done) {
+            ctx->kd_done = false;
+            std::swap(ctx->b_sorted, ctx->b_sorted2);
+            std::swap(ctx->b_vsort, ctx->b_vsort2);
+            ctx->upkeep_fused = true;
+            ctx->rec_at_build = false;
+            continue;
+        }
         const int32_t *slot_of = (const int32_t *)ctx->b_slot_of.p;
         // lists kept for the next step (and a context with the fused
         // upkeep state): positions, sorted records and the displacement test

@@ -58,6 +58,23 @@ struct ForceOut {
     double *partial;  // [2 * nblocks] or nullptr
 };
 
+// The velocity-Verlet step fused into the staged Verlet-list force kernel.
+// From the forces of x(t) the kernel finishes v(t) and starts the next step
+// for its own particles (half kick, half kick, drift: the arithmetic of the
+// separate sorted-order integrator kernel) and tests their displacement
+// since the list build.  Records and velocities go to second buffers: other
+// workgroups of the same launch still stage the old positions.
+struct KickArgs {
+    PosT *rec_out;          // records after the drift, same slots as the input
+    const double *vs_in;    // velocities by compact index, (x, y, z) triples
+    double *vs_out;
+    const double *xrs;      // list-build reference positions by compact index, SoA
+    int32_t *flag;          // set to 1 when a particle moved more than sqrt(thr2)
+    double im[MDLJ_MAX_SPECIES];  // 1 / mass per species
+    double dt, thr2;
+    int64_t pad_slot;       // the padding record, copied to rec_out as it is
+};
+
 // Device buffers that grow on demand.
 struct DevBuf {
     void *p = nullptr;
@@ -132,7 +149,7 @@ struct mdlj_ctx {
     DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
         b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart, b_vsort,
-        b_vsort2, b_xrsort, b_tinv;
+        b_vsort2, b_xrsort, b_tinv, b_sorted2;
     int64_t nhalo = 0;            // entries of b_halo
     int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 
@@ -171,6 +188,12 @@ struct mdlj_ctx {
     int32_t *d_hflag = nullptr;
     hipEvent_t ev_flag = nullptr;
     bool dflag_zero = false;
+    // fused integrator step: kd_req is set by the integrator around a force
+    // call whose step continues in sorted order (kd_dt its time step);
+    // kd_go is the decision taken for the current configuration after the
+    // structure was made current, kd_done that the force kernel ran fused
+    bool kd_req = false, kd_go = false, kd_done = false;
+    double kd_dt = 0.0;
     double t_force_us = 0, t_build_us = 0;
     int64_t t_nforce = 0, t_nbuild = 0;
     double last_force_us = 0, last_build_us = 0;
@@ -239,6 +262,11 @@ mdlj_status leave_sorted(mdlj_ctx *ctx);
 // Before a rebuild: caller-order positions from the sorted state, the
 // velocities kept for the next sorted step (no-op without such state).
 mdlj_status positions_for_rebuild(mdlj_ctx *ctx);
+// Before a force call that may fuse the integrator step: decide (kd_go)
+// and, if the state is still in caller order, carry it into sorted order.
+mdlj_status kd_prepare(mdlj_ctx *ctx, const mdlj_config &c, bool energy);
+// Arguments of the fused step from the context's current buffers.
+mdlj_status kd_args(mdlj_ctx *ctx, KickArgs *ka);
 
 // --- force evaluation (api.cpp) ---------------------------------------------
 // Bring the neighbour structure of c up to date for the current positions.

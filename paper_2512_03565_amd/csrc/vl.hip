@@ -580,14 +580,36 @@ __device__ __forceinline__ void stage_rows_fx(const PosT *__restrict__ rec, cons
     }
 }
 
-template <typename T, bool E, bool MS, int G, int V>
+// The fused integrator step of one particle (record slot s, compact index
+// t) along axis k from its force component f: v += f dt / (2m) twice (the
+// end of this step and the start of the next) and x += v dt, the
+// expressions of the separate sorted-order step, so trajectories agree bit
+// for bit.  Returns the displacement from the list-build reference.
+__device__ __forceinline__ double kick_drift_axis(const KickArgs &ka,
+                                                  const PosT *__restrict__ rec, int s, int64_t t,
+                                                  int64_t n, int k, double f)
+{
+    const int sp = rec[s].t;
+    // 1/m of the species by selects (no dynamic index into the argument)
+    double im = ka.im[0];
+#pragma unroll
+    for (int q = 1; q < MDLJ_MAX_SPECIES; ++q) im = sp == q ? ka.im[q] : im;
+    const double h = 0.5 * ka.dt * im;
+    const double u = (ka.vs_in[3 * t + k] + h * f) + h * f;
+    ka.vs_out[3 * t + k] = u;
+    const double x = (&rec[s].x)[k] + ka.dt * u;
+    (&ka.rec_out[s].x)[k] = x;
+    return x - ka.xrs[k * n + t];
+}
+
+template <typename T, bool E, bool MS, int G, int V, bool KD>
 __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ rec,
                                                 const int32_t *__restrict__ start,
                                                 const int32_t *__restrict__ ibase, Grid g,
                                                 int tiles_x, const uint16_t *__restrict__ nbr,
                                                 const int32_t *__restrict__ len, int32_t cap,
                                                 int64_t n, int cmax, LJTable<T> tab, ForceOut fo,
-                                                int remap, double fxs)
+                                                int remap, double fxs, KickArgs ka)
 {
     // FP32 pair law: fixed-point staged records; fxs is their scale and tab
     // holds sig^2 fxs^2, 24 eps fxs and rc^2 fxs^2, so that every pair
@@ -605,6 +627,8 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
     const int tid = threadIdx.x;
     const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
     if (MS) lds_table_load(lt, tab, tid, blockDim.x);
+    // fused step: the padding record is carried over to the new records
+    if (KD && blockIdx.x == 0 && tid == 0) ka.rec_out[ka.pad_slot] = rec[ka.pad_slot];
     const int64_t tile = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int tx = (int)((uint32_t)tile % (uint32_t)tiles_x);
     const uint32_t rr = (uint32_t)tile / (uint32_t)tiles_x;
@@ -760,7 +784,18 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
         a.fx = seg_sum(a.fx, SEG);
         a.fy = seg_sum(a.fy, SEG);
         a.fz = seg_sum(a.fz, SEG);
-        if (act && l == 0) {
+        if constexpr (KD) {
+            // lanes 0, 1, 2 of an i's segment step its x, y and z, lane 3
+            // copies species and caller index: one 32-byte record store
+            static_assert(SEG >= 4, "the fused step needs 4 lanes per i");
+            double d = 0.0;
+            if (act && l < 3)
+                d = kick_drift_axis(ka, rec, i, t, n, l, l == 0 ? a.fx : (l == 1 ? a.fy : a.fz));
+            if (act && l == 3)
+                *(int2 *)&ka.rec_out[i].t = *(const int2 *)&rec[i].t;
+            const double dy = __shfl_down(d, 1, SEG), dz = __shfl_down(d, 2, SEG);
+            if (act && l == 0 && !(d * d + dy * dy + dz * dz <= ka.thr2)) atomicOr(ka.flag, 1);
+        } else if (act && l == 0) {
             fo.fx[i] = a.fx;
             fo.fy[i] = a.fy;
             fo.fz[i] = a.fz;
@@ -926,7 +961,7 @@ __global__ __launch_bounds__(256) void k_vl_wpi(const PosT *__restrict__ rec,
 
 template <typename T, bool E, bool MS, bool N3>
 int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, ForceOut &fo,
-                  int remap)
+                  int remap, const KickArgs *kdp)
 {
     const int64_t n = ctx->n;
     const PosT *rec = (const PosT *)ctx->b_sorted.p;
@@ -971,9 +1006,18 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         const int32_t *ibase = (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1;
         const uint16_t *nbr16 = (const uint16_t *)ctx->b_nbr.p;
         const int32_t *start = (const int32_t *)ctx->b_start.p;
-#define VL_LDS(GG, VV)                                                                        \
-    k_vl_lds<T, E, MS, GG, VV><<<nbt, VL_LDS_TB, lds, s>>>(rec, start, ibase, g, tiles_x, nbr16, len, \
-                                                     cap, n, cmax, tx, fo, remap, fxs)
+        const KickArgs none = {};
+        // the fused integrator step only with forces alone (no energies)
+        const bool kd = kdp != nullptr && !E;
+#define VL_LDS(GG, VV)                                                                          \
+    do {                                                                                        \
+        if (kd)                                                                                 \
+            k_vl_lds<T, false, MS, GG, VV, true><<<nbt, VL_LDS_TB, lds, s>>>(                   \
+                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, *kdp); \
+        else                                                                                    \
+            k_vl_lds<T, E, MS, GG, VV, false><<<nbt, VL_LDS_TB, lds, s>>>(                      \
+                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, none); \
+    } while (0)
         const int key = cfg.tile_i * 100 + cfg.tile_j;
         switch (key) {
         case 802: VL_LDS(8, 2); break;
@@ -984,6 +1028,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         default: return -1;
         }
 #undef VL_LDS
+        ctx->kd_done = kd;
         return nbt;
     }
     // 32-bit buffer offsets: records must stay under 2 GiB
@@ -1003,10 +1048,10 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
 
 template <typename T, bool E, bool MS>
 int64_t launch_vl_n3(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, ForceOut &fo,
-                     int remap)
+                     int remap, const KickArgs *kdp)
 {
-    if (cfg.newton3) return launch_vl<T, E, MS, true>(ctx, cfg, tab, fo, remap);
-    return launch_vl<T, E, MS, false>(ctx, cfg, tab, fo, remap);
+    if (cfg.newton3) return launch_vl<T, E, MS, true>(ctx, cfg, tab, fo, remap, kdp);
+    return launch_vl<T, E, MS, false>(ctx, cfg, tab, fo, remap, kdp);
 }
 
 template <typename T>
@@ -1018,16 +1063,23 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
     const bool ms = ctx->nspec > 1;
     const int remap = 1;
     if (cfg.newton3) STCHK(zero_forces(ctx, fo, ctx->n_ext + 1));
+    // the integrator step fused into the staged kernel (decided by kd_prepare)
+    KickArgs ka;
+    const KickArgs *kdp = nullptr;
+    if (ctx->kd_go && cfg.staged && !cfg.newton3 && !energy) {
+        STCHK(kd_args(ctx, &ka));
+        kdp = &ka;
+    }
     int64_t nw;
     if (energy) {
         const int64_t maxw = std::max<int64_t>(ctx->n + 64, ctx->grid.ncell_int);
         STCHK(ensure(ctx, ctx->b_partial, sizeof(double) * 2 * maxw));
         fo.partial = (double *)ctx->b_partial.p;
-        nw = ms ? launch_vl_n3<T, true, true>(ctx, cfg, tab, fo, remap)
-                : launch_vl_n3<T, true, false>(ctx, cfg, tab, fo, remap);
+        nw = ms ? launch_vl_n3<T, true, true>(ctx, cfg, tab, fo, remap, nullptr)
+                : launch_vl_n3<T, true, false>(ctx, cfg, tab, fo, remap, nullptr);
     } else {
-        nw = ms ? launch_vl_n3<T, false, true>(ctx, cfg, tab, fo, remap)
-                : launch_vl_n3<T, false, false>(ctx, cfg, tab, fo, remap);
+        nw = ms ? launch_vl_n3<T, false, true>(ctx, cfg, tab, fo, remap, kdp)
+                : launch_vl_n3<T, false, false>(ctx, cfg, tab, fo, remap, kdp);
     }
     if (nw == -2) return set_err(ctx, MDLJ_ERR_ARG, "neighbourhood too large for LDS staging");
     if (nw == -3) return set_err(ctx, MDLJ_ERR_ARG, "too many records for 32-bit buffer offsets");

@@ -160,14 +160,16 @@ def test_velocity_verlet_fast_particles_force_early_rebuilds(m, orc, cfg):
     assert np.abs(v - v_ref).max() < 1e-8, cfg
 
 
-@pytest.mark.parametrize("prec,cfg", [(0, (1, 2, 16, 4, 0, 0, 1)), (1, (1, 2, 8, 8, 0, 0)),
+@pytest.mark.parametrize("prec,cfg", [(0, (1, 2, 16, 4, 0, 0, 1)), (1, (1, 2, 16, 4, 0, 0, 1)),
+                                      (0, (1, 2, 8, 4, 0, 0, 1)), (1, (1, 2, 8, 8, 0, 0)),
                                       (1, (1, 0, 0, 0, 0, 0))])
 def test_velocity_verlet_one_call_equals_single_steps(m, prec, cfg):
     # Between Verlet-list rebuilds a multi-step call keeps the integrator
     # state in sorted order and writes it back before each rebuild and on
-    # return; one-step calls never enter that state.  The arithmetic is the
-    # same, so 60 steps in one call and 60 calls of one step must agree bit
-    # for bit, over six scheduled rebuilds and the displacement tests.
+    # return (with the staged kernels the force kernel takes the integrator
+    # step itself); one-step calls never enter that state.  The arithmetic is
+    # the same, so 60 steps in one call and 60 calls of one step must agree
+    # bit for bit, over six scheduled rebuilds and the displacement tests.
     import torch
     s = scenes.config2()
     n = len(s["pos"])
@@ -191,6 +193,38 @@ def test_velocity_verlet_one_call_equals_single_steps(m, prec, cfg):
     assert out[0][2] == out[1][2] >= 6, (cfg, out[0][2], out[1][2])
     assert np.array_equal(out[0][0], out[1][0]), cfg
     assert np.array_equal(out[0][1], out[1][1]), cfg
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_velocity_verlet_fused_step_with_early_rebuilds_bitwise(m, prec):
+    # Fast particles cross skin/2 between scheduled rebuilds.  A staged force
+    # call that takes the integrator step itself learns of the crossing only
+    # after its launch; its records and velocities must then be dropped and
+    # the step redone after the rebuild.  One call must still agree bit for
+    # bit with one-step calls, which never fuse.
+    import torch
+    s = scenes.config1()
+    v0 = 15.0 * s["vel"]
+    cfg = (1, 2, 16, 4, 0, 0, 1)
+    out = []
+    for single in (False, True):
+        with m.System(s["pos"], s["box"], s["rc"], skin=0.3, rebuild_every=6,
+                      precision=prec) as sysm:
+            sysm.set_config(cfg)
+            vel = [torch.tensor(np.ascontiguousarray(v0[:, k]), device="cuda") for k in range(3)]
+            sysm.set_timing(True)
+            if single:
+                for _ in range(24):
+                    sysm.step_vv(vel, s["dt"], 1)
+            else:
+                sysm.step_vv(vel, s["dt"], 24)
+            _, _, nf, nb = sysm.get_timing()
+            out.append((sysm.get_positions(), torch.stack(vel, 1).cpu().numpy(), nb, nf))
+    print(f"[fused step, early rebuilds] prec={prec} rebuilds {out[0][2]} / {out[1][2]}, "
+          f"force calls {out[0][3]} / {out[1][3]}", flush=True)
+    assert out[0][2] == out[1][2] >= 6, (out[0][2], out[1][2])  # the schedule alone gives 4
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
 
 
 def test_vl_cells_exactly_list_range_wide(m, orc):
