@@ -100,10 +100,10 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2 };
  * and stages its 27-cell neighbourhood.  VL wave-per-i: a workgroup owns 4
  * consecutive cells along x and stages the 9 rows of 6 cells around them;
  * the Verlet list then holds 16-bit indices into that staged set; with
- * FP32 pair arithmetic its records are staged as 32-bit fixed point
- * relative to the tile centre (12 bytes, exact separations to within the
- * grid 1/s, 1.5e-8 sigma for cells of 2.8 sigma), with all-FP64 as FP64
- * (24 bytes).  A scene whose neighbourhoods do not fit the 64 KB staging
+ * FP32 pair arithmetic its records are kept as 32-bit fixed-point words of
+ * one frame centred on the box (16 bytes with the species in global memory,
+ * 12 in LDS; separations exact to within the grid 1/s, 1.2e-7 sigma for a
+ * box of 175 sigma), with all-FP64 as FP64 (24 bytes).  A scene whose neighbourhoods do not fit the 64 KB staging
  * budget rejects staged configurations with MDLJ_ERR_ARG.  staged = 0 reads
  * every j-particle from global memory.
  */
@@ -252,7 +252,10 @@ mdlj_status mdlj_retune_needed(const float *before8, const float *now8, double t
  * velocities in the context in sorted order (the velocities also across
  * list rebuilds); the caller's arrays and the context's positions are
  * brought up to date before the call returns (also when it returns an
- * error).
+ * error).  With a staged Verlet-list configuration the force kernel takes
+ * the integrator step between rebuilds itself; the trajectory is the same,
+ * bit for bit, and the time of those force calls (mdlj_get_timing)
+ * includes it.
  */
 mdlj_status mdlj_step_vv(mdlj_ctx *ctx, double *vx, double *vy, double *vz, double dt,
                          int32_t nsteps);

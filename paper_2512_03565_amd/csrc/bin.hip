@@ -537,6 +537,7 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
         g, start, unordered, ctx->x, ctx->y, ctx->z, ctx->type, (PosT *)ctx->b_sorted.p,
         (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p, (int32_t *)ctx->b_hstart.p);
     k_pad_record<<<1, 64, 0, s>>>((PosT *)ctx->b_sorted.p, n_ext);
+    ctx->fx_valid = false;
     HIPCHK(ctx, hipGetLastError());
     ctx->grid = g;
     ctx->n_ext = n_ext;

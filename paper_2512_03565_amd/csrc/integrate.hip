@@ -272,7 +272,9 @@ __global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__
                                                       const int32_t *__restrict__ start,
                                                       const char4 *__restrict__ img,
                                                       PosT *__restrict__ rec, double lx, double ly,
-                                                      double lz, int32_t *flag, int32_t *host)
+                                                      double lz, int32_t *flag, int32_t *host,
+                                                      uint4 *__restrict__ fxr, double cx,
+                                                      double cy, double cz, double fs)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_flag(flag, host);
     // HALO_LANES lanes per halo cell (cells hold ~17 records at liquid
@@ -289,6 +291,10 @@ __global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__
         q.y += (double)c.y * ly;
         q.z += (double)c.z * lz;
         rec[b + m] = q;
+        // the images' fixed-point words, when the records have them
+        if (fxr)
+            fxr[b + m] = make_uint4(to_fx(q.x, cx, fs), to_fx(q.y, cy, fs), to_fx(q.z, cz, fs),
+                                    (unsigned)q.t);
     }
 }
 
@@ -387,7 +393,8 @@ mdlj_status finish_fused_upkeep(mdlj_ctx *ctx)
         k_refresh_halo<<<ceil_div(ctx->nhalo, 256 / HALO_LANES), 256, 0, ctx->stream>>>(
             ctx->nhalo, (const int2 *)ctx->b_halo.p, (const int32_t *)ctx->b_start.p,
             (const char4 *)ctx->b_img.p, (PosT *)ctx->b_sorted.p, ctx->box[0], ctx->box[1],
-            ctx->box[2], flag, ctx->d_hflag);
+            ctx->box[2], flag, ctx->d_hflag, ctx->fx_valid ? (uint4 *)ctx->b_fxrec.p : nullptr,
+            ctx->fx_c[0], ctx->fx_c[1], ctx->fx_c[2], ctx->fx_s);
     } else {
         k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag);
     }
@@ -433,6 +440,7 @@ mdlj_status build_halo_list(mdlj_ctx *ctx)
 mdlj_status refresh_records(mdlj_ctx *ctx)
 {
     ctx->rec_at_build = false;
+    ctx->fx_valid = false;
     k_refresh<<<ceil_div(ctx->n_ext, 256), 256, 0, ctx->stream>>>(
         ctx->n_ext, (PosT *)ctx->b_sorted.p, (const char4 *)ctx->b_img.p, ctx->x, ctx->y, ctx->z,
         ctx->box[0], ctx->box[1], ctx->box[2]);
@@ -581,6 +589,13 @@ static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, do
             ctx->kd_done = false;
             std::swap(ctx->b_sorted, ctx->b_sorted2);
             std::swap(ctx->b_vsort, ctx->b_vsort2);
+            // the FP32-pair kernel wrote the interior records' fixed-point
+            // words too (the halo refresh adds the images'); the FP64 one
+            // did not
+            if (ctx->kd_fx)
+                std::swap(ctx->b_fxrec, ctx->b_fxrec2);
+            else
+                ctx->fx_valid = false;
             ctx->upkeep_fused = true;
             ctx->rec_at_build = false;
             continue;
@@ -605,6 +620,7 @@ static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, do
                 (const double *)ctx->b_xrsort.p, h * h, flag);
             ctx->upkeep_fused = true;
             ctx->rec_at_build = false;
+            ctx->fx_valid = false;
             HIPCHK(ctx, hipGetLastError());
             continue;
         }

@@ -484,6 +484,7 @@ mdlj_status vcl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
     HIPCHK(ctx, hipGetLastError());
     // swap: the force path reads b_sorted as the record array
     std::swap(ctx->b_sorted, ctx->b_clu);
+    ctx->fx_valid = false;
     ctx->n_ext = nslot;
     STCHK(ensure(ctx, ctx->b_img, sizeof(char4) * (nslot > 0 ? nslot : 1)));
     HIPCHK(ctx, hipMemsetAsync(ctx->b_img.p, 0, sizeof(char4) * (nslot > 0 ? nslot : 1), s));

@@ -512,28 +512,32 @@ typedef __attribute__((address_space(3))) const double lds_cdouble;
 typedef __attribute__((address_space(3))) const int lds_cint;
 typedef __attribute__((address_space(3))) const unsigned lds_cuint;
 
-// Fixed-point frame of the FP32-pair staged kernel.  A staged record is
-// {x, y, z, species} in 32 bits: the coordinate relative to the tile centre
-// times s (a power of two), rounded, plus 2^31.  Paired with the high word
-// 0x43300000 such a word is the binary64 number 2^52 + word, so the
-// difference of two of them is the exact integer separation, formed by the
-// same FP64 subtraction as for FP64 coordinates and with no conversion
-// instruction.  What is given up is the rounding of each coordinate to the
-// grid 1/s (s is chosen so that the staged neighbourhood reaches less than
-// 2^30 steps from the tile centre: 1/s is 1.5e-8 for cells of 2.8 sigma),
-// far below the FP32 pair law's own rounding.  A record takes 12 bytes of
-// LDS instead of 24, so more workgroups fit on a compute unit.
-__device__ __forceinline__ unsigned to_fx(double v, double o, double s)
-{
-    // the clamp keeps the conversion defined for a particle that has run
-    // far off (the force call is then repeated after a rebuild)
-    const double q = fmin(fmax(rint((v - o) * s), -2.0e9), 2.0e9);
-    return (unsigned)(int)q ^ 0x80000000u;
-}
-
+// Fixed-point layout of the FP32-pair staged kernel: a staged record is
+// {x, y, z} as 32-bit words (to_fx) of one frame for the whole grid, its
+// species apart.  The separation of two records is the exact integer
+// difference of their words, formed by the same FP64 subtraction as for
+// FP64 coordinates and with no conversion instruction.  What is given up is
+// the rounding of each coordinate to the grid 1/s (s is chosen so that every
+// record, halo images included, stays within 2^30 steps of the centre: 1/s
+// is 1.2e-7 sigma for a box of 175 sigma), below the FP32 pair law's own
+// rounding.  The words are kept in global memory, 16 bytes per record with
+// the species, so that staging reads half the bytes of the FP64 records, and
+// a staged record takes 12 bytes of LDS instead of 24.
 __device__ __forceinline__ double fx_value(unsigned w)
 {
     return __hiloint2double(0x43300000, (int)w);
+}
+
+// Fixed-point copy of the records for the FP32-pair staged kernel: x, y, z
+// as words of one frame for the whole grid (centre c, scale s) and the
+// species, 16 bytes per record.
+__global__ void k_fx_records(int64_t nrec, const PosT *__restrict__ rec, double cx, double cy,
+                             double cz, double s, uint4 *__restrict__ fxr)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nrec) return;
+    const PosT p = rec[k];
+    fxr[k] = make_uint4(to_fx(p.x, cx, s), to_fx(p.y, cy, s), to_fx(p.z, cz, s), (unsigned)p.t);
 }
 
 // the padding record: word 0 on every axis (coordinate -2^31), at least
@@ -542,74 +546,71 @@ __device__ __forceinline__ double fx_value(unsigned w)
 constexpr unsigned FX_PAD = 0u;
 
 // Staging of the fixed-point layout: record k of the nine concatenated rows
-// (four per thread in flight, rows found without branches as in stage_rows).
-__device__ __forceinline__ void stage_rows_fx(const PosT *__restrict__ rec, const int *seg_b,
+// from the fixed-point record array (four per thread in flight, rows found
+// without branches as in stage_rows).
+__device__ __forceinline__ void stage_rows_fx(const uint4 *__restrict__ fxr, const int *seg_b,
                                               const int *seg_c, int C, unsigned *sd, int *st,
-                                              bool types, double ox, double oy, double oz,
-                                              double s, int tid, int nthr)
+                                              bool types, int tid, int nthr)
 {
     constexpr int U = 4;
     int c[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) c[q] = seg_c[q + 1];
     for (int k0 = tid; k0 < C; k0 += U * nthr) {
-        unsigned x[U], y[U], z[U];
-        int t[U];
+        uint4 w[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = min(k0 + u * nthr, C - 1);
             int r = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) r += k >= c[q];
-            const PosT *p = rec + seg_b[r] + (k - seg_c[r]);
-            x[u] = to_fx(p->x, ox, s);
-            y[u] = to_fx(p->y, oy, s);
-            z[u] = to_fx(p->z, oz, s);
-            t[u] = types ? p->t : 0;
+            w[u] = fxr[seg_b[r] + (k - seg_c[r])];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k0 + u * nthr;
             if (k < C) {
-                sd[3 * k] = x[u];
-                sd[3 * k + 1] = y[u];
-                sd[3 * k + 2] = z[u];
-                if (types) st[k] = t[u];
+                sd[3 * k] = w[u].x;
+                sd[3 * k + 1] = w[u].y;
+                sd[3 * k + 2] = w[u].z;
+                if (types) st[k] = (int)w[u].w;
             }
         }
     }
 }
 
 // The fused integrator step of one particle (record slot s, compact index
-// t) along axis k from its force component f: v += f dt / (2m) twice (the
-// end of this step and the start of the next) and x += v dt, the
+// t) along axis k from its force component f, given the axis coordinate x,
+// velocity v and list-build reference xr and the species sp: v += f dt / (2m)
+// twice (the end of this step and the start of the next) and x += v dt, the
 // expressions of the separate sorted-order step, so trajectories agree bit
-// for bit.  Returns the displacement from the list-build reference.
-__device__ __forceinline__ double kick_drift_axis(const KickArgs &ka,
-                                                  const PosT *__restrict__ rec, int s, int64_t t,
-                                                  int64_t n, int k, double f)
+// for bit.  Returns the displacement from the reference.
+template <bool FX>
+__device__ __forceinline__ double kick_drift_axis(const KickArgs &ka, int s, int64_t t, int k,
+                                                  double f, double x, double v, double xr, int sp)
 {
-    const int sp = rec[s].t;
     // 1/m of the species by selects (no dynamic index into the argument)
     double im = ka.im[0];
 #pragma unroll
     for (int q = 1; q < MDLJ_MAX_SPECIES; ++q) im = sp == q ? ka.im[q] : im;
     const double h = 0.5 * ka.dt * im;
-    const double u = (ka.vs_in[3 * t + k] + h * f) + h * f;
+    const double u = (v + h * f) + h * f;
     ka.vs_out[3 * t + k] = u;
-    const double x = (&rec[s].x)[k] + ka.dt * u;
-    (&ka.rec_out[s].x)[k] = x;
-    return x - ka.xrs[k * n + t];
+    const double y = x + ka.dt * u;
+    (&ka.rec_out[s].x)[k] = y;
+    if (FX) ((unsigned *)&ka.fxr_out[s])[k] = to_fx(y, ka.fx_c[k], ka.fx_s);
+    return y - xr;
 }
 
 template <typename T, bool E, bool MS, int G, int V, bool KD>
-__global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ rec,
-                                                const int32_t *__restrict__ start,
-                                                const int32_t *__restrict__ ibase, Grid g,
-                                                int tiles_x, const uint16_t *__restrict__ nbr,
-                                                const int32_t *__restrict__ len, int32_t cap,
-                                                int64_t n, int cmax, LJTable<T> tab, ForceOut fo,
-                                                int remap, double fxs, KickArgs ka)
+__device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
+                                            const int32_t *__restrict__ start,
+                                            const int32_t *__restrict__ ibase, const Grid &g,
+                                            int tiles_x, const uint16_t *__restrict__ nbr,
+                                            const int32_t *__restrict__ len, int32_t cap,
+                                            int64_t n, int cmax, const LJTable<T> &tab,
+                                            const ForceOut &fo, int remap, double fxs,
+                                            const uint4 *__restrict__ fxr, const KickArgs &ka)
 {
     // FP32 pair law: fixed-point staged records; fxs is their scale and tab
     // holds sig^2 fxs^2, 24 eps fxs and rc^2 fxs^2, so that every pair
@@ -628,7 +629,10 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
     const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
     if (MS) lds_table_load(lt, tab, tid, blockDim.x);
     // fused step: the padding record is carried over to the new records
-    if (KD && blockIdx.x == 0 && tid == 0) ka.rec_out[ka.pad_slot] = rec[ka.pad_slot];
+    if (KD && blockIdx.x == 0 && tid == 0) {
+        ka.rec_out[ka.pad_slot] = rec[ka.pad_slot];
+        if (FX) ka.fxr_out[ka.pad_slot] = fxr[ka.pad_slot];
+    }
     const int64_t tile = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int tx = (int)((uint32_t)tile % (uint32_t)tiles_x);
     const uint32_t rr = (uint32_t)tile / (uint32_t)tiles_x;
@@ -665,7 +669,32 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
     int i = i0 + lane / SEG;
     bool act = i < ie;
     int64_t t = t0 + (act ? i - ib : 0);
-    PosT pi = rec[act ? i : ib];
+    // i's record: FP64 coordinates and species, or (fixed point) the words
+    // and species
+    PosT pi;
+    uint4 qi;
+    auto load_i = [&](int k) {
+        if constexpr (FX)
+            qi = fxr[k];
+        else
+            pi = rec[k];
+    };
+    load_i(act ? i : ib);
+    // fused step: lane l of an i's segment needs word l & 3 of its record
+    // (x, y, z, or species and caller index) and, for l < 3, that axis's
+    // velocity and reference position; requested with the i-group's other
+    // loads, so that their latency overlaps the pair loop
+    double kx = 0.0, kv = 0.0, kr = 0.0;
+    auto load_kd = [&]() {
+        if constexpr (KD) {
+            const int lk = l & 3, la = min(lk, 2);
+            const int64_t ts = min(t, n - 1);
+            kx = ((const double *)(rec + (act ? i : ib)))[lk];
+            kv = ka.vs_in[3 * ts + la];
+            kr = ka.xrs[la * n + ts];
+        }
+    };
+    load_kd();
     int32_t L = len[min(t, n - 1)];
     L = act ? L : 0;
     uint32_t vo = (uint32_t)(((t - t0) * cap + V * l) * 2);
@@ -687,12 +716,8 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
     // st2[k]
     unsigned *sd = (unsigned *)stage;
     int *st2 = (int *)(sd + 3 * cmax);
-    // tile centre of the fixed-point frame
-    const double ox = (cx0 + 0.5 * STAGE_K) * g.edge[0];
-    const double oy = (cy + 0.5) * g.edge[1];
-    const double oz = (cz + 0.5) * g.edge[2];
     if constexpr (FX) {
-        stage_rows_fx(rec, seg_b, seg_c, C, sd, st2, MS, ox, oy, oz, fxs, tid, blockDim.x);
+        stage_rows_fx(fxr, seg_b, seg_c, C, sd, st2, MS, tid, blockDim.x);
         if (tid == 0) {
             sd[3 * C] = sd[3 * C + 1] = sd[3 * C + 2] = FX_PAD;
             if (MS) st2[C] = 0;
@@ -708,28 +733,35 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
     // LDS byte addresses of the staged coordinates and species
     const uint32_t xb = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) double *)sp;
     const uint32_t tb = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) int *)(FX ? st2 : st);
-    // i's coordinates in the frame of its staged partners
-    auto frame = [&](const PosT &q, double &x, double &y, double &z) {
+    // i's coordinates in the frame of its staged partners, and its species
+    auto frame = [&](double &x, double &y, double &z) {
         if constexpr (FX) {
-            x = fx_value(to_fx(q.x, ox, fxs));
-            y = fx_value(to_fx(q.y, oy, fxs));
-            z = fx_value(to_fx(q.z, oz, fxs));
+            x = fx_value(qi.x);
+            y = fx_value(qi.y);
+            z = fx_value(qi.z);
         } else {
-            x = q.x;
-            y = q.y;
-            z = q.z;
+            x = pi.x;
+            y = pi.y;
+            z = pi.z;
         }
     };
+    auto species_i = [&]() -> int {
+        if constexpr (FX)
+            return (int)qi.w;
+        else
+            return pi.t;
+    };
     double xi, yi, zi;
-    frame(pi, xi, yi, zi);
+    frame(xi, yi, zi);
     double bu = 0.0, bw = 0.0;
     for (bool first = true; i0 < ie; i0 += NW * G, first = false) {
         if (!first) {
             i = i0 + lane / SEG;
             act = i < ie;
             t = t0 + (act ? i - ib : 0);
-            pi = rec[act ? i : ib];
-            frame(pi, xi, yi, zi);
+            load_i(act ? i : ib);
+            load_kd();
+            frame(xi, yi, zi);
             L = len[min(t, n - 1)];
             L = act ? L : 0;
             vo = (uint32_t)(((t - t0) * cap + V * l) * 2);
@@ -753,7 +785,7 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
                         tj = *(lds_cint *)(uintptr_t)at;
                     }
                     lds_cuint *q = (lds_cuint *)(uintptr_t)ad;
-                    const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, tj);
+                    const PairP<T> p = pair_params<T, MS>(tab, lt, species_i(), tj);
                     lj_pair<T, E>(xi, yi, zi, fx_value(q[0]), fx_value(q[1]), fx_value(q[2]),
                                   true, p, rc2, a, fxp, fyp, fzp);
                 } else {
@@ -765,7 +797,7 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
                                                     : mad16<false, 4>(w[u >> 1], tb);
                         tj = *(lds_cint *)(uintptr_t)at;
                     }
-                    const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, tj);
+                    const PairP<T> p = pair_params<T, MS>(tab, lt, species_i(), tj);
                     lds_cdouble *q = (lds_cdouble *)(uintptr_t)ad;
                     lj_pair<T, E>(xi, yi, zi, q[0], q[1], q[2], true, p, rc2, a, fxp, fyp, fzp);
                 }
@@ -790,9 +822,12 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
             static_assert(SEG >= 4, "the fused step needs 4 lanes per i");
             double d = 0.0;
             if (act && l < 3)
-                d = kick_drift_axis(ka, rec, i, t, n, l, l == 0 ? a.fx : (l == 1 ? a.fy : a.fz));
-            if (act && l == 3)
-                *(int2 *)&ka.rec_out[i].t = *(const int2 *)&rec[i].t;
+                d = kick_drift_axis<FX>(ka, i, t, l, l == 0 ? a.fx : (l == 1 ? a.fy : a.fz), kx,
+                                        kv, kr, species_i());
+            if (act && l == 3) {
+                ((double *)(ka.rec_out + i))[3] = kx;
+                if (FX) ((unsigned *)&ka.fxr_out[i])[3] = (unsigned)species_i();
+            }
             const double dy = __shfl_down(d, 1, SEG), dz = __shfl_down(d, 2, SEG);
             if (act && l == 0 && !(d * d + dy * dy + dz * dz <= ka.thr2)) atomicOr(ka.flag, 1);
         } else if (act && l == 0) {
@@ -825,6 +860,31 @@ __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(const PosT *__restrict__ r
         }
     }
 }
+
+#define VL_LDS_PARAMS                                                                            \
+    const PosT *__restrict__ rec, const int32_t *__restrict__ start,                            \
+        const int32_t *__restrict__ ibase, Grid g, int tiles_x, const uint16_t *__restrict__ nbr, \
+        const int32_t *__restrict__ len, int32_t cap, int64_t n, int cmax, LJTable<T> tab,      \
+        ForceOut fo, int remap, double fxs, const uint4 *__restrict__ fxr, KickArgs ka
+
+template <typename T, bool E, bool MS, int G, int V, bool KD>
+__global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(VL_LDS_PARAMS)
+{
+    vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, len, cap, n, cmax, tab, fo,
+                                    remap, fxs, fxr, ka);
+}
+
+// The same, held to 64 registers so that eight wavefronts share a SIMD:
+// for the FP32-pair fused step, whose prefetched operands would otherwise
+// cost two of them (taken only where the cap causes no spills).
+template <typename T, bool E, bool MS, int G, int V, bool KD>
+__global__ __launch_bounds__(VL_LDS_TB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
+k_vl_lds_w8(VL_LDS_PARAMS)
+{
+    vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, len, cap, n, cmax, tab, fo,
+                                    remap, fxs, fxr, ka);
+}
+#undef VL_LDS_PARAMS
 
 // i-per-lane over ELL lists.
 template <typename T, bool E, bool MS, bool N3>
@@ -984,14 +1044,35 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         const size_t lds = (size_t)cmax * ((FX ? 3 * sizeof(unsigned) : 3 * sizeof(double)) +
                                            (MS ? sizeof(int) : 0));
         if (lds > (size_t)STAGE_LDS_BYTES || N3) return -2;
-        // fixed-point scale: the staged neighbourhood of a tile reaches
-        // STAGE_K / 2 + 1 cells from its centre along x and 3/2 cells along y
-        // and z; with rc + skin more for particles that drift before a
-        // rebuild, it must stay within 2^30 steps
-        const double reach = std::max({0.5 * (STAGE_K + 2) * g.edge[0], 1.5 * g.edge[1],
-                                       1.5 * g.edge[2]}) +
-                             ctx->rc + ctx->skin;
+        // fixed-point frame: centred on the box, records (with the halo
+        // images, one cell beyond the box) plus rc + skin for particles that
+        // drift before a rebuild within 2^30 steps of the centre
+        double reach = 0.0;
+        for (int a = 0; a < 3; ++a)
+            reach = std::max(reach, 0.5 * g.L[a] + g.h[a] * g.edge[a]);
+        reach += ctx->rc + ctx->skin;
         const double fxs = FX ? std::exp2(std::floor(std::log2(1073741824.0 / reach))) : 1.0;
+        const uint4 *fxr = nullptr;
+        KickArgs kk = {};
+        if (kdp) kk = *kdp;
+        if (FX) {
+            const double c[3] = {0.5 * g.L[0], 0.5 * g.L[1], 0.5 * g.L[2]};
+            if (!ctx->fx_valid || ctx->fx_s != fxs || memcmp(ctx->fx_c, c, sizeof c) != 0) {
+                if (ensure(ctx, ctx->b_fxrec, sizeof(uint4) * nrec) != MDLJ_OK) return -4;
+                k_fx_records<<<ceil_div(nrec, 256), 256, 0, s>>>(nrec, rec, c[0], c[1], c[2], fxs,
+                                                                 (uint4 *)ctx->b_fxrec.p);
+                ctx->fx_s = fxs;
+                memcpy(ctx->fx_c, c, sizeof c);
+                ctx->fx_valid = true;
+            }
+            fxr = (const uint4 *)ctx->b_fxrec.p;
+            if (kdp && !E) {
+                if (ensure(ctx, ctx->b_fxrec2, sizeof(uint4) * nrec) != MDLJ_OK) return -4;
+                kk.fxr_out = (uint4 *)ctx->b_fxrec2.p;
+                memcpy(kk.fx_c, c, sizeof c);
+                kk.fx_s = fxs;
+            }
+        }
         LJTable<T> tx = tab;
         if (FX) {
             for (int k = 0; k < tab.ns * tab.ns; ++k) {
@@ -1011,12 +1092,22 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         const bool kd = kdp != nullptr && !E;
 #define VL_LDS(GG, VV)                                                                          \
     do {                                                                                        \
+        bool done = false;                                                                      \
+        if constexpr (FX && GG >= 8) {                                                          \
+            if (kd) {                                                                           \
+                k_vl_lds_w8<T, false, MS, GG, VV, true><<<nbt, VL_LDS_TB, lds, s>>>(            \
+                    rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, \
+                    fxr, kk);                                                                   \
+                done = true;                                                                    \
+            }                                                                                   \
+        }                                                                                       \
+        if (done) break;                                                                        \
         if (kd)                                                                                 \
             k_vl_lds<T, false, MS, GG, VV, true><<<nbt, VL_LDS_TB, lds, s>>>(                   \
-                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, *kdp); \
+                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr, kk); \
         else                                                                                    \
             k_vl_lds<T, E, MS, GG, VV, false><<<nbt, VL_LDS_TB, lds, s>>>(                      \
-                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, none); \
+                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr, none); \
     } while (0)
         const int key = cfg.tile_i * 100 + cfg.tile_j;
         switch (key) {
@@ -1029,6 +1120,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         }
 #undef VL_LDS
         ctx->kd_done = kd;
+        ctx->kd_fx = kd && FX;
         return nbt;
     }
     // 32-bit buffer offsets: records must stay under 2 GiB
@@ -1083,6 +1175,7 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
     }
     if (nw == -2) return set_err(ctx, MDLJ_ERR_ARG, "neighbourhood too large for LDS staging");
     if (nw == -3) return set_err(ctx, MDLJ_ERR_ARG, "too many records for 32-bit buffer offsets");
+    if (nw == -4) return MDLJ_ERR_NOMEM;
     if (nw < 0) return set_err(ctx, MDLJ_ERR_ARG, "unsupported Verlet-list shape");
     HIPCHK(ctx, hipGetLastError());
     *nblocks = nw;
