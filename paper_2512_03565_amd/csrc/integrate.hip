@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__
                                                       const char4 *__restrict__ img,
                                                       PosT *__restrict__ rec, double lx, double ly,
                                                       double lz, int32_t *flag, int32_t *host,
-                                                      uint4 *__restrict__ fxr, double cx,
+                                                      FxWords *__restrict__ fxr, double cx,
                                                       double cy, double cz, double fs)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_flag(flag, host);
@@ -293,8 +293,7 @@ __global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__
         rec[b + m] = q;
         // the images' fixed-point words, when the records have them
         if (fxr)
-            fxr[b + m] = make_uint4(to_fx(q.x, cx, fs), to_fx(q.y, cy, fs), to_fx(q.z, cz, fs),
-                                    (unsigned)q.t);
+            fxr[b + m] = FxWords{to_fx(q.x, cx, fs), to_fx(q.y, cy, fs), to_fx(q.z, cz, fs)};
     }
 }
 
@@ -393,7 +392,7 @@ mdlj_status finish_fused_upkeep(mdlj_ctx *ctx)
         k_refresh_halo<<<ceil_div(ctx->nhalo, 256 / HALO_LANES), 256, 0, ctx->stream>>>(
             ctx->nhalo, (const int2 *)ctx->b_halo.p, (const int32_t *)ctx->b_start.p,
             (const char4 *)ctx->b_img.p, (PosT *)ctx->b_sorted.p, ctx->box[0], ctx->box[1],
-            ctx->box[2], flag, ctx->d_hflag, ctx->fx_valid ? (uint4 *)ctx->b_fxrec.p : nullptr,
+            ctx->box[2], flag, ctx->d_hflag, ctx->fx_valid ? (FxWords *)ctx->b_fxrec.p : nullptr,
             ctx->fx_c[0], ctx->fx_c[1], ctx->fx_c[2], ctx->fx_s);
     } else {
         k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag);

@@ -71,6 +71,11 @@ __device__ __forceinline__ unsigned to_fx(double v, double c, double s)
     return (unsigned)(int)q ^ 0x80000000u;
 }
 
+// The fixed-point words of one record's x, y and z (12 bytes).
+struct FxWords {
+    unsigned x, y, z;
+};
+
 // The velocity-Verlet step fused into the staged Verlet-list force kernel.
 // From the forces of x(t) the kernel finishes v(t) and starts the next step
 // for its own particles (half kick, half kick, drift: the arithmetic of the
@@ -88,7 +93,7 @@ struct KickArgs {
     int64_t pad_slot;       // the padding record, copied to rec_out as it is
     // FP32-pair kernel: fixed-point words of the new positions (frame fx_c,
     // fx_s) to a second word array; null otherwise
-    uint4 *fxr_out;
+    FxWords *fxr_out;
     double fx_c[3], fx_s;
 };
 
@@ -166,7 +171,7 @@ struct mdlj_ctx {
     DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
         b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart, b_vsort,
-        b_vsort2, b_xrsort, b_tinv, b_sorted2, b_fxrec, b_fxrec2;
+        b_vsort2, b_xrsort, b_tinv, b_sorted2, b_fxrec, b_fxrec2, b_fxspec;
     int64_t nhalo = 0;            // entries of b_halo
     int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 
@@ -212,8 +217,9 @@ struct mdlj_ctx {
     bool kd_req = false, kd_go = false, kd_done = false, kd_fx = false;
     double kd_dt = 0.0;
     // fixed-point words of the records (b_fxrec, frame centre fx_c and scale
-    // fx_s) for the FP32-pair staged kernel; fx_valid: they match the
-    // records (writers of the records that do not keep them clear it)
+    // fx_s; the species per record in b_fxspec) for the FP32-pair staged
+    // kernel; fx_valid: they match the records (writers of the records that
+    // do not keep them clear it)
     bool fx_valid = false;
     double fx_c[3] = {0, 0, 0}, fx_s = 0.0;
     double t_force_us = 0, t_build_us = 0;

@@ -520,24 +520,27 @@ typedef __attribute__((address_space(3))) const unsigned lds_cuint;
 // the rounding of each coordinate to the grid 1/s (s is chosen so that every
 // record, halo images included, stays within 2^30 steps of the centre: 1/s
 // is 1.2e-7 sigma for a box of 175 sigma), below the FP32 pair law's own
-// rounding.  The words are kept in global memory, 16 bytes per record with
-// the species, so that staging reads half the bytes of the FP64 records, and
-// a staged record takes 12 bytes of LDS instead of 24.
+// rounding.  The words are kept in global memory (12 bytes per record, the
+// species apart), so that staging reads 12 bytes per record instead of the
+// 32 of the FP64 records, and a staged record takes 12 bytes of LDS instead
+// of 24.
 __device__ __forceinline__ double fx_value(unsigned w)
 {
     return __hiloint2double(0x43300000, (int)w);
 }
 
 // Fixed-point copy of the records for the FP32-pair staged kernel: x, y, z
-// as words of one frame for the whole grid (centre c, scale s) and the
-// species, 16 bytes per record.
+// as words of one frame for the whole grid (centre c, scale s), 12 bytes per
+// record, and the species apart.
 __global__ void k_fx_records(int64_t nrec, const PosT *__restrict__ rec, double cx, double cy,
-                             double cz, double s, uint4 *__restrict__ fxr)
+                             double cz, double s, FxWords *__restrict__ fxr,
+                             int32_t *__restrict__ spec)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nrec) return;
     const PosT p = rec[k];
-    fxr[k] = make_uint4(to_fx(p.x, cx, s), to_fx(p.y, cy, s), to_fx(p.z, cz, s), (unsigned)p.t);
+    fxr[k] = FxWords{to_fx(p.x, cx, s), to_fx(p.y, cy, s), to_fx(p.z, cz, s)};
+    spec[k] = p.t;
 }
 
 // the padding record: word 0 on every axis (coordinate -2^31), at least
@@ -548,7 +551,8 @@ constexpr unsigned FX_PAD = 0u;
 // Staging of the fixed-point layout: record k of the nine concatenated rows
 // from the fixed-point record array (four per thread in flight, rows found
 // without branches as in stage_rows).
-__device__ __forceinline__ void stage_rows_fx(const uint4 *__restrict__ fxr, const int *seg_b,
+__device__ __forceinline__ void stage_rows_fx(const FxWords *__restrict__ fxr,
+                                              const int32_t *__restrict__ spec, const int *seg_b,
                                               const int *seg_c, int C, unsigned *sd, int *st,
                                               bool types, int tid, int nthr)
 {
@@ -557,14 +561,17 @@ __device__ __forceinline__ void stage_rows_fx(const uint4 *__restrict__ fxr, con
 #pragma unroll
     for (int q = 0; q < 8; ++q) c[q] = seg_c[q + 1];
     for (int k0 = tid; k0 < C; k0 += U * nthr) {
-        uint4 w[U];
+        FxWords w[U];
+        int t[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = min(k0 + u * nthr, C - 1);
             int r = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) r += k >= c[q];
-            w[u] = fxr[seg_b[r] + (k - seg_c[r])];
+            const int j = seg_b[r] + (k - seg_c[r]);
+            w[u] = fxr[j];
+            t[u] = types ? spec[j] : 0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -573,7 +580,7 @@ __device__ __forceinline__ void stage_rows_fx(const uint4 *__restrict__ fxr, con
                 sd[3 * k] = w[u].x;
                 sd[3 * k + 1] = w[u].y;
                 sd[3 * k + 2] = w[u].z;
-                if (types) st[k] = (int)w[u].w;
+                if (types) st[k] = t[u];
             }
         }
     }
@@ -610,7 +617,8 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
                                             const int32_t *__restrict__ len, int32_t cap,
                                             int64_t n, int cmax, const LJTable<T> &tab,
                                             const ForceOut &fo, int remap, double fxs,
-                                            const uint4 *__restrict__ fxr, const KickArgs &ka)
+                                            const FxWords *__restrict__ fxr,
+                                            const int32_t *__restrict__ fxspec, const KickArgs &ka)
 {
     // FP32 pair law: fixed-point staged records; fxs is their scale and tab
     // holds sig^2 fxs^2, 24 eps fxs and rc^2 fxs^2, so that every pair
@@ -672,12 +680,15 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     // i's record: FP64 coordinates and species, or (fixed point) the words
     // and species
     PosT pi;
-    uint4 qi;
+    FxWords qi;
+    int qt = 0;
     auto load_i = [&](int k) {
-        if constexpr (FX)
+        if constexpr (FX) {
             qi = fxr[k];
-        else
+            if (MS) qt = fxspec[k];
+        } else {
             pi = rec[k];
+        }
     };
     load_i(act ? i : ib);
     // fused step: lane l of an i's segment needs word l & 3 of its record
@@ -717,7 +728,7 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     unsigned *sd = (unsigned *)stage;
     int *st2 = (int *)(sd + 3 * cmax);
     if constexpr (FX) {
-        stage_rows_fx(fxr, seg_b, seg_c, C, sd, st2, MS, tid, blockDim.x);
+        stage_rows_fx(fxr, fxspec, seg_b, seg_c, C, sd, st2, MS, tid, blockDim.x);
         if (tid == 0) {
             sd[3 * C] = sd[3 * C + 1] = sd[3 * C + 2] = FX_PAD;
             if (MS) st2[C] = 0;
@@ -747,7 +758,7 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     };
     auto species_i = [&]() -> int {
         if constexpr (FX)
-            return (int)qi.w;
+            return qt;
         else
             return pi.t;
     };
@@ -824,10 +835,7 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
             if (act && l < 3)
                 d = kick_drift_axis<FX>(ka, i, t, l, l == 0 ? a.fx : (l == 1 ? a.fy : a.fz), kx,
                                         kv, kr, species_i());
-            if (act && l == 3) {
-                ((double *)(ka.rec_out + i))[3] = kx;
-                if (FX) ((unsigned *)&ka.fxr_out[i])[3] = (unsigned)species_i();
-            }
+            if (act && l == 3) ((double *)(ka.rec_out + i))[3] = kx;
             const double dy = __shfl_down(d, 1, SEG), dz = __shfl_down(d, 2, SEG);
             if (act && l == 0 && !(d * d + dy * dy + dz * dz <= ka.thr2)) atomicOr(ka.flag, 1);
         } else if (act && l == 0) {
@@ -865,24 +873,26 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     const PosT *__restrict__ rec, const int32_t *__restrict__ start,                            \
         const int32_t *__restrict__ ibase, Grid g, int tiles_x, const uint16_t *__restrict__ nbr, \
         const int32_t *__restrict__ len, int32_t cap, int64_t n, int cmax, LJTable<T> tab,      \
-        ForceOut fo, int remap, double fxs, const uint4 *__restrict__ fxr, KickArgs ka
+        ForceOut fo, int remap, double fxs, const FxWords *__restrict__ fxr,                     \
+        const int32_t *__restrict__ fxspec, KickArgs ka
 
 template <typename T, bool E, bool MS, int G, int V, bool KD>
 __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(VL_LDS_PARAMS)
 {
     vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, len, cap, n, cmax, tab, fo,
-                                    remap, fxs, fxr, ka);
+                                    remap, fxs, fxr, fxspec, ka);
 }
 
 // The same, held to 64 registers so that eight wavefronts share a SIMD:
 // for the FP32-pair fused step, whose prefetched operands would otherwise
-// cost two of them (taken only where the cap causes no spills).
+// cost two of them (taken only where the cap causes no spills: one
+// species, 8 or 16 i's per wavefront).
 template <typename T, bool E, bool MS, int G, int V, bool KD>
 __global__ __launch_bounds__(VL_LDS_TB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 k_vl_lds_w8(VL_LDS_PARAMS)
 {
     vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, len, cap, n, cmax, tab, fo,
-                                    remap, fxs, fxr, ka);
+                                    remap, fxs, fxr, fxspec, ka);
 }
 #undef VL_LDS_PARAMS
 
@@ -1052,23 +1062,28 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
             reach = std::max(reach, 0.5 * g.L[a] + g.h[a] * g.edge[a]);
         reach += ctx->rc + ctx->skin;
         const double fxs = FX ? std::exp2(std::floor(std::log2(1073741824.0 / reach))) : 1.0;
-        const uint4 *fxr = nullptr;
+        const FxWords *fxr = nullptr;
+        const int32_t *fxspec = nullptr;
         KickArgs kk = {};
         if (kdp) kk = *kdp;
         if (FX) {
             const double c[3] = {0.5 * g.L[0], 0.5 * g.L[1], 0.5 * g.L[2]};
             if (!ctx->fx_valid || ctx->fx_s != fxs || memcmp(ctx->fx_c, c, sizeof c) != 0) {
-                if (ensure(ctx, ctx->b_fxrec, sizeof(uint4) * nrec) != MDLJ_OK) return -4;
-                k_fx_records<<<ceil_div(nrec, 256), 256, 0, s>>>(nrec, rec, c[0], c[1], c[2], fxs,
-                                                                 (uint4 *)ctx->b_fxrec.p);
+                if (ensure(ctx, ctx->b_fxrec, sizeof(FxWords) * nrec) != MDLJ_OK ||
+                    ensure(ctx, ctx->b_fxspec, sizeof(int32_t) * nrec) != MDLJ_OK)
+                    return -4;
+                k_fx_records<<<ceil_div(nrec, 256), 256, 0, s>>>(
+                    nrec, rec, c[0], c[1], c[2], fxs, (FxWords *)ctx->b_fxrec.p,
+                    (int32_t *)ctx->b_fxspec.p);
                 ctx->fx_s = fxs;
                 memcpy(ctx->fx_c, c, sizeof c);
                 ctx->fx_valid = true;
             }
-            fxr = (const uint4 *)ctx->b_fxrec.p;
+            fxr = (const FxWords *)ctx->b_fxrec.p;
+            fxspec = (const int32_t *)ctx->b_fxspec.p;
             if (kdp && !E) {
-                if (ensure(ctx, ctx->b_fxrec2, sizeof(uint4) * nrec) != MDLJ_OK) return -4;
-                kk.fxr_out = (uint4 *)ctx->b_fxrec2.p;
+                if (ensure(ctx, ctx->b_fxrec2, sizeof(FxWords) * nrec) != MDLJ_OK) return -4;
+                kk.fxr_out = (FxWords *)ctx->b_fxrec2.p;
                 memcpy(kk.fx_c, c, sizeof c);
                 kk.fx_s = fxs;
             }
@@ -1093,21 +1108,23 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
 #define VL_LDS(GG, VV)                                                                          \
     do {                                                                                        \
         bool done = false;                                                                      \
-        if constexpr (FX && GG >= 8) {                                                          \
+        if constexpr (FX && !MS && GG >= 8) {                                                   \
             if (kd) {                                                                           \
                 k_vl_lds_w8<T, false, MS, GG, VV, true><<<nbt, VL_LDS_TB, lds, s>>>(            \
                     rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, \
-                    fxr, kk);                                                                   \
+                    fxr, fxspec, kk);                                                           \
                 done = true;                                                                    \
             }                                                                                   \
         }                                                                                       \
         if (done) break;                                                                        \
         if (kd)                                                                                 \
             k_vl_lds<T, false, MS, GG, VV, true><<<nbt, VL_LDS_TB, lds, s>>>(                   \
-                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr, kk); \
+                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr,   \
+                fxspec, kk);                                                                    \
         else                                                                                    \
             k_vl_lds<T, E, MS, GG, VV, false><<<nbt, VL_LDS_TB, lds, s>>>(                      \
-                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr, none); \
+                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr,   \
+                fxspec, none);                                                                  \
     } while (0)
         const int key = cfg.tile_i * 100 + cfg.tile_j;
         switch (key) {
