@@ -273,6 +273,11 @@ mdlj_status mdlj_set_mass(mdlj_ctx *ctx, int32_t s, double mass);
 mdlj_status mdlj_set_timing(mdlj_ctx *ctx, int32_t on);
 mdlj_status mdlj_get_timing(mdlj_ctx *ctx, double *force_us, double *build_us,
                             int64_t *n_force, int64_t *n_build);
+/* Of the timed force kernels, those that took the velocity-Verlet step too
+ * (staged Verlet lists inside mdlj_step_vv): summed microseconds and count
+ * since mdlj_set_timing.  Synchronises the stream like mdlj_get_timing.
+ * Outputs may be NULL; MDLJ_ERR_ARG for a NULL context. */
+mdlj_status mdlj_get_timing_fused(mdlj_ctx *ctx, double *fused_us, int64_t *n_fused);
 
 /* Eight scene features the learned tuner reads (log10 N, density,
  * rc / sigma_max, species count, expected neighbours within rc, cell

@@ -295,6 +295,10 @@ static mdlj_status account(mdlj_ctx *ctx, const mdlj_ctx::Timed &t)
     ctx->last_force_us = 1e3 * tf;
     ctx->t_force_us += 1e3 * tf;
     ctx->t_nforce++;
+    if (t.fused) {
+        ctx->t_fused_us += 1e3 * tf;
+        ctx->t_nfused++;
+    }
     if (t.e0) {
         float tb = 0;
         HIPCHK(ctx, hipEventElapsedTime(&tb, t.e0, t.e1));
@@ -376,7 +380,7 @@ mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW, F
     if (!ready(ctx, &why)) return set_err(ctx, MDLJ_ERR_STATE, why);
     const mdlj_config c = ctx->cfg;
     bool rebuilt = false, pending = false;
-    mdlj_ctx::Timed tm = {nullptr, nullptr, nullptr, false};
+    mdlj_ctx::Timed tm = {nullptr, nullptr, nullptr, false, false};
     if (ctx->timing) {
         // e0 only when the call rebuilds (recorded by rebuild()); a mark
         // left by a call that failed goes back to the pool
@@ -412,6 +416,7 @@ mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW, F
     }
     if (ctx->timing) {
         tm.rebuilt = rebuilt;
+        tm.fused = ctx->kd_done;
         tm.e0 = ctx->build_mark;
         ctx->build_mark = nullptr;
         ctx->want_build_mark = false;
@@ -712,8 +717,17 @@ mdlj_status mdlj_set_timing(mdlj_ctx *ctx, int32_t on)
     if (!ctx) return MDLJ_ERR_ARG;
     STCHK(collect_timing(ctx));
     ctx->timing = on != 0;
-    ctx->t_force_us = ctx->t_build_us = 0;
-    ctx->t_nforce = ctx->t_nbuild = 0;
+    ctx->t_force_us = ctx->t_build_us = ctx->t_fused_us = 0;
+    ctx->t_nforce = ctx->t_nbuild = ctx->t_nfused = 0;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_get_timing_fused(mdlj_ctx *ctx, double *fused_us, int64_t *n_fused)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    STCHK(collect_timing(ctx));
+    if (fused_us) *fused_us = ctx->t_fused_us;
+    if (n_fused) *n_fused = ctx->t_nfused;
     return MDLJ_OK;
 }
 

@@ -59,28 +59,56 @@ __global__ void k_bin_count(int64_t n, double *__restrict__ x, double *__restric
                             int32_t *__restrict__ rank, int32_t *__restrict__ count,
                             int32_t *__restrict__ flags)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double p[3] = {x[i], y[i], z[i]};
-    if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) {
-        atomicOr(&flags[0], 1);
-        cell_of[i] = -1;
-        rank[i] = 0;
-        return;
-    }
-    int64_t e = 0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (MDLJ_WAVE - 1);
+    bool valid = i < n;
+    int32_t e = 0;
+    if (valid) {
+        double p[3] = {x[i], y[i], z[i]};
+        if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) {
+            atomicOr(&flags[0], 1);
+            cell_of[i] = -1;
+            rank[i] = 0;
+            valid = false;
+        } else {
+            int64_t ee = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double xw = wrap_coord(p[a], g.L[a]);
-        int c = cell_coord(xw, g.inv[a], g.n[a]);
-        e += (int64_t)(c + g.h[a]) * g.stride[a];
-        p[a] = xw;
+            for (int a = 0; a < 3; ++a) {
+                double xw = wrap_coord(p[a], g.L[a]);
+                int c = cell_coord(xw, g.inv[a], g.n[a]);
+                ee += (int64_t)(c + g.h[a]) * g.stride[a];
+                p[a] = xw;
+            }
+            x[i] = p[0];
+            y[i] = p[1];
+            z[i] = p[2];
+            e = (int32_t)ee;
+            cell_of[i] = e;
+        }
     }
-    x[i] = p[0];
-    y[i] = p[1];
-    z[i] = p[2];
-    cell_of[i] = (int32_t)e;
-    rank[i] = atomicAdd(&count[e], 1);
+    // Lanes of a wavefront in the same cell take one atomic: the lowest lane
+    // of a group adds the group's size and hands out the base (particles in
+    // spatial order put a wavefront into a few cells).  Up to 16 groups are
+    // formed; lanes left over add 1 each.  Ranks within a cell are a set of
+    // distinct numbers in any order (the fill sorts each cell by its key).
+    uint64_t todo = __builtin_amdgcn_ballot_w64(valid);
+    int leader = lane, sub = 0, size = 1;
+    for (int it = 0; it < 16 && todo != 0; ++it) {
+        const int ld = __builtin_ctzll(todo);
+        const int32_t el = __builtin_amdgcn_readlane(e, ld);
+        const uint64_t grp = __builtin_amdgcn_ballot_w64(valid && e == el);
+        if ((grp >> lane) & 1) {
+            leader = ld;
+            sub = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(grp >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)grp, 0u));
+            size = __builtin_popcountll(grp);
+        }
+        todo &= ~grp;
+    }
+    int32_t base = 0;
+    if (valid && leader == lane) base = atomicAdd(&count[e], size);
+    base = __shfl(base, leader);
+    if (valid) rank[i] = base + sub;
 }
 
 // Extended-cell counts: a halo cell holds as many records as its source.

@@ -196,6 +196,7 @@ struct mdlj_ctx {
     struct Timed {
         hipEvent_t e0, e1, e2;
         bool rebuilt;
+        bool fused;  // the force kernel took the integrator step too
     };
     bool timing = false;
     // inside a timed force call: rebuild() records build_mark at its start
@@ -222,8 +223,8 @@ struct mdlj_ctx {
     // do not keep them clear it)
     bool fx_valid = false;
     double fx_c[3] = {0, 0, 0}, fx_s = 0.0;
-    double t_force_us = 0, t_build_us = 0;
-    int64_t t_nforce = 0, t_nbuild = 0;
+    double t_force_us = 0, t_build_us = 0, t_fused_us = 0;
+    int64_t t_nforce = 0, t_nbuild = 0, t_nfused = 0;
     double last_force_us = 0, last_build_us = 0;
 };
 

@@ -1029,6 +1029,33 @@ __global__ __launch_bounds__(256) void k_vl_wpi(const PosT *__restrict__ rec,
                      (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE);
 }
 
+// The fixed-point words of the current records, converted when stale.  The
+// frame is centred on the box; every record (halo images one cell beyond
+// the box) plus rc + skin for particles that drift before a rebuild stays
+// within 2^30 steps of the centre.  *scale receives s.
+static mdlj_status fx_words(mdlj_ctx *ctx, double *scale)
+{
+    const Grid &g = ctx->grid;
+    double reach = 0.0;
+    for (int a = 0; a < 3; ++a) reach = std::max(reach, 0.5 * g.L[a] + g.h[a] * g.edge[a]);
+    reach += ctx->rc + ctx->skin;
+    const double fxs = std::exp2(std::floor(std::log2(1073741824.0 / reach)));
+    const double c[3] = {0.5 * g.L[0], 0.5 * g.L[1], 0.5 * g.L[2]};
+    *scale = fxs;
+    if (ctx->fx_valid && ctx->fx_s == fxs && memcmp(ctx->fx_c, c, sizeof c) == 0) return MDLJ_OK;
+    const int64_t nrec = ctx->n_ext + 1;  // records + the padding record
+    STCHK(ensure(ctx, ctx->b_fxrec, sizeof(FxWords) * nrec));
+    STCHK(ensure(ctx, ctx->b_fxspec, sizeof(int32_t) * nrec));
+    k_fx_records<<<ceil_div(nrec, 256), 256, 0, ctx->stream>>>(
+        nrec, (const PosT *)ctx->b_sorted.p, c[0], c[1], c[2], fxs, (FxWords *)ctx->b_fxrec.p,
+        (int32_t *)ctx->b_fxspec.p);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->fx_s = fxs;
+    memcpy(ctx->fx_c, c, sizeof c);
+    ctx->fx_valid = true;
+    return MDLJ_OK;
+}
+
 template <typename T, bool E, bool MS, bool N3>
 int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, ForceOut &fo,
                   int remap, const KickArgs *kdp)
@@ -1054,37 +1081,19 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         const size_t lds = (size_t)cmax * ((FX ? 3 * sizeof(unsigned) : 3 * sizeof(double)) +
                                            (MS ? sizeof(int) : 0));
         if (lds > (size_t)STAGE_LDS_BYTES || N3) return -2;
-        // fixed-point frame: centred on the box, records (with the halo
-        // images, one cell beyond the box) plus rc + skin for particles that
-        // drift before a rebuild within 2^30 steps of the centre
-        double reach = 0.0;
-        for (int a = 0; a < 3; ++a)
-            reach = std::max(reach, 0.5 * g.L[a] + g.h[a] * g.edge[a]);
-        reach += ctx->rc + ctx->skin;
-        const double fxs = FX ? std::exp2(std::floor(std::log2(1073741824.0 / reach))) : 1.0;
+        double fxs = 1.0;
+        if (FX && fx_words(ctx, &fxs) != MDLJ_OK) return -4;
         const FxWords *fxr = nullptr;
         const int32_t *fxspec = nullptr;
         KickArgs kk = {};
         if (kdp) kk = *kdp;
         if (FX) {
-            const double c[3] = {0.5 * g.L[0], 0.5 * g.L[1], 0.5 * g.L[2]};
-            if (!ctx->fx_valid || ctx->fx_s != fxs || memcmp(ctx->fx_c, c, sizeof c) != 0) {
-                if (ensure(ctx, ctx->b_fxrec, sizeof(FxWords) * nrec) != MDLJ_OK ||
-                    ensure(ctx, ctx->b_fxspec, sizeof(int32_t) * nrec) != MDLJ_OK)
-                    return -4;
-                k_fx_records<<<ceil_div(nrec, 256), 256, 0, s>>>(
-                    nrec, rec, c[0], c[1], c[2], fxs, (FxWords *)ctx->b_fxrec.p,
-                    (int32_t *)ctx->b_fxspec.p);
-                ctx->fx_s = fxs;
-                memcpy(ctx->fx_c, c, sizeof c);
-                ctx->fx_valid = true;
-            }
             fxr = (const FxWords *)ctx->b_fxrec.p;
             fxspec = (const int32_t *)ctx->b_fxspec.p;
             if (kdp && !E) {
                 if (ensure(ctx, ctx->b_fxrec2, sizeof(FxWords) * nrec) != MDLJ_OK) return -4;
                 kk.fxr_out = (FxWords *)ctx->b_fxrec2.p;
-                memcpy(kk.fx_c, c, sizeof c);
+                memcpy(kk.fx_c, ctx->fx_c, sizeof kk.fx_c);
                 kk.fx_s = fxs;
             }
         }

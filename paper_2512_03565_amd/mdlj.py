@@ -119,6 +119,7 @@ _SIGS = {
     "mdlj_retune_needed": [C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_double,
                            C.POINTER(C.c_int32)],
     "mdlj_get_timing": [_ctxp, _d, _d, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "mdlj_get_timing_fused": [_ctxp, _d, C.POINTER(C.c_int64)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(lib, _name)
@@ -336,6 +337,13 @@ class System:
         check(lib.mdlj_get_timing(self.ctx, C.byref(f), C.byref(b), C.byref(nf), C.byref(nb)),
               self.ctx)
         return f.value, b.value, nf.value, nb.value
+
+    def get_timing_fused(self):
+        """(us_total, n) of the timed force kernels that took the integrator
+        step too, since set_timing."""
+        f, nf = C.c_double(), C.c_int64()
+        check(lib.mdlj_get_timing_fused(self.ctx, C.byref(f), C.byref(nf)), self.ctx)
+        return f.value, nf.value
 
     # --- learned tuner network -------------------------------------------
     def mlp_init(self, k, seed=0):

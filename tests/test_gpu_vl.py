@@ -187,10 +187,17 @@ def test_velocity_verlet_one_call_equals_single_steps(m, prec, cfg):
             else:
                 sysm.step_vv(vel, s["dt"], 60)
             _, _, nf, nb = sysm.get_timing()
-            out.append((sysm.get_positions(), torch.stack(vel, 1).cpu().numpy(), nb))
-    print(f"[vv one call vs single steps] prec={prec} cfg={cfg} rebuilds {out[0][2]} / {out[1][2]}",
-          flush=True)
+            _, nfused = sysm.get_timing_fused()
+            out.append((sysm.get_positions(), torch.stack(vel, 1).cpu().numpy(), nb, nfused))
+    print(f"[vv one call vs single steps] prec={prec} cfg={cfg} rebuilds {out[0][2]} / {out[1][2]}"
+          f", fused force calls {out[0][3]} / {out[1][3]}", flush=True)
     assert out[0][2] == out[1][2] >= 6, (cfg, out[0][2], out[1][2])
+    # staged lists: every step of the call but the last and those before a
+    # rebuild takes the integrator step inside the force kernel; one-step
+    # calls never do
+    staged = len(cfg) == 7 and cfg[6] == 1
+    assert out[1][3] == 0
+    assert (out[0][3] >= 60 - 1 - out[0][2]) if staged else out[0][3] == 0, out[0][3]
     assert np.array_equal(out[0][0], out[1][0]), cfg
     assert np.array_equal(out[0][1], out[1][1]), cfg
 
