@@ -422,12 +422,14 @@ __global__ void k_int_counts(Grid g, const int32_t *__restrict__ count, int32_t 
 // host[0] = non-finite flag, host[1] = records with halo images,
 // host[2] = largest cell occupancy (system-scope stores to pinned memory)
 __global__ void k_publish_bin(const int32_t *__restrict__ flags, const int32_t *__restrict__ total,
-                              int32_t *host)
+                              int32_t *host, uint32_t seq)
 {
     if (threadIdx.x == 0) {
         __hip_atomic_store(host, flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(host + 1, *total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(host + 2, flags[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        // after the values: the host waits for this word
+        __hip_atomic_store((uint32_t *)host + 3, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -546,9 +548,10 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     // non-finite flag, record total and largest occupancy to the host in
     // one small kernel
     STCHK(ensure_host_flag(ctx));
-    k_publish_bin<<<1, 64, 0, s>>>(flags, start + g.ncell_ext, ctx->d_hflag + 4);
+    const uint32_t seq = ++ctx->flag_seq;
+    k_publish_bin<<<1, 64, 0, s>>>(flags, start + g.ncell_ext, ctx->d_hflag + 4, seq);
     HIPCHK(ctx, hipGetLastError());
-    HIPCHK(ctx, hipStreamSynchronize(s));
+    STCHK(wait_host_words(ctx, 7, seq));
     const int32_t host[3] = {ctx->h_flag[4], ctx->h_flag[5], ctx->h_flag[6]};
     if (host[0]) return set_err(ctx, MDLJ_ERR_NONFINITE, "non-finite particle position");
     const int64_t n_ext = host[1];

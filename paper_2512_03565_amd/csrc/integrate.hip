@@ -250,16 +250,20 @@ __global__ void k_leave_velocities(int64_t n, const int32_t *__restrict__ tinv,
 // (system scope, so the host sees it once the kernel has finished) and is
 // cleared for the next step.  The integrator kernel that set it has
 // finished: it ran before on the same stream.
-__device__ __forceinline__ void publish_flag(int32_t *flag, int32_t *host)
+// The value goes to the host together with the publication's sequence
+// number in one 64-bit store, so the host knows the word it reads is this
+// publication's without a system-scope fence on the stream.
+__device__ __forceinline__ void publish_flag(int32_t *flag, int32_t *host, uint32_t seq)
 {
     const int32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(host, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const uint64_t w = ((uint64_t)seq << 32) | (uint32_t)v;
+    __hip_atomic_store((uint64_t *)host, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_publish_flag(int32_t *flag, int32_t *host)
+__global__ void k_publish_flag(int32_t *flag, int32_t *host, uint32_t seq)
 {
-    if (threadIdx.x == 0) publish_flag(flag, host);
+    if (threadIdx.x == 0) publish_flag(flag, host, seq);
 }
 
 // Halo records from their source records, a group of lanes per halo cell:
@@ -273,10 +277,10 @@ __global__ __launch_bounds__(256) void k_refresh_halo(int64_t nh, const int2 *__
                                                       const char4 *__restrict__ img,
                                                       PosT *__restrict__ rec, double lx, double ly,
                                                       double lz, int32_t *flag, int32_t *host,
-                                                      FxWords *__restrict__ fxr, double cx,
-                                                      double cy, double cz, double fs)
+                                                      uint32_t seq, FxWords *__restrict__ fxr,
+                                                      double cx, double cy, double cz, double fs)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) publish_flag(flag, host);
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish_flag(flag, host, seq);
     // HALO_LANES lanes per halo cell (cells hold ~17 records at liquid
     // densities, so a whole wavefront per cell would idle most lanes)
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / HALO_LANES;
@@ -349,8 +353,13 @@ mdlj_status ensure_host_flag(mdlj_ctx *ctx)
     // coherent: the kernel's store reaches host memory without a cache
     // write-back
     HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocCoherent));
+    memset(ctx->h_flag, 0, 64);
+    ctx->flag_seq = ctx->flag_seq_disp = 0;
     HIPCHK(ctx, hipHostGetDevicePointer((void **)&ctx->d_hflag, ctx->h_flag, 0));
-    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_flag, hipEventDisableTiming));
+    // no system-scope fence when recorded (it would write back the L2 each
+    // step): the flag word carries its own sequence number instead
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_flag,
+                                        hipEventDisableTiming | hipEventDisableSystemFence));
     return MDLJ_OK;
 }
 
@@ -365,17 +374,41 @@ mdlj_status launch_displacement_check(mdlj_ctx *ctx)
                                                              (const double *)ctx->b_xref.p, h * h,
                                                              flag);
     HIPCHK(ctx, hipGetLastError());
-    k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag);
+    ctx->flag_seq_disp = ++ctx->flag_seq;
+    k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag, ctx->flag_seq_disp);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev_flag, ctx->stream));
     ctx->dflag_zero = true;
     return MDLJ_OK;
 }
 
+mdlj_status wait_host_words(mdlj_ctx *ctx, int at, uint32_t seq)
+{
+    const uint32_t *w = (const uint32_t *)ctx->h_flag + at;
+    for (int k = 0; k < (1 << 24); ++k)
+        if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return MDLJ_OK;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return MDLJ_OK;
+    return set_err(ctx, MDLJ_ERR_HIP, "host words were not published");
+}
+
 mdlj_status check_result(mdlj_ctx *ctx, bool *too_far)
 {
     HIPCHK(ctx, hipEventSynchronize(ctx->ev_flag));
-    *too_far = ctx->h_flag[0] != 0;
+    // the publishing kernel has finished; its store to host memory carries
+    // the sequence number.  Should it not be visible yet, wait for it, and
+    // in the end for the whole stream (a full synchronisation)
+    const uint64_t *w = (const uint64_t *)ctx->h_flag;
+    uint64_t v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+    for (int k = 0; (uint32_t)(v >> 32) != ctx->flag_seq_disp && k < (1 << 20); ++k)
+        v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+    if ((uint32_t)(v >> 32) != ctx->flag_seq_disp) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+        if ((uint32_t)(v >> 32) != ctx->flag_seq_disp)
+            return set_err(ctx, MDLJ_ERR_HIP, "displacement flag was not published");
+    }
+    *too_far = (int32_t)(uint32_t)v != 0;
     return MDLJ_OK;
 }
 
@@ -388,14 +421,16 @@ mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far)
 mdlj_status finish_fused_upkeep(mdlj_ctx *ctx)
 {
     int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
+    ctx->flag_seq_disp = ++ctx->flag_seq;
     if (ctx->nhalo > 0) {
         k_refresh_halo<<<ceil_div(ctx->nhalo, 256 / HALO_LANES), 256, 0, ctx->stream>>>(
             ctx->nhalo, (const int2 *)ctx->b_halo.p, (const int32_t *)ctx->b_start.p,
             (const char4 *)ctx->b_img.p, (PosT *)ctx->b_sorted.p, ctx->box[0], ctx->box[1],
-            ctx->box[2], flag, ctx->d_hflag, ctx->fx_valid ? (FxWords *)ctx->b_fxrec.p : nullptr,
+            ctx->box[2], flag, ctx->d_hflag, ctx->flag_seq_disp,
+            ctx->fx_valid ? (FxWords *)ctx->b_fxrec.p : nullptr,
             ctx->fx_c[0], ctx->fx_c[1], ctx->fx_c[2], ctx->fx_s);
     } else {
-        k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag);
+        k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag, ctx->flag_seq_disp);
     }
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev_flag, ctx->stream));

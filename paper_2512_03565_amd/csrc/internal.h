@@ -210,6 +210,9 @@ struct mdlj_ctx {
     int32_t *h_flag = nullptr;
     int32_t *d_hflag = nullptr;
     hipEvent_t ev_flag = nullptr;
+    // sequence numbers of publications to the host words: the last one
+    // handed out, and that of the last displacement flag
+    uint32_t flag_seq = 0, flag_seq_disp = 0;
     bool dflag_zero = false;
     // fused integrator step: kd_req is set by the integrator around a force
     // call whose step continues in sorted order (kd_dt its time step);
@@ -277,6 +280,10 @@ mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far);
 // memory behind ctx->ev_flag (read with check_result).
 mdlj_status launch_displacement_check(mdlj_ctx *ctx);
 mdlj_status check_result(mdlj_ctx *ctx, bool *too_far);
+// Wait until h_flag[at] holds seq: written (release, system scope) by a
+// small kernel after the host words it publishes.  Spins, then falls back
+// to a stream synchronisation.
+mdlj_status wait_host_words(mdlj_ctx *ctx, int at, uint32_t seq);
 mdlj_status refresh_records(mdlj_ctx *ctx);
 // After a fused integrator step: refresh the halo records from their
 // sources; the same kernel hands the displacement flag to the host (behind

@@ -178,11 +178,14 @@ __device__ __forceinline__ void half_runs(const int (*rs)[STAGE_K + 3],
 }
 
 // host[0..3] = src[0..3] (system-scope stores to pinned memory)
-__global__ void k_publish4(const int32_t *__restrict__ src, int32_t *host)
+__global__ void k_publish4(const int32_t *__restrict__ src, int32_t *host, uint32_t seq)
 {
-    if (threadIdx.x < 4)
-        __hip_atomic_store(host + threadIdx.x, src[threadIdx.x], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_SYSTEM);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 4; ++k)
+            __hip_atomic_store(host + k, src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        // after the values: the host waits for this word
+        __hip_atomic_store((uint32_t *)host + 4, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // Staged records and candidate-list entries of the largest tile, for the
@@ -1371,9 +1374,10 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         HIPCHK(ctx, hipGetLastError());
         // the four maxima to pinned host words in one small kernel
         STCHK(ensure_host_flag(ctx));
-        k_publish4<<<1, 64, 0, ctx->stream>>>(maxlen, ctx->d_hflag + 8);
+        const uint32_t seq = ++ctx->flag_seq;
+        k_publish4<<<1, 64, 0, ctx->stream>>>(maxlen, ctx->d_hflag + 8, seq);
         HIPCHK(ctx, hipGetLastError());
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        STCHK(wait_host_words(ctx, 12, seq));
         const int32_t hmax[4] = {ctx->h_flag[8], ctx->h_flag[9], ctx->h_flag[10], ctx->h_flag[11]};
         if (tiled && (hmax[2] > cmax || hmax[3] > ccand)) {
             // a tile over the sizes built nothing: exact sizes, or (if those
