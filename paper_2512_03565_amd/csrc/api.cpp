@@ -524,7 +524,6 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
     }
     if (ctx->build_mark) ctx->ev_pool.push_back(ctx->build_mark);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-    if (ctx->ev_flag) (void)hipEventDestroy(ctx->ev_flag);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
     DevBuf *bufs[] = {&ctx->b_cell_of, &ctx->b_rank,    &ctx->b_count,   &ctx->b_start,
                       &ctx->b_slot_of, &ctx->b_sorted,  &ctx->b_scan_part, &ctx->b_fsorted,

@@ -356,10 +356,6 @@ mdlj_status ensure_host_flag(mdlj_ctx *ctx)
     memset(ctx->h_flag, 0, 64);
     ctx->flag_seq = ctx->flag_seq_disp = 0;
     HIPCHK(ctx, hipHostGetDevicePointer((void **)&ctx->d_hflag, ctx->h_flag, 0));
-    // no system-scope fence when recorded (it would write back the L2 each
-    // step): the flag word carries its own sequence number instead
-    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_flag,
-                                        hipEventDisableTiming | hipEventDisableSystemFence));
     return MDLJ_OK;
 }
 
@@ -377,7 +373,6 @@ mdlj_status launch_displacement_check(mdlj_ctx *ctx)
     ctx->flag_seq_disp = ++ctx->flag_seq;
     k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag, ctx->flag_seq_disp);
     HIPCHK(ctx, hipGetLastError());
-    HIPCHK(ctx, hipEventRecord(ctx->ev_flag, ctx->stream));
     ctx->dflag_zero = true;
     return MDLJ_OK;
 }
@@ -394,13 +389,12 @@ mdlj_status wait_host_words(mdlj_ctx *ctx, int at, uint32_t seq)
 
 mdlj_status check_result(mdlj_ctx *ctx, bool *too_far)
 {
-    HIPCHK(ctx, hipEventSynchronize(ctx->ev_flag));
-    // the publishing kernel has finished; its store to host memory carries
-    // the sequence number.  Should it not be visible yet, wait for it, and
-    // in the end for the whole stream (a full synchronisation)
+    // the publishing kernel's store to host memory carries the sequence
+    // number: spin on it (no event between the kernels, which would stall
+    // the stream), and in the end wait for the whole stream
     const uint64_t *w = (const uint64_t *)ctx->h_flag;
     uint64_t v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
-    for (int k = 0; (uint32_t)(v >> 32) != ctx->flag_seq_disp && k < (1 << 20); ++k)
+    for (int k = 0; (uint32_t)(v >> 32) != ctx->flag_seq_disp && k < (1 << 24); ++k)
         v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
     if ((uint32_t)(v >> 32) != ctx->flag_seq_disp) {
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -433,7 +427,6 @@ mdlj_status finish_fused_upkeep(mdlj_ctx *ctx)
         k_publish_flag<<<1, 64, 0, ctx->stream>>>(flag, ctx->d_hflag, ctx->flag_seq_disp);
     }
     HIPCHK(ctx, hipGetLastError());
-    HIPCHK(ctx, hipEventRecord(ctx->ev_flag, ctx->stream));
     ctx->dflag_zero = true;
     return MDLJ_OK;
 }

@@ -204,12 +204,12 @@ struct mdlj_ctx {
     hipEvent_t build_mark = nullptr;
     std::vector<hipEvent_t> ev_pool;
     std::deque<Timed> ev_pending;
-    // displacement check result (pinned host memory, d_hflag its device
-    // address) and its event; dflag_zero: the device-side flag is known to
-    // hold 0
+    // host words written by small kernels (pinned host memory, d_hflag its
+    // device address): the displacement flag with its sequence number, the
+    // binning results and the list-build maxima; dflag_zero: the
+    // device-side flag is known to hold 0
     int32_t *h_flag = nullptr;
     int32_t *d_hflag = nullptr;
-    hipEvent_t ev_flag = nullptr;
     // sequence numbers of publications to the host words: the last one
     // handed out, and that of the last displacement flag
     uint32_t flag_seq = 0, flag_seq_disp = 0;
@@ -272,12 +272,13 @@ mdlj_status check_finite(mdlj_ctx *ctx, const double *x, const double *y, const 
 // --- integrator and record upkeep (integrate.hip) ---------------------------
 mdlj_status save_reference(mdlj_ctx *ctx);
 // Pinned host words ctx->h_flag (16 int32) and their device address
-// ctx->d_hflag: [0] the displacement flag, [4..7] binning results, [8..11]
-// Verlet-list build maxima.
+// ctx->d_hflag: [0] the displacement flag and [1] its sequence number,
+// [4..6] binning results and [7] their sequence number, [8..11] Verlet-list
+// build maxima and [12] their sequence number.
 mdlj_status ensure_host_flag(mdlj_ctx *ctx);
 mdlj_status moved_too_far(mdlj_ctx *ctx, bool *too_far);
 // Enqueue the skin/2 displacement check; its result lands in pinned host
-// memory behind ctx->ev_flag (read with check_result).
+// memory with the sequence number flag_seq_disp (read with check_result).
 mdlj_status launch_displacement_check(mdlj_ctx *ctx);
 mdlj_status check_result(mdlj_ctx *ctx, bool *too_far);
 // Wait until h_flag[at] holds seq: written (release, system scope) by a
@@ -286,8 +287,8 @@ mdlj_status check_result(mdlj_ctx *ctx, bool *too_far);
 mdlj_status wait_host_words(mdlj_ctx *ctx, int at, uint32_t seq);
 mdlj_status refresh_records(mdlj_ctx *ctx);
 // After a fused integrator step: refresh the halo records from their
-// sources; the same kernel hands the displacement flag to the host (behind
-// ctx->ev_flag) and clears it for the next step.
+// sources; the same kernel hands the displacement flag to the host (with
+// the sequence number flag_seq_disp) and clears it for the next step.
 mdlj_status finish_fused_upkeep(mdlj_ctx *ctx);
 // (halo cell, source cell) pairs of the current grid, for the halo refresh.
 mdlj_status build_halo_list(mdlj_ctx *ctx);
