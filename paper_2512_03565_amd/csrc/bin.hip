@@ -236,16 +236,20 @@ __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
     sorted_orig[start[e] + rank[i]] = (int32_t)i;
 }
 
-// One wavefront per extended cell: interior cells gather their records,
-// halo cells copy the records of their source cell shifted by +-L.  Within
-// a cell records are ordered by the key (x half, caller index): first the
-// particles in the lower half of the cell along x, then the upper half,
-// each by caller index.  The order does not depend on the order in which
-// the counting atomics were served: element m of the source cell's
-// unordered list goes to slot b + (number of elements with a smaller key).
-// Halo cells rank their source's list the same way, so every image has the
-// order of its source.  hstart[e] = first slot of the upper half (the list
-// build uses the halves to drop candidates more than one cell away in x).
+// FILL_LANES lanes per extended cell (cells hold ~17 records at liquid
+// densities, so a whole wavefront per cell would idle most lanes): interior
+// cells gather their records, halo cells copy the records of their source
+// cell shifted by +-L.  Within a cell records are ordered by the key
+// (x half, caller index): first the particles in the lower half of the cell
+// along x, then the upper half, each by caller index.  The order does not
+// depend on the order in which the counting atomics were served: element m
+// of the source cell's unordered list goes to slot b + (number of elements
+// with a smaller key).  Halo cells rank their source's list the same way, so
+// every image has the order of its source.  hstart[e] = first slot of the
+// upper half (the list build uses the halves to drop candidates more than
+// one cell away in x).
+constexpr int FILL_LANES = 16;
+
 __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict__ start,
                                               const int32_t *__restrict__ unordered,
                                               const double *__restrict__ x,
@@ -257,46 +261,51 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
                                               char4 *__restrict__ img,
                                               int32_t *__restrict__ hstart)
 {
-    int64_t e = (int64_t)blockIdx.x * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
-    int lane = threadIdx.x & (MDLJ_WAVE - 1);
-    if (e >= g.ncell_ext) return;
-    const int32_t b = start[e], cnt = start[e + 1] - b;
-    double sh[3];
-    signed char code[3];
-    int64_t src = 0;
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FILL_LANES;
+    const int sub = threadIdx.x & (FILL_LANES - 1);
+    // a group of lanes past the last cell has no records: every lane of a
+    // group runs the same trips, so the shuffles below read only lanes of
+    // the own group, all active
+    const bool live = e < g.ncell_ext;
+    int32_t b = 0, cnt = 0, sb = 0;
+    double sh[3] = {0.0, 0.0, 0.0};
+    signed char code[3] = {0, 0, 0};
     bool interior = true;
     int sx_cell = 0;
+    if (live) {
+        b = start[e];
+        cnt = start[e + 1] - b;
+        int64_t src = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        int c = (int)(((uint32_t)e / (uint32_t)g.stride[a]) % (uint32_t)g.e[a]) - g.h[a];
-        int s = c;
-        sh[a] = 0.0;
-        code[a] = 0;
-        if (c < 0) { s = c + g.n[a]; sh[a] = -g.L[a]; code[a] = -1; interior = false; }
-        if (c >= g.n[a]) { s = c - g.n[a]; sh[a] = g.L[a]; code[a] = 1; interior = false; }
-        src += (int64_t)(s + g.h[a]) * g.stride[a];
-        if (a == 0) sx_cell = s;
+        for (int a = 0; a < 3; ++a) {
+            int c = (int)(((uint32_t)e / (uint32_t)g.stride[a]) % (uint32_t)g.e[a]) - g.h[a];
+            int s = c;
+            if (c < 0) { s = c + g.n[a]; sh[a] = -g.L[a]; code[a] = -1; interior = false; }
+            if (c >= g.n[a]) { s = c - g.n[a]; sh[a] = g.L[a]; code[a] = 1; interior = false; }
+            src += (int64_t)(s + g.h[a]) * g.stride[a];
+            if (a == 0) sx_cell = s;
+        }
+        sb = start[src];
     }
-    const int32_t sb = start[src];
     // caller indices are below 2^30: key = upper-half bit 31 | caller index
     const double xmid = ((double)sx_cell + 0.5) * g.edge[0];
     auto key_of = [&](int32_t i) {
         return (uint32_t)i | (x[i] < xmid ? 0u : 0x80000000u);
     };
     int32_t nlow = 0;
-    for (int32_t m0 = 0; m0 < cnt; m0 += MDLJ_WAVE) {
-        const int32_t m = m0 + lane;
+    for (int32_t m0 = 0; m0 < cnt; m0 += FILL_LANES) {
+        const int32_t m = m0 + sub;
         const int32_t i = m < cnt ? unordered[sb + m] : 0;
         const uint32_t ki = m < cnt ? key_of(i) : 0xffffffffu;
         int32_t rank = 0;
-        for (int32_t q0 = 0; q0 < cnt; q0 += MDLJ_WAVE) {
-            const int32_t vi = q0 + lane < cnt ? unordered[sb + q0 + lane] : 0;
-            const uint32_t v = q0 + lane < cnt ? key_of(vi) : 0xffffffffu;
-            const int32_t nq = min(cnt - q0, MDLJ_WAVE);
-            for (int32_t q = 0; q < nq; ++q) rank += __builtin_amdgcn_readlane(v, q) < ki;
+        for (int32_t q0 = 0; q0 < cnt; q0 += FILL_LANES) {
+            const int32_t vi = q0 + sub < cnt ? unordered[sb + q0 + sub] : 0;
+            const uint32_t v = q0 + sub < cnt ? key_of(vi) : 0xffffffffu;
+            const int32_t nq = min(cnt - q0, FILL_LANES);
+            for (int32_t q = 0; q < nq; ++q) rank += __shfl(v, q, FILL_LANES) < ki;
         }
-        nlow += __popcll(__ballot(m < cnt && ki < 0x80000000u));
         if (m < cnt) {
+            nlow += ki < 0x80000000u ? 1 : 0;
             const int32_t k = b + rank;
             PosT r;
             r.x = x[i] + sh[0];
@@ -309,7 +318,10 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
             if (interior) slot_of[i] = k;
         }
     }
-    if (lane == 0) hstart[e] = b + nlow;
+    // the group's count of lower-half records
+#pragma unroll
+    for (int o = FILL_LANES / 2; o > 0; o >>= 1) nlow += __shfl_xor(nlow, o, FILL_LANES);
+    if (live && sub == 0) hstart[e] = b + nlow;
 }
 
 // The padding record at slot n_ext: far outside the box, no particle.
@@ -564,7 +576,7 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     k_scatter<<<ceil_div(n, TB), TB, 0, s>>>(n, (int32_t *)ctx->b_cell_of.p,
                                               (int32_t *)ctx->b_rank.p, start, unordered);
     STCHK(ensure(ctx, ctx->b_hstart, sizeof(int32_t) * g.ncell_ext));
-    k_fill<<<ceil_div(g.ncell_ext, TB / MDLJ_WAVE), TB, 0, s>>>(
+    k_fill<<<ceil_div(g.ncell_ext, TB / FILL_LANES), TB, 0, s>>>(
         g, start, unordered, ctx->x, ctx->y, ctx->z, ctx->type, (PosT *)ctx->b_sorted.p,
         (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p, (int32_t *)ctx->b_hstart.p);
     k_pad_record<<<1, 64, 0, s>>>((PosT *)ctx->b_sorted.p, n_ext);
