@@ -553,7 +553,6 @@ mdlj_status kd_prepare(mdlj_ctx *ctx, const mdlj_config &c, bool energy)
 
 mdlj_status kd_args(mdlj_ctx *ctx, KickArgs *ka)
 {
-    const int64_t n = ctx->n;
     STCHK(ensure(ctx, ctx->b_sorted2, sizeof(PosT) * (ctx->n_ext + 1)));
     int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
     if (!ctx->dflag_zero) HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
@@ -569,7 +568,6 @@ mdlj_status kd_args(mdlj_ctx *ctx, KickArgs *ka)
     const double h = 0.5 * ctx->skin;
     ka->thr2 = h * h;
     ka->pad_slot = ctx->n_ext;
-    (void)n;
     return MDLJ_OK;
 }
 

@@ -149,15 +149,20 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
 // candidates per trip and the hits are packed in candidate order with a
 // ballot and a lane prefix count, so each list row is written as one
 // contiguous run.  The lists equal those of the per-particle builds above
-// entry for entry.
+// entry for entry (a partner at distance zero, which only the particle
+// itself can be, is left out by the distance test).
 // LOCAL: 16-bit staged indices, rows padded with C (the staged count);
 // otherwise sorted-record slots at nbr[t * st + k * sk], padded with `pad`.
 // HALF keeps partners with a larger caller index only.
 // A tile whose neighbourhood exceeds cmax records its size in maxnb and
 // builds nothing; the host then falls back to the per-particle build.
 constexpr int BUILD_TB = 512;
-// slack after the candidate lists: a trip of 2 x 64 lanes may read past the
-// last list, into entries set to index 0
+// Each candidate list is padded to a multiple of a trip (2 x 64 lanes) with
+// the index of a far-away padding record staged after the neighbourhood, so
+// lanes past a list need no test of their own: CAND_PAD bounds the padding
+// of a tile's lists, CAND_SLACK the entries after the last one.
+constexpr int CAND_TRIP = 2 * MDLJ_WAVE;
+constexpr int CAND_PAD = 2 * STAGE_K * (CAND_TRIP - 1);
 constexpr int CAND_SLACK = 2 * MDLJ_WAVE;
 
 // Candidate runs of the tiled build.  Records in a cell are ordered lower x
@@ -250,6 +255,7 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     __shared__ int hs[9][RC - 1];        // hstart[] of the cells of each row
     __shared__ int seg_c[10];            // staged offset of each row
     __shared__ int nc[2 * STAGE_K + 1];  // offsets of the (tile cell, half) candidate lists
+    __shared__ int qlen[2 * STAGE_K];    // their lengths before the padding
     __shared__ int roff[2 * STAGE_K][9]; // offset of row r's run inside list q
     __shared__ int wmx[NW];
     const int tid = threadIdx.x;
@@ -285,13 +291,16 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         int v = 0;
         if (lane < 9) v = rs[lane][ncx + 2] - rs[lane][0];
         const int q = lane - 16;
-        if (q >= 0 && q < 2 * ncx)
+        if (q >= 0 && q < 2 * ncx) {
             for (int r = 0; r < 9; ++r) {
                 int b, e;
                 half_runs(rs, hs, r, q >> 1, q & 1, trim, b, e);
                 roff[q][r] = v;
                 v += e - b;
             }
+            qlen[q] = v;
+            v = (v + CAND_TRIP - 1) & ~(CAND_TRIP - 1);
+        }
         // inclusive scans over lanes 0..15 and 16..31
         for (int o = 1; o < 16; o <<= 1) {
             const int u = __shfl_up(v, o, 16);
@@ -304,17 +313,22 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     }
     __syncthreads();
     const int C = seg_c[9];
-    if (C > cmax || nc[2 * ncx] > ccand) {  // block-uniform: report the sizes, build nothing
+    // candidates before the padding, for the host's sizing
+    int ncu = 0;
+    for (int q = 0; q < 2 * ncx; ++q) ncu += qlen[q];
+    if (C > cmax || ncu > ccand) {  // block-uniform: report the sizes, build nothing
         if (tid == 0) {
             atomicMax(maxnb, max(C, cmax + 1));
-            atomicMax(maxnc, nc[2 * ncx]);
+            atomicMax(maxnc, ncu);
         }
         return;
     }
+    // cmax + 1 staged records: the neighbourhood and the padding record C
+    const int cm1 = cmax + 1;
     double *srec = stage;
-    int32_t *sslot = (int32_t *)(stage + (size_t)RW * cmax);
-    int32_t *sorig = sslot + (LOCAL ? 0 : cmax);
-    uint16_t *cand = (uint16_t *)(sorig + (HALF ? cmax : 0));
+    int32_t *sslot = (int32_t *)(stage + (size_t)RW * cm1);
+    int32_t *sorig = sslot + (LOCAL ? 0 : cm1);
+    uint16_t *cand = (uint16_t *)(sorig + (HALF ? cm1 : 0));
     {
         // two records per thread in flight; rows found without branches and
         // loads unconditional (past the end record C - 1 is read, not stored)
@@ -351,7 +365,8 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
             }
         }
     }
-    // candidate runs: list q (tile cell q / 2, half q % 2), row r
+    // candidate runs: list q (tile cell q / 2, half q % 2), row r; then
+    // each list's padding
     for (int w = wv; w < 9 * 2 * ncx; w += NW) {
         const int q = w / 9, r = w % 9;
         const int off = nc[q] + roff[q][r];
@@ -360,7 +375,13 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         const int b = seg_c[r] + rb - rs[r][0], m = re - rb;
         for (int u = lane; u < m; u += MDLJ_WAVE) cand[off + u] = (uint16_t)(b + u);
     }
-    if (tid < CAND_SLACK) cand[nc[2 * ncx] + tid] = 0;
+    for (int q = wv; q < 2 * ncx; q += NW)
+        for (int u = nc[q] + qlen[q] + lane; u < nc[q + 1]; u += MDLJ_WAVE) cand[u] = (uint16_t)C;
+    if (tid < CAND_SLACK) cand[nc[2 * ncx] + tid] = (uint16_t)C;
+    if (tid == 0) {
+        double *d = srec + RW * C;
+        d[0] = d[1] = d[2] = PAD_COORD;
+    }
     __syncthreads();
     const int ib = rs[4][1], ie = rs[4][ncx + 1];
     // starts of tile cells 1 .. STAGE_K - 1 (row 4, row cells 2 ..), for a
@@ -398,7 +419,6 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         const int mi = min(MDLJ_WAVE, (ie - i0 + NW - 1) / NW);
         for (int k = 0; k < mi; ++k) {
             const int i = i0 + NW * k;
-            const int own = __builtin_amdgcn_readlane(own_l, k);
             const double xi = bcast(xl, k), yi = bcast(yl, k), zi = bcast(zl, k);
             const int32_t oi = HALF ? __builtin_amdgcn_readlane(oi_l, k) : 0;
             const int pb = __builtin_amdgcn_readlane(pb_l, k);
@@ -407,18 +427,22 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
             uint16_t *row16 = (uint16_t *)nbr_out + t * cap;
             int32_t *row32 = (int32_t *)nbr_out + (ELL ? t : t * cap);
             uint32_t cnt = 0;
-            // two trips of 64 candidates in flight; every lane reads a valid
-            // index (slack entries are 0), lanes past the list are masked
-            for (int p0 = pb; p0 < pe; p0 += 2 * MDLJ_WAVE) {
-                const int rem = pe - p0;
+            // two trips of 64 candidates in flight; the list is padded to
+            // whole trips with the padding record, which no test passes
+            for (int p0 = pb; p0 < pe; p0 += CAND_TRIP) {
                 const int ka = cand[p0 + lane];
                 const int kb = cand[p0 + MDLJ_WAVE + lane];
                 const double *da = srec + RW * ka;
                 const double *db = srec + RW * kb;
                 const double ax = xi - da[0], ay = yi - da[1], az = zi - da[2];
                 const double bx = xi - db[0], by = yi - db[1], bz = zi - db[2];
-                bool ha = (lane < rem) & (ka != own) & (ax * ax + ay * ay + az * az < rl2);
-                bool hb = (lane + MDLJ_WAVE < rem) & (kb != own) & (bx * bx + by * by + bz * bz < rl2);
+                // 0 < r^2 < rl2 in one unsigned compare of the bit patterns
+                // (positive doubles order like their bits; r^2 = 0, i
+                // itself, wraps to the largest value): a single compare
+                // feeds the ballot directly
+                const uint64_t lim = (uint64_t)__double_as_longlong(rl2) - 1;
+                bool ha = (uint64_t)__double_as_longlong(ax * ax + ay * ay + az * az) - 1 < lim;
+                bool hb = (uint64_t)__double_as_longlong(bx * bx + by * by + bz * bz) - 1 < lim;
                 if (HALF) {
                     ha &= sorig[ka] > oi;
                     hb &= sorig[kb] > oi;
@@ -464,7 +488,7 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
         for (int w = 1; w < NW; ++w) wmax = max(wmax, wmx[w]);
         if (wmax > 0) atomic_max_rare(maxlen, wmax);
         atomic_max_rare(maxnb, C);
-        atomic_max_rare(maxnc, nc[2 * ncx]);
+        atomic_max_rare(maxnc, ncu);
     }
 }
 
@@ -1213,9 +1237,9 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
 
 size_t build_tile_lds(bool local, bool half, int cmax, int ccand)
 {
-    return (size_t)cmax * (3 * sizeof(double) + (local ? 0 : sizeof(int32_t)) +
-                           (half ? sizeof(int32_t) : 0)) +
-           (size_t)(ccand + CAND_SLACK) * sizeof(uint16_t);
+    return (size_t)(cmax + 1) * (3 * sizeof(double) + (local ? 0 : sizeof(int32_t)) +
+                                 (half ? sizeof(int32_t) : 0)) +
+           (size_t)(ccand + CAND_PAD + CAND_SLACK) * sizeof(uint16_t);
 }
 
 mdlj_status launch_build_tile(mdlj_ctx *ctx, bool local, bool half, bool ell, double rl2,
