@@ -54,6 +54,13 @@ __device__ __forceinline__ int64_t source_cell(int64_t e, const Grid &g)
     return src;
 }
 
+__global__ void k_clear_bins(int32_t *__restrict__ count, int64_t ncell, int32_t *__restrict__ flags)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < ncell) count[e] = 0;
+    if (e < 4) flags[e] = 0;
+}
+
 __global__ void k_bin_count(int64_t n, double *__restrict__ x, double *__restrict__ y,
                             double *__restrict__ z, Grid g, int32_t *__restrict__ cell_of,
                             int32_t *__restrict__ rank, int32_t *__restrict__ count,
@@ -322,19 +329,17 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
 #pragma unroll
     for (int o = FILL_LANES / 2; o > 0; o >>= 1) nlow += __shfl_xor(nlow, o, FILL_LANES);
     if (live && sub == 0) hstart[e] = b + nlow;
-}
-
-// The padding record at slot n_ext: far outside the box, no particle.
-__global__ void k_pad_record(PosT *__restrict__ rec, int64_t slot)
-{
-    if (threadIdx.x == 0) {
+    // the padding record at slot n_ext, after the last cell: far outside the
+    // box, no particle
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         PosT p;
         p.x = p.y = p.z = 1.0e7;
         p.t = 0;
         p.orig = -1;
-        rec[slot] = p;
+        rec[start[g.ncell_ext]] = p;
     }
 }
+
 
 __global__ void k_unpermute(int64_t n, const int32_t *__restrict__ slot_of,
                             const double *__restrict__ fx, const double *__restrict__ fy,
@@ -546,8 +551,8 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     int32_t *start = (int32_t *)ctx->b_start.p;
     int32_t *flags = (int32_t *)ctx->b_flags.p;
     hipStream_t s = ctx->stream;
-    HIPCHK(ctx, hipMemsetAsync(count, 0, sizeof(int32_t) * g.ncell_ext, s));
-    HIPCHK(ctx, hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, s));
+    // cell counts and the four binning flags cleared in one launch
+    k_clear_bins<<<ceil_div(g.ncell_ext, 256), 256, 0, s>>>(count, g.ncell_ext, flags);
     const int TB = 256;
     k_bin_count<<<ceil_div(n, TB), TB, 0, s>>>(n, ctx->x, ctx->y, ctx->z, g,
                                                  (int32_t *)ctx->b_cell_of.p,
@@ -579,7 +584,6 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     k_fill<<<ceil_div(g.ncell_ext, TB / FILL_LANES), TB, 0, s>>>(
         g, start, unordered, ctx->x, ctx->y, ctx->z, ctx->type, (PosT *)ctx->b_sorted.p,
         (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p, (int32_t *)ctx->b_hstart.p);
-    k_pad_record<<<1, 64, 0, s>>>((PosT *)ctx->b_sorted.p, n_ext);
     ctx->fx_valid = false;
     HIPCHK(ctx, hipGetLastError());
     ctx->grid = g;
