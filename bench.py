@@ -21,7 +21,7 @@ and the learned tuner; each is then run for --steps steps.  The headline
 value is the exhaustive choice's throughput in useful pairs (r < rc,
 unordered) per second.
 
-Prints one JSON line.  --gpus > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus > 1 is refused: the library runs on one GPU.
 """
 import argparse
 import json
@@ -157,8 +157,9 @@ def cpu_baseline(scene, budget_s):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(a spatial decomposition into one brick per GPU, with halo exchange, "
+              "is how the work would shard)", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"
