@@ -259,7 +259,9 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     __shared__ int roff[2 * STAGE_K][9]; // offset of row r's run inside list q
     __shared__ int wmx[NW];
     const int tid = threadIdx.x;
-    const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
+    // the wavefront index as a uniform value: the per-i addressing below
+    // then stays in scalar registers
+    const int lane = tid & (MDLJ_WAVE - 1), wv = __builtin_amdgcn_readfirstlane(tid / MDLJ_WAVE);
     const int64_t tile = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int tx = (int)((uint32_t)tile % (uint32_t)tiles_x);
     const uint32_t rr = (uint32_t)tile / (uint32_t)tiles_x;
@@ -458,8 +460,9 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
                 // only spills into its neighbours (the host then rebuilds with a
                 // larger capacity); column-major rows must stop at cap
                 if (LOCAL) {
-                    if (ha) row16[qa] = (uint16_t)ka;
-                    if (hb) row16[qb] = (uint16_t)kb;
+                    // 32-bit byte offsets from the row's (scalar) address
+                    if (ha) *(uint16_t *)((char *)row16 + 2u * qa) = (uint16_t)ka;
+                    if (hb) *(uint16_t *)((char *)row16 + 2u * qb) = (uint16_t)kb;
                 } else if (!ELL) {
                     if (ha) row32[qa] = sslot[ka];
                     if (hb) row32[qb] = sslot[kb];
