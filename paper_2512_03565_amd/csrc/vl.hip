@@ -664,7 +664,8 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     __shared__ double red[2 * NW];
     const double rc2 = tab.rc2d;
     const int tid = threadIdx.x;
-    const int lane = tid & (MDLJ_WAVE - 1), wv = tid / MDLJ_WAVE;
+    // the wavefront index as a uniform value (i-group bases in scalar registers)
+    const int lane = tid & (MDLJ_WAVE - 1), wv = __builtin_amdgcn_readfirstlane(tid / MDLJ_WAVE);
     if (MS) lds_table_load(lt, tab, tid, blockDim.x);
     // fused step: the padding record is carried over to the new records
     if (KD && blockIdx.x == 0 && tid == 0) {
