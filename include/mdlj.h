@@ -101,10 +101,11 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2 };
  * consecutive cells along x and stages the 9 rows of 6 cells around them;
  * the Verlet list then holds 16-bit indices into that staged set; with
  * FP32 pair arithmetic its records are kept as 32-bit fixed-point words of
- * one frame centred on the box (16 bytes with the species in global memory,
- * 12 in LDS; separations exact to within the grid 1/s, 1.2e-7 sigma for a
- * box of 175 sigma), with all-FP64 as FP64 (24 bytes).  A scene whose neighbourhoods do not fit the 64 KB staging
- * budget rejects staged configurations with MDLJ_ERR_ARG.  staged = 0 reads
+ * one frame centred on the box (12 bytes, the species apart, in global
+ * memory and in LDS; separations exact to within the grid 1/s, 1.2e-7
+ * sigma for a box of 175 sigma), with all-FP64 as FP64 (24 bytes).  A scene
+ * whose neighbourhoods do not fit the 64 KB staging budget rejects staged
+ * configurations with MDLJ_ERR_ARG.  staged = 0 reads
  * every j-particle from global memory.
  */
 typedef struct {
