@@ -1071,6 +1071,14 @@ static mdlj_status fx_words(mdlj_ctx *ctx, double *scale)
     for (int a = 0; a < 3; ++a) reach = std::max(reach, 0.5 * g.L[a] + g.h[a] * g.edge[a]);
     reach += ctx->rc + ctx->skin;
     const double fxs = std::exp2(std::floor(std::log2(1073741824.0 / reach)));
+    // the grid step bounds the error the words add to the FP32 pair law's:
+    // above 2^-21 of the smallest sigma (boxes beyond about 1000 sigma) it
+    // would take the forces past their 1e-5 bar, and the kernel is refused
+    double sig_min = ctx->sig[0];
+    for (int k = 1; k < ctx->nspec; ++k) sig_min = std::min(sig_min, ctx->sig[k]);
+    if (fxs * sig_min < 2097152.0)
+        return set_err(ctx, MDLJ_ERR_ARG,
+                       "box too large for the fixed-point frame of the FP32-pair staged kernel");
     const double c[3] = {0.5 * g.L[0], 0.5 * g.L[1], 0.5 * g.L[2]};
     *scale = fxs;
     if (ctx->fx_valid && ctx->fx_s == fxs && memcmp(ctx->fx_c, c, sizeof c) == 0) return MDLJ_OK;
@@ -1113,7 +1121,10 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
                                            (MS ? sizeof(int) : 0));
         if (lds > (size_t)STAGE_LDS_BYTES || N3) return -2;
         double fxs = 1.0;
-        if (FX && fx_words(ctx, &fxs) != MDLJ_OK) return -4;
+        if (FX) {
+            const mdlj_status fst = fx_words(ctx, &fxs);
+            if (fst != MDLJ_OK) return fst == MDLJ_ERR_ARG ? -5 : -4;
+        }
         const FxWords *fxr = nullptr;
         const int32_t *fxspec = nullptr;
         KickArgs kk = {};
@@ -1233,6 +1244,7 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
     if (nw == -2) return set_err(ctx, MDLJ_ERR_ARG, "neighbourhood too large for LDS staging");
     if (nw == -3) return set_err(ctx, MDLJ_ERR_ARG, "too many records for 32-bit buffer offsets");
     if (nw == -4) return MDLJ_ERR_NOMEM;
+    if (nw == -5) return MDLJ_ERR_ARG;  // message set by fx_words
     if (nw < 0) return set_err(ctx, MDLJ_ERR_ARG, "unsupported Verlet-list shape");
     HIPCHK(ctx, hipGetLastError());
     *nblocks = nw;

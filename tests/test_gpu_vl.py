@@ -234,6 +234,29 @@ def test_velocity_verlet_fused_step_with_early_rebuilds_bitwise(m, prec):
     assert np.array_equal(out[0][1], out[1][1])
 
 
+def test_vl_fixed_point_frame_limits(m, orc):
+    # The FP32-pair staged kernel reads fixed-point words of one frame per
+    # box.  A long box of 900 sigma still gets a grid step of 2^-21 sigma and
+    # meets the 1e-5 bar; at 1110 sigma the step would be 2^-20 and the
+    # kernel is refused (MDLJ_ERR_ARG), while the all-FP64 one is not.
+    pos, box = scenes.sc_lattice(600, 6, 6, 1.5, 0.1, seed=45)
+    s = dict(pos=pos, box=box, rc=2.5, eps=[1.0], sig=[1.0], types=None)
+    staged = [c for c in vl_configs(m) if len(c) == 7]
+    check(m, orc, s, staged[:2], "900 sigma", skin=0.3)
+    pos, box = scenes.sc_lattice(740, 6, 6, 1.5, 0.1, seed=46)
+    assert box[0] > 1100
+    with m.System(pos, box, 2.5, skin=0.3, precision=0) as sysm:
+        sysm.set_config(staged[0])
+        with pytest.raises(m.MdljError) as ei:
+            sysm.forces()
+        assert ei.value.status == -1
+        assert "fixed-point" in str(ei.value)
+        sysm.set_precision(1)
+        f, U, W = sysm.forces()
+    ref = orc.forces(pos, box, 2.5)
+    assert P.force_error(f, ref["f"]) <= 1e-12
+
+
 def test_vl_cells_exactly_list_range_wide(m, orc):
     # box 16 x 1.75 = 28 = 10 x (rc + skin): cells exactly rc + skin wide, so
     # the list build may not drop candidates by cell halves
