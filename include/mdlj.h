@@ -105,7 +105,9 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2 };
  * memory and in LDS; separations exact to within the grid 1/s, 1.2e-7
  * sigma for a box of 175 sigma), with all-FP64 as FP64 (24 bytes).  A scene
  * whose neighbourhoods do not fit the 64 KB staging budget rejects staged
- * configurations with MDLJ_ERR_ARG.  staged = 0 reads
+ * configurations with MDLJ_ERR_ARG, and so does a box whose fixed-point
+ * step would exceed 2^-21 of the smallest sigma (beyond about 1000 sigma)
+ * for the FP32-pair staged ones.  staged = 0 reads
  * every j-particle from global memory.
  */
 typedef struct {
