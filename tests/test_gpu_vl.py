@@ -203,6 +203,36 @@ def test_velocity_verlet_one_call_equals_single_steps(m, prec, cfg):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_velocity_verlet_fused_step_two_species_two_masses_bitwise(m, prec):
+    # The fused step picks 1/m by species; one-step calls use the separate
+    # kick kernels, which index the mass table directly.  Two species of
+    # different mass: one call of 30 steps equals 30 one-step calls bit for bit.
+    import torch
+    s = scenes.config4(ncell=12)
+    n = len(s["pos"])
+    v0 = scenes.mb_velocities(n, 1.0, 1.0, seed=81)
+    cfg = (1, 2, 16, 4, 0, 0, 1)
+    out = []
+    for single in (False, True):
+        with m.System(s["pos"], s["box"], s["rc"], s["eps"], s["sig"], types=s["types"],
+                      skin=0.3, rebuild_every=10, precision=prec, mass=[1.0, 2.5]) as sysm:
+            sysm.set_config(cfg)
+            vel = [torch.tensor(np.ascontiguousarray(v0[:, k]), device="cuda") for k in range(3)]
+            sysm.set_timing(True)
+            if single:
+                for _ in range(30):
+                    sysm.step_vv(vel, s["dt"], 1)
+            else:
+                sysm.step_vv(vel, s["dt"], 30)
+            _, nfused = sysm.get_timing_fused()
+            out.append((sysm.get_positions(), torch.stack(vel, 1).cpu().numpy(), nfused))
+    print(f"[fused step, two masses] prec={prec} fused calls {out[0][2]} / {out[1][2]}", flush=True)
+    assert out[0][2] > 20 and out[1][2] == 0
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_velocity_verlet_fused_step_with_early_rebuilds_bitwise(m, prec):
     # Fast particles cross skin/2 between scheduled rebuilds.  A staged force
     # call that takes the integrator step itself learns of the crossing only
