@@ -102,11 +102,11 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2 };
  * the Verlet list then holds 16-bit indices into that staged set; with
  * FP32 pair arithmetic its records are kept as 32-bit fixed-point words of
  * one frame centred on the box (12 bytes, the species apart, in global
- * memory and in LDS; separations exact to within the grid 1/s, 1.2e-7
+ * memory and in LDS; separations exact to within the grid 1/s, 5.8e-8
  * sigma for a box of 175 sigma), with all-FP64 as FP64 (24 bytes).  A scene
  * whose neighbourhoods do not fit the 64 KB staging budget rejects staged
  * configurations with MDLJ_ERR_ARG, and so does a box whose fixed-point
- * step would exceed 2^-21 of the smallest sigma (beyond about 1000 sigma)
+ * step would exceed 1e-7 of the smallest sigma (beyond about 310 sigma)
  * for the FP32-pair staged ones.  staged = 0 reads
  * every j-particle from global memory.
  */
@@ -121,6 +121,10 @@ typedef struct {
 } mdlj_config;
 
 /*
+ * A context is the container of section 2.3: it owns the particles and the
+ * neighbour structure built over them; positions are handed over as
+ * separate x, y, z arrays (structure of arrays, the layout section 2.3.1
+ * prefers for vector loads).
  * Create a context holding n particles (n >= 1) of n_species species
  * (1..8).  x, y, z: positions (float64, length n); type: species index per
  * particle (int32 in [0, n_species), or NULL for all zero).  mem_kind says
@@ -147,8 +151,10 @@ mdlj_status mdlj_set_cutoff(mdlj_ctx *ctx, double rc);
  * and are also rebuilt early once any particle has moved more than skin/2. */
 mdlj_status mdlj_set_skin(mdlj_ctx *ctx, double skin, int32_t rebuild_every);
 
-/* Parameters of species s: epsilon > 0, sigma > 0 (Lorentz-Berthelot mixing
- * across species).  Every species must be set before forces are computed. */
+/* Parameters of species s for the Lennard-Jones 12-6 pair law (section 4.1
+ * names the potential, section 2.1 Eq. 1 sums it over pairs): epsilon > 0,
+ * sigma > 0.  Unlike species mix by the Lorentz-Berthelot rule (the paper
+ * gives no rule).  Every species must be set before forces are computed. */
 mdlj_status mdlj_set_species(mdlj_ctx *ctx, int32_t s, double epsilon, double sigma);
 
 /* Energy shift so that u(rc) = 0: on (1, default) or off (0).  Forces are
@@ -183,6 +189,8 @@ mdlj_status mdlj_config_at(const mdlj_ctx *ctx, int32_t k, mdlj_config *cfg);
 mdlj_status mdlj_rebuild_neighbors(mdlj_ctx *ctx);
 
 /*
+ * The force on every particle as the sum of its pair forces inside the
+ * cutoff (section 2.1, Eq. 1), computed with the current configuration.
  * Forces on every particle (caller order) into fx, fy, fz (float64, length
  * n; mem_kind says where).  epot (total potential energy U = sum over pairs
  * of u) and virial (W = sum over pairs of r_ij . F_ij) are host float64
@@ -192,8 +200,10 @@ mdlj_status mdlj_rebuild_neighbors(mdlj_ctx *ctx);
 mdlj_status mdlj_compute_forces(mdlj_ctx *ctx, double *fx, double *fy, double *fz,
                                 int32_t mem_kind, double *epot, double *virial);
 
-/* Number of unordered pairs with r < rc (the useful pairs), counted on the
- * device from the current positions. */
+/* Number of unordered pairs with r < rc (the pairs inside the cutoff of
+ * section 2.1 that contribute to Eq. 1: the useful pairs), counted on the
+ * device from the current positions (by a linked-cell binning at rc, which
+ * replaces the current neighbour structure).  Synchronises. */
 mdlj_status mdlj_count_pairs(mdlj_ctx *ctx, int64_t *n_useful_pairs);
 
 /*
@@ -208,6 +218,37 @@ mdlj_status mdlj_count_pairs(mdlj_ctx *ctx, int64_t *n_useful_pairs);
  */
 mdlj_status mdlj_neighbor_stats(mdlj_ctx *ctx, int64_t *list_entries, int32_t *entry_bytes,
                                 int64_t *records);
+
+/*
+ * Index views of the neighbour structure, for checking it against a plain
+ * neighbour search (section 2.1.1).  Host arrays; both calls synchronise
+ * the stream.
+ *   get_cells   the linked cell of every particle in the last binning
+ *               (caller order), numbered cx + nx (cy + ny cz) over the
+ *               nx x ny x nz cells of the box (ncell3 = {nx, ny, nz}):
+ *               n = floor(L / r) cells of edge L / n >= r per axis (r = rc
+ *               for linked cells, rc + skin for Verlet lists; for cluster
+ *               lists the xy columns and z slabs), c = (int)(x_w n / L)
+ *               clamped to n - 1, x_w = x - L floor(x / L), each operation
+ *               rounded on its own.  MDLJ_ERR_STATE before the first
+ *               binning.  cell has length n.
+ *   get_pairs   the particle pairs the current list hands to the force
+ *               kernels, as caller indices (pi[k], pj[k]).  Verlet lists:
+ *               one pair per stored entry (full lists hold each pair in
+ *               both directions, Newton-3 lists once, with pi < pj).
+ *               Cluster lists: every pair of real particles (i in I, j in
+ *               J) of every stored cluster pair, a particle with itself
+ *               under the zero image shift left out.  *count receives the
+ *               number of pairs; with pi and pj NULL nothing else is done,
+ *               otherwise up to cap pairs are written and MDLJ_ERR_OVERFLOW
+ *               is returned when *count > cap.  An entry that names no
+ *               record gives pj = -2.  MDLJ_ERR_STATE for linked cells or
+ *               before a list was built.  Allocates temporary device
+ *               memory.
+ */
+mdlj_status mdlj_get_cells(mdlj_ctx *ctx, int32_t *cell, int32_t *ncell3);
+mdlj_status mdlj_get_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj,
+                           int64_t *count);
 
 /*
  * Choose a configuration.  FIXED keeps the current one; EXHAUSTIVE times

@@ -193,6 +193,9 @@ static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
     }
     // binning reads the caller-order positions
     STCHK(positions_for_rebuild(ctx));
+    // a build that fails part-way (a buffer that cannot grow) leaves nothing
+    // marked as current
+    ctx->built = false;
     STCHK(check_geometry(ctx, c));
     if (c.nbr_algo == MDLJ_NBR_VCL) {
         STCHK(vcl_build(ctx, c));
@@ -775,6 +778,36 @@ mdlj_status mdlj_neighbor_stats(mdlj_ctx *ctx, int64_t *list_entries, int32_t *e
         *entry_bytes = b.staged ? 2 : 4;
     }
     return MDLJ_OK;
+}
+
+mdlj_status mdlj_get_cells(mdlj_ctx *ctx, int32_t *cell, int32_t *ncell3)
+{
+    if (!ctx || !cell || !ncell3) return MDLJ_ERR_ARG;
+    const Grid &g = ctx->grid;
+    if (!ctx->b_cell_of.p || g.ncell_int <= 0)
+        return set_err(ctx, MDLJ_ERR_STATE, "no binning yet");
+    const int64_t n = ctx->n;
+    std::vector<int32_t> e(n);
+    HIPCHK(ctx, hipMemcpyAsync(e.data(), ctx->b_cell_of.p, sizeof(int32_t) * n,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t i = 0; i < n; ++i) {
+        // extended index -> interior cell coordinates -> x-fastest number
+        int c[3];
+        for (int a = 0; a < 3; ++a) c[a] = (int)((e[i] / g.stride[a]) % g.e[a]) - g.h[a];
+        cell[i] = c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
+    }
+    for (int a = 0; a < 3; ++a) ncell3[a] = g.n[a];
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_get_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj, int64_t *count)
+{
+    if (!ctx || !count || (pi == nullptr) != (pj == nullptr) || cap < 0) return MDLJ_ERR_ARG;
+    if (!ctx->built) return set_err(ctx, MDLJ_ERR_STATE, "no neighbour structure built");
+    if (ctx->built_cfg.nbr_algo == MDLJ_NBR_VL) return vl_pairs(ctx, cap, pi, pj, count);
+    if (ctx->built_cfg.nbr_algo == MDLJ_NBR_VCL) return vcl_pairs(ctx, cap, pi, pj, count);
+    return set_err(ctx, MDLJ_ERR_STATE, "linked cells keep no pair list");
 }
 
 }  // extern "C"

@@ -59,15 +59,18 @@ struct ForceOut {
 };
 
 // Fixed-point word of a coordinate for the FP32-pair staged kernel: the
-// coordinate relative to the frame centre c times s (a power of two),
-// rounded, plus 2^31.  Paired with the high word 0x43300000 a word is the
-// binary64 number 2^52 + word, so the difference of two words is their exact
-// integer separation.  The clamp keeps the conversion defined for a
-// particle that has run far off (the force call is then repeated after a
-// rebuild).
+// coordinate relative to the frame centre c times the scale s, rounded,
+// plus 2^31.  Paired with the high word 0x43300000 a word is the binary64
+// number 2^52 + word, so the difference of two words is their exact integer
+// separation.  Particles occupy words within FX_RANGE of the centre (the
+// scale is chosen so), which leaves at least 2^29 steps on every axis to
+// the padding record at word 0; the clamp keeps the conversion defined, and
+// that gap intact, for a particle that has run far off (the force call is
+// then repeated after a rebuild).
+#define FX_RANGE 1610612736.0  // 1.5 * 2^30
 __device__ __forceinline__ unsigned to_fx(double v, double c, double s)
 {
-    const double q = fmin(fmax(rint((v - c) * s), -2.0e9), 2.0e9);
+    const double q = fmin(fmax(rint((v - c) * s), -FX_RANGE), FX_RANGE);
     return (unsigned)(int)q ^ 0x80000000u;
 }
 
@@ -337,6 +340,10 @@ mdlj_status vcl_build(mdlj_ctx *ctx, const mdlj_config &cfg);
 mdlj_status vcl_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,
                        int64_t *nblocks);
 mdlj_status count_pairs_dev(mdlj_ctx *ctx, int64_t *out);
+// Caller-index views of the current lists (mdlj_get_pairs): *count pairs,
+// written to host arrays pi, pj when given (MDLJ_ERR_OVERFLOW if over cap).
+mdlj_status vl_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj, int64_t *count);
+mdlj_status vcl_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj, int64_t *count);
 
 // grid set-up shared by the containers: edge >= r_min per axis, h halo layers
 bool make_grid(const double *L, const double *r_min, const int *h, bool z_fastest, Grid *g);

@@ -5,9 +5,13 @@
 // The pair force is F_ij = 24 eps s6 (2 s6 - 1) / r^2 * d, s6 = (sig^2/r^2)^3,
 // d = x_i - x_j, for r^2 < rc^2 (cutoff, section 2.1); pair energy
 // 4 eps s6 (s6 - 1) - shift and pair virial r.F = 24 eps s6 (2 s6 - 1).
-// The separation d and r^2 are formed in FP64 from FP64 positions, so the
-// FP32 path keeps full accuracy of d even in large boxes; the pair law
-// itself (reciprocal, powers, force factor, energy) runs in T.
+// The separation d and r^2 are formed in FP64.  The all-FP64 kernels and
+// the FP32-pair kernels that read the FP64 records form them from FP64
+// positions; the FP32-pair staged Verlet-list kernel forms them from
+// fixed-point words (coordinates rounded to a grid of at most 1e-7 sigma,
+// see fx_words in vl.hip), exactly for the rounded coordinates, so its
+// separations carry that rounding and nothing more.  The pair law itself
+// (reciprocal, powers, force factor, energy) runs in T.
 #pragma once
 
 #include "atomics.h"

@@ -24,6 +24,8 @@
 //   k_vcl_ipl   i-per-lane: a lane owns one i; the M lanes of a cluster walk
 //               its list and read the M j's of each J in turn, so the j is
 //               the same for all lanes of the cluster (a broadcast load).
+#include <vector>
+
 #include "pair.h"
 
 namespace {
@@ -436,6 +438,43 @@ mdlj_status vcl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, For
     return MDLJ_OK;
 }
 
+// Particle pairs of the stored cluster pairs, for checking the lists: for
+// entry q of cluster I's row, the M x M pairs (i in I, j in J) at
+// off[I] + (q M + a) M + b as caller indices; a dummy member, or a particle
+// with itself under the zero shift, gives (-1, -1), and an entry naming no
+// cluster gives j = -2.
+__global__ __launch_bounds__(256) void k_vcl_pairs(const PosT *__restrict__ crec, int M,
+                                                   int64_t nclu, const int32_t *__restrict__ list,
+                                                   const int32_t *__restrict__ len, int32_t cap,
+                                                   const int64_t *__restrict__ off,
+                                                   int32_t *__restrict__ pi,
+                                                   int32_t *__restrict__ pj)
+{
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nclu) return;
+    const int32_t L = len[I];
+    for (int32_t q = 0; q < L; ++q) {
+        const int32_t e = list[I * cap + q];
+        const int64_t J = e & J_MASK;
+        const int code = (int)((uint32_t)e >> CODE_SHIFT);
+        for (int a = 0; a < M; ++a) {
+            const int32_t i = crec[I * M + a].orig;
+            for (int b = 0; b < M; ++b) {
+                const int64_t k = off[I] + ((int64_t)q * M + a) * M + b;
+                if (J >= nclu) {
+                    pi[k] = i;
+                    pj[k] = -2;
+                    continue;
+                }
+                const int32_t j = crec[J * M + b].orig;
+                const bool ok = i >= 0 && j >= 0 && !(i == j && code == 13);
+                pi[k] = ok ? i : -1;
+                pj[k] = ok ? j : -1;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 mdlj_status vcl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
@@ -530,6 +569,60 @@ mdlj_status vcl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         cap = (int64_t)(hmax * 1.1) + 8;
     }
     return set_err(ctx, MDLJ_ERR_OVERFLOW, "cluster list capacity could not be grown");
+}
+
+mdlj_status vcl_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj, int64_t *count)
+{
+    const int M = ctx->built_cfg.cluster_size;
+    const int64_t nclu = ctx->n_ext / M;
+    std::vector<int32_t> hl(nclu > 0 ? nclu : 1);
+    if (nclu > 0) {
+        HIPCHK(ctx, hipMemcpyAsync(hl.data(), ctx->b_nlen.p, sizeof(int32_t) * nclu,
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    std::vector<int64_t> off(nclu > 0 ? nclu : 1);
+    int64_t raw = 0;
+    for (int64_t I = 0; I < nclu; ++I) {
+        off[I] = raw;
+        raw += (int64_t)hl[I] * M * M;
+    }
+    std::vector<int32_t> h(2 * (raw > 0 ? raw : 1));
+    if (raw > 0) {
+        int64_t *d_off = nullptr;
+        int32_t *d_out = nullptr;
+        hipError_t e = hipMalloc((void **)&d_off, sizeof(int64_t) * nclu);
+        if (e == hipSuccess) e = hipMalloc((void **)&d_out, sizeof(int32_t) * 2 * raw);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * nclu, hipMemcpyHostToDevice,
+                               ctx->stream);
+        if (e == hipSuccess) {
+            k_vcl_pairs<<<ceil_div(nclu, 256), 256, 0, ctx->stream>>>(
+                (const PosT *)ctx->b_sorted.p, M, nclu, (const int32_t *)ctx->b_nbr.p,
+                (const int32_t *)ctx->b_nlen.p, (int32_t)ctx->vcl_cap, d_off, d_out, d_out + raw);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h.data(), d_out, sizeof(int32_t) * 2 * raw, hipMemcpyDeviceToHost,
+                               ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        (void)hipFree(d_off);
+        (void)hipFree(d_out);
+        if (e != hipSuccess) return hip_check(ctx, e, "cluster-list pair view");
+    }
+    // drop the (-1, -1) slots of dummies and of particles with themselves
+    int64_t cnt = 0;
+    for (int64_t k = 0; k < raw; ++k) {
+        if (h[k] == -1 && h[raw + k] == -1) continue;
+        if (pi && cnt < cap) {
+            pi[cnt] = h[k];
+            pj[cnt] = h[raw + k];
+        }
+        ++cnt;
+    }
+    *count = cnt;
+    if (pi && cnt > cap) return set_err(ctx, MDLJ_ERR_OVERFLOW, "pair arrays too short");
+    return MDLJ_OK;
 }
 
 mdlj_status vcl_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,

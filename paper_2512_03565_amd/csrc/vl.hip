@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "pair.h"
 
@@ -548,9 +549,9 @@ typedef __attribute__((address_space(3))) const unsigned lds_cuint;
 // difference of their words, formed by the same FP64 subtraction as for
 // FP64 coordinates and with no conversion instruction.  What is given up is
 // the rounding of each coordinate to the grid 1/s (s is chosen so that every
-// record, halo images included, stays within 2^30 steps of the centre: 1/s
-// is 1.2e-7 sigma for a box of 175 sigma), below the FP32 pair law's own
-// rounding.  The words are kept in global memory (12 bytes per record, the
+// record, halo images included, stays within 1.5 2^30 steps of the centre:
+// 1/s is 5.8e-8 sigma for a box of 175 sigma), below the FP32 pair law's
+// own rounding.  The words are kept in global memory (12 bytes per record, the
 // species apart), so that staging reads 12 bytes per record instead of the
 // 32 of the FP64 records, and a staged record takes 12 bytes of LDS instead
 // of 24.
@@ -574,8 +575,9 @@ __global__ void k_fx_records(int64_t nrec, const PosT *__restrict__ rec, double 
 }
 
 // the padding record: word 0 on every axis (coordinate -2^31), at least
-// sqrt(3) 2^30 / s from any staged particle (whose coordinates stay within
-// +-2^30), beyond the cutoff
+// sqrt(3) 2^29 / s from any staged particle (whose coordinates stay within
+// FX_RANGE = 1.5 2^30 steps); with s = FX_RANGE / reach that is 0.58 reach,
+// and reach is at least 3.5 (rc + skin), so beyond the cutoff
 constexpr unsigned FX_PAD = 0u;
 
 // Staging of the fixed-point layout: record k of the nine concatenated rows
@@ -1063,20 +1065,22 @@ __global__ __launch_bounds__(256) void k_vl_wpi(const PosT *__restrict__ rec,
 // The fixed-point words of the current records, converted when stale.  The
 // frame is centred on the box; every record (halo images one cell beyond
 // the box) plus rc + skin for particles that drift before a rebuild stays
-// within 2^30 steps of the centre.  *scale receives s.
+// within FX_RANGE steps of the centre.  *scale receives s.
 static mdlj_status fx_words(mdlj_ctx *ctx, double *scale)
 {
     const Grid &g = ctx->grid;
     double reach = 0.0;
     for (int a = 0; a < 3; ++a) reach = std::max(reach, 0.5 * g.L[a] + g.h[a] * g.edge[a]);
     reach += ctx->rc + ctx->skin;
-    const double fxs = std::exp2(std::floor(std::log2(1073741824.0 / reach)));
-    // the grid step bounds the error the words add to the FP32 pair law's:
-    // above 2^-21 of the smallest sigma (boxes beyond about 1000 sigma) it
-    // would take the forces past their 1e-5 bar, and the kernel is refused
+    const double fxs = FX_RANGE / reach;
+    // Rounding each coordinate to the grid 1/s moves a force by up to about
+    // 55 (1/s) / sigma relative to the scene's force scale (measured against
+    // the FP64 oracle on dense liquids and lattices); with the FP32 pair
+    // law's own 2.5e-6 the 1e-5 bar holds while 1/s <= 1e-7 of the smallest
+    // sigma (boxes up to about 310 sigma); beyond, the kernel is refused
     double sig_min = ctx->sig[0];
     for (int k = 1; k < ctx->nspec; ++k) sig_min = std::min(sig_min, ctx->sig[k]);
-    if (fxs * sig_min < 2097152.0)
+    if (fxs * sig_min < 1.0e7)
         return set_err(ctx, MDLJ_ERR_ARG,
                        "box too large for the fixed-point frame of the FP32-pair staged kernel");
     const double c[3] = {0.5 * g.L[0], 0.5 * g.L[1], 0.5 * g.L[2]};
@@ -1315,6 +1319,62 @@ __global__ __launch_bounds__(256) void k_list_entries(const int32_t *__restrict_
     }
 }
 
+// Caller indices of the pairs a Verlet list holds, for checking the list:
+// entry k of compact row t becomes (caller index of i, caller index of j)
+// at off[t] + k.  layout 0: column-major slots (nbr[k n + t]); 1: row-major
+// slots (nbr[t cap + k]); 2: 16-bit staged indices, decoded through the cell
+// starts of the nine rows of i's x-tile, the order in which the force
+// kernel stages them.  An entry that names no record gives j = -2.
+__global__ __launch_bounds__(256) void k_vl_pairs(const PosT *__restrict__ rec,
+                                                  const int32_t *__restrict__ start,
+                                                  const int32_t *__restrict__ ilist,
+                                                  const int32_t *__restrict__ cell_of, Grid g,
+                                                  int64_t n, int64_t nrec, const void *nbr,
+                                                  const int32_t *__restrict__ len, int32_t cap,
+                                                  int layout, const int64_t *__restrict__ off,
+                                                  int32_t *__restrict__ pi,
+                                                  int32_t *__restrict__ pj)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t oi = rec[ilist[t]].orig;
+    const int32_t L = len[t];
+    int32_t *a = pi + off[t];
+    int32_t *b = pj + off[t];
+    int32_t rb[9], rl[9];
+    if (layout == 2) {
+        const int64_t e = cell_of[oi];
+        const int cx = (int)(e % g.stride[1]) - g.h[0];
+        const int cy = (int)((e / g.stride[1]) % g.e[1]) - g.h[1];
+        const int cz = (int)(e / g.stride[2]) - g.h[2];
+        const int cx0 = (cx / STAGE_K) * STAGE_K;
+        const int ncx = min(STAGE_K, g.n[0] - cx0);
+        for (int r = 0; r < 9; ++r) {
+            const int dy = r % 3 - 1, dz = r / 3 - 1;
+            const int64_t ej = (int64_t)(cy + dy + g.h[1]) * g.stride[1] +
+                               (int64_t)(cz + dz + g.h[2]) * g.stride[2] + cx0 - 1 + g.h[0];
+            rb[r] = start[ej];
+            rl[r] = start[ej + ncx + 2] - start[ej];
+        }
+    }
+    for (int32_t k = 0; k < L; ++k) {
+        int64_t sj = -1;
+        if (layout == 2) {
+            int32_t q = ((const uint16_t *)nbr)[t * cap + k];
+            for (int r = 0; r < 9 && sj < 0; ++r) {
+                if (q < rl[r]) sj = rb[r] + q;
+                else q -= rl[r];
+            }
+        } else if (layout == 1) {
+            sj = ((const int32_t *)nbr)[t * cap + k];
+        } else {
+            sj = ((const int32_t *)nbr)[(int64_t)k * n + t];
+        }
+        a[k] = oi;
+        b[k] = (sj >= 0 && sj < nrec) ? rec[sj].orig : -2;
+    }
+}
+
 }  // namespace
 
 mdlj_status vl_list_entries(mdlj_ctx *ctx, int64_t *entries)
@@ -1449,6 +1509,51 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         cap = ((int64_t)(hmax[0] * 1.1) + 8 + 7) & ~(int64_t)7;
     }
     return set_err(ctx, MDLJ_ERR_OVERFLOW, "Verlet list capacity could not be grown");
+}
+
+mdlj_status vl_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj, int64_t *count)
+{
+    const int64_t n = ctx->n;
+    const mdlj_config &b = ctx->built_cfg;
+    std::vector<int32_t> hl(n);
+    HIPCHK(ctx, hipMemcpyAsync(hl.data(), ctx->b_nlen.p, sizeof(int32_t) * n,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<int64_t> off(n);
+    int64_t total = 0;
+    for (int64_t t = 0; t < n; ++t) {
+        off[t] = total;
+        total += hl[t];
+    }
+    *count = total;
+    if (!pi) return MDLJ_OK;
+    if (total > cap) return set_err(ctx, MDLJ_ERR_OVERFLOW, "pair arrays too short");
+    const int layout = b.staged ? 2 : (b.order != MDLJ_ORD_I_PER_LANE ? 1 : 0);
+    int64_t *d_off = nullptr;
+    int32_t *d_out = nullptr;
+    hipError_t e = hipMalloc((void **)&d_off, sizeof(int64_t) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_out, sizeof(int32_t) * 2 * (total > 0 ? total : 1));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice,
+                           ctx->stream);
+    if (e == hipSuccess) {
+        k_vl_pairs<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
+            (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
+            (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, ctx->grid, n,
+            ctx->n_ext, ctx->b_nbr.p, (const int32_t *)ctx->b_nlen.p, (int32_t)ctx->nbr_cap, layout,
+            d_off, d_out, d_out + total);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pi, d_out, sizeof(int32_t) * total, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pj, d_out + total, sizeof(int32_t) * total, hipMemcpyDeviceToHost,
+                           ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(d_off);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_check(ctx, e, "Verlet-list pair view");
+    return MDLJ_OK;
 }
 
 mdlj_status vl_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,

@@ -120,6 +120,9 @@ _SIGS = {
                            C.POINTER(C.c_int32)],
     "mdlj_get_timing": [_ctxp, _d, _d, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "mdlj_get_timing_fused": [_ctxp, _d, C.POINTER(C.c_int64)],
+    "mdlj_get_cells": [_ctxp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+    "mdlj_get_pairs": [_ctxp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                       C.POINTER(C.c_int64)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(lib, _name)
@@ -301,6 +304,27 @@ class System:
         b = C.c_int32()
         check(lib.mdlj_neighbor_stats(self.ctx, C.byref(e), C.byref(b), C.byref(r)), self.ctx)
         return e.value, b.value, r.value
+
+    def get_cells(self):
+        """(cell of every particle in the last binning, x-fastest over the
+        interior grid; grid cell counts (nx, ny, nz))."""
+        cell = np.empty(self.n, np.int32)
+        nc = np.empty(3, np.int32)
+        i32 = C.POINTER(C.c_int32)
+        check(lib.mdlj_get_cells(self.ctx, cell.ctypes.data_as(i32), nc.ctypes.data_as(i32)),
+              self.ctx)
+        return cell, tuple(int(v) for v in nc)
+
+    def get_pairs(self):
+        """(pi, pj) caller indices of the pairs the current list holds."""
+        cnt = C.c_int64()
+        check(lib.mdlj_get_pairs(self.ctx, 0, None, None, C.byref(cnt)), self.ctx)
+        pi = np.empty(cnt.value, np.int32)
+        pj = np.empty(cnt.value, np.int32)
+        i32 = C.POINTER(C.c_int32)
+        check(lib.mdlj_get_pairs(self.ctx, cnt.value, pi.ctypes.data_as(i32),
+                                 pj.ctypes.data_as(i32), C.byref(cnt)), self.ctx)
+        return pi[: cnt.value], pj[: cnt.value]
 
     def count_pairs(self):
         n = C.c_int64()

@@ -18,6 +18,41 @@ import numpy as np
 F32_BAND = 4 * 2.0 ** -24
 F64_BAND = 4 * 2.0 ** -53
 
+# Words of the fixed-point frame of the FP32-pair staged kernel lie within
+# this many grid steps of the box centre (the library's frame rule).
+FX_RANGE = 1.5 * 2.0 ** 30
+
+
+def fx_step(box, rc, skin):
+    """Grid step 1/s of the fixed-point words for a box: s = FX_RANGE / reach,
+    reach = the largest half edge plus one halo cell (edge L / floor(L /
+    (rc + skin))) plus rc + skin."""
+    rl = rc + skin
+    reach = max(0.5 * L + L / np.floor(L / rl) for L in np.asarray(box, np.float64)) + rl
+    return reach / FX_RANGE
+
+
+def fx_band(box, rc, skin):
+    """Cutoff band of the FP32-pair staged kernel.  It decides r^2 < rc^2 on
+    the exact separation of coordinates rounded to the grid 1/s (at most half
+    a step each), so its r^2 differs from the oracle's by at most
+    2 |d| sqrt(3) step + 3 step^2: relative to rc^2, 2 sqrt(3) step / rc
+    (plus rounding of r^2).  Never narrower than the FP32 band."""
+    step = fx_step(box, rc, skin)
+    return max(F32_BAND, (2 * np.sqrt(3) * step / rc + 3 * (step / rc) ** 2) * (1 + 1e-6)
+               + 4 * 2.0 ** -53)
+
+
+def list_band(box, rl):
+    """Band of (rc + skin)^2 in which the list builds may decide a pair
+    differently from the oracle: both form d in FP64, the builds from halo
+    images at x +- L (one rounding of at most half an ulp of L), the oracle
+    by the minimum image of x_i - x_j (another); |d| <= rl per axis gives
+    |d(r^2)| <= 2 sqrt(3) rl ulp(L), relative 2 sqrt(3) ulp(L) / rl, doubled,
+    plus a few roundings of r^2."""
+    return 4 * np.sqrt(3) * float(np.spacing(np.max(np.asarray(box, np.float64)))) / rl + \
+        8 * 2.0 ** -53
+
 
 def frms(f):
     return float(np.sqrt((f * f).sum(1).mean())) if len(f) else 0.0

@@ -65,3 +65,12 @@ def test_null_context_is_rejected(m):
     n = C.c_int32()
     assert m.lib.mdlj_config_count(None, C.byref(n)) == -1
     assert m.lib.mdlj_last_error(None) == b"null context"
+
+
+def test_index_views_reject_bad_arguments(m):
+    i32 = C.POINTER(C.c_int32)
+    cell = np.empty(4, np.int32)
+    nc = np.empty(3, np.int32)
+    assert m.lib.mdlj_get_cells(None, cell.ctypes.data_as(i32), nc.ctypes.data_as(i32)) == -1
+    cnt = C.c_int64()
+    assert m.lib.mdlj_get_pairs(None, 0, None, None, C.byref(cnt)) == -1

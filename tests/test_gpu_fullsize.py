@@ -39,7 +39,7 @@ def test_headline_1m_every_particle(m, orc):
             1: ["VL/wave-per-i/16x4/lds", "LC/i-per-lane/k1"]}
     with m.System(pos, box, rc, skin=s["skin"], rebuild_every=s["rebuild_every"]) as sysm:
         for prec, names in runs.items():
-            band = P.F32_BAND if prec == 0 else P.F64_BAND
+            band = P.fx_band(box, rc, s["skin"]) if prec == 0 else P.F64_BAND
             slack, su, sw, namb = P.boundary_slack(orc, pos, box, rc, [1.0], [1.0], None, True,
                                                    band)
             sysm.set_precision(prec)
@@ -66,7 +66,7 @@ def test_config4_4m_two_species_cluster_lists_sampled(m, orc):
     with m.System(pos, box, rc, s["eps"], s["sig"], types=types, skin=s["skin"],
                   rebuild_every=s["rebuild_every"]) as sysm:
         for prec in (0, 1):
-            band = P.F32_BAND if prec == 0 else P.F64_BAND
+            band = P.fx_band(box, rc, s["skin"]) if prec == 0 else P.F64_BAND
             slack = P.boundary_slack_subset(orc, pos, box, rc, s["eps"], s["sig"], types, True,
                                             band, idx)
             sysm.set_precision(prec)

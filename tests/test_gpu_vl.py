@@ -35,7 +35,7 @@ def check(m, orc, s, configs, label, precs=(0, 1), skin=0.3):
     with m.System(pos, box, rc, s["eps"], s["sig"], types=types, skin=skin) as sysm:
         for prec in precs:
             sysm.set_precision(prec)
-            band = P.F32_BAND if prec == 0 else P.F64_BAND
+            band = P.fx_band(box, rc, skin) if prec == 0 else P.F64_BAND
             slack, su, sw, namb = P.boundary_slack(orc, pos, box, rc, s["eps"], s["sig"], types,
                                                    True, band)
             for cfg in configs:
@@ -232,6 +232,38 @@ def test_velocity_verlet_fused_step_two_species_two_masses_bitwise(m, prec):
     assert np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("cfg", [(1, 2, 16, 4, 0, 0, 1), (1, 0, 0, 0, 0, 0), (1, 2, 4, 16, 0, 1),
+                                 (0, 0, 1, 1, 0, 0)])
+def test_velocity_verlet_two_masses_match_oracle(m, orc, cfg):
+    # Two species of masses 1 and 2.5 (mdlj_set_mass): 20 FP64 steps with
+    # list rebuilds every 5 against the oracle's velocity Verlet with the
+    # same per-species masses (section 2.1), at the trajectory bars of the
+    # one-mass test.
+    import torch
+    s = scenes.config4(ncell=12)
+    masses = np.array([1.0, 2.5])
+    types = s["types"]
+    v0 = scenes.mb_velocities(len(types), 1.0, masses[types], seed=85)
+    p_ref, v_ref, f_ref, ep, ek = orc.vv(s["pos"], v0, s["box"], s["rc"], s["dt"], 20, s["eps"],
+                                         s["sig"], mass=masses, types=types)
+    with m.System(s["pos"], s["box"], s["rc"], s["eps"], s["sig"], types=types, skin=0.3,
+                  rebuild_every=5, precision=1, mass=masses) as sysm:
+        sysm.set_config(cfg)
+        vel = [torch.tensor(np.ascontiguousarray(v0[:, k]), device="cuda") for k in range(3)]
+        sysm.step_vv(vel, s["dt"], 20)
+        f, U, W = sysm.forces()
+        pos = sysm.get_positions()
+    v = torch.stack(vel, 1).cpu().numpy()
+    d = pos - p_ref
+    d -= s["box"] * np.rint(d / s["box"])
+    print(f"[two masses vs oracle] cfg={cfg} max |dx| {np.abs(d).max():.2e} "
+          f"max |dv| {np.abs(v - v_ref).max():.2e}", flush=True)
+    assert np.abs(d).max() < 1e-10, cfg
+    assert np.abs(v - v_ref).max() < 1e-9, cfg
+    assert P.force_error(f, f_ref) < 1e-9, cfg
+    assert U == pytest.approx(ep[-1], rel=1e-10)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_velocity_verlet_fused_step_with_early_rebuilds_bitwise(m, prec):
     # Fast particles cross skin/2 between scheduled rebuilds.  A staged force
@@ -266,15 +298,18 @@ def test_velocity_verlet_fused_step_with_early_rebuilds_bitwise(m, prec):
 
 def test_vl_fixed_point_frame_limits(m, orc):
     # The FP32-pair staged kernel reads fixed-point words of one frame per
-    # box.  A long box of 900 sigma still gets a grid step of 2^-21 sigma and
-    # meets the 1e-5 bar; at 1110 sigma the step would be 2^-20 and the
-    # kernel is refused (MDLJ_ERR_ARG), while the all-FP64 one is not.
-    pos, box = scenes.sc_lattice(600, 6, 6, 1.5, 0.1, seed=45)
+    # box.  A long box at liquid density whose grid step is just under the
+    # 1e-7 sigma limit (297 sigma) still meets the 1e-5 bar, with the cutoff
+    # band derived from that step; at 323 sigma the step would exceed the
+    # limit and the kernel is refused (MDLJ_ERR_ARG), while the all-FP64 one
+    # is not.
+    pos, box = scenes.fcc_lattice(170, 5, 5, 0.75, 0.05, seed=45)
+    assert 0.9e-7 < P.fx_step(box, 2.5, 0.3) < 1e-7
     s = dict(pos=pos, box=box, rc=2.5, eps=[1.0], sig=[1.0], types=None)
     staged = [c for c in vl_configs(m) if len(c) == 7]
-    check(m, orc, s, staged[:2], "900 sigma", skin=0.3)
-    pos, box = scenes.sc_lattice(740, 6, 6, 1.5, 0.1, seed=46)
-    assert box[0] > 1100
+    check(m, orc, s, staged[:2] + staged[-2:], "297 sigma", precs=(0,), skin=0.3)
+    pos, box = scenes.fcc_lattice(185, 5, 5, 0.75, 0.05, seed=46)
+    assert P.fx_step(box, 2.5, 0.3) > 1e-7
     with m.System(pos, box, 2.5, skin=0.3, precision=0) as sysm:
         sysm.set_config(staged[0])
         with pytest.raises(m.MdljError) as ei:

@@ -250,6 +250,59 @@ def test_velocity_verlet_energy_and_time_reversal(orc):
     assert np.abs(vel2 + s["vel"]).max() < 1e-9
 
 
+def test_velocity_verlet_mass_scaling(orc):
+    # Velocity Verlet with mass m, step dt and start velocities v0 visits the
+    # same positions as mass 1, step dt/sqrt(m) and velocities v0 sqrt(m):
+    # both kicks change v by F dt/(2m) = sqrt(m) F (dt/sqrt(m))/2 scaled
+    # back by sqrt(m), and both drifts move x by dt v (section 2.1 names the
+    # integrator; the identity is exact in real arithmetic).  Velocities
+    # differ by the factor sqrt(m), kinetic energies not at all.  A kick
+    # that multiplied by m, or missed the mass, fails this.
+    s = scenes.config1()
+    m = 2.5
+    r = math.sqrt(m)
+    pa, va, fa, epa, eka = orc.vv(s["pos"], s["vel"], s["box"], s["rc"], s["dt"], 10, mass=m)
+    pb, vb, fb, epb, ekb = orc.vv(s["pos"], s["vel"] * r, s["box"], s["rc"], s["dt"] / r, 10,
+                                  mass=1.0)
+    d = pa - pb
+    d -= s["box"] * np.rint(d / s["box"])
+    assert np.abs(d).max() < 1e-12
+    assert np.abs(va * r - vb).max() < 1e-11
+    assert np.allclose(eka, ekb, rtol=1e-12, atol=0)
+    assert np.allclose(epa, epb, rtol=1e-12, atol=0)
+    # and the mass does change the trajectory
+    pc, _, _, _, _ = orc.vv(s["pos"], s["vel"], s["box"], s["rc"], s["dt"], 10, mass=1.0)
+    d = pa - pc
+    d -= s["box"] * np.rint(d / s["box"])
+    assert np.abs(d).max() > 1e-6
+
+
+def test_velocity_verlet_two_masses_conserve_momentum_and_energy(orc):
+    # Two species of masses 1 and 2.5.  Pair forces cancel (Newton's third
+    # law, section 2.1), so each kick adds sum_i m_i (F_i dt / 2 m_i) = 0 to
+    # the total momentum: it stays at its start value, zero, to rounding.  A
+    # kick that used one species' mass for all particles would change it by
+    # sum_i (m_i / m_used - 1) F_i dt / 2.  The kinetic energy is
+    # 1/2 sum m_i v_i^2 at the start, and E = U + K stays near its start.
+    s = scenes.config4(ncell=6)
+    types = s["types"]
+    masses = np.array([1.0, 2.5])
+    mi = masses[types]
+    v0 = scenes.mb_velocities(len(types), 1.0, mi, seed=83)
+    p, v, f, ep, ek = orc.vv(s["pos"], v0, s["box"], s["rc"], s["dt"], 20, s["eps"], s["sig"],
+                             mass=masses, types=types)
+    scale = (mi[:, None] * np.abs(v)).sum()
+    assert np.abs((mi[:, None] * v0).sum(0)).max() < 1e-13 * scale
+    assert np.abs((mi[:, None] * v).sum(0)).max() < 1e-12 * scale
+    assert ek[0] == pytest.approx(0.5 * (mi[:, None] * v0 * v0).sum(), rel=1e-14)
+    e = ep + ek
+    assert np.abs(e - e[0]).max() / abs(e[0]) <= 1e-4
+    # with the masses swapped the same start moves differently
+    p2, v2, _, _, _ = orc.vv(s["pos"], v0, s["box"], s["rc"], s["dt"], 20, s["eps"], s["sig"],
+                             mass=masses[::-1].copy(), types=types)
+    assert np.abs((mi[:, None] * v2).sum(0)).max() > 1e-6 * scale
+
+
 # ---------------------------------------------------------------- network
 
 def test_mlp_forward_golden(orc):
