@@ -200,6 +200,30 @@ mdlj_status mdlj_rebuild_neighbors(mdlj_ctx *ctx);
 mdlj_status mdlj_compute_forces(mdlj_ctx *ctx, double *fx, double *fy, double *fz,
                                 int32_t mem_kind, double *epot, double *virial);
 
+/*
+ * mdlj_compute_forces for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * fx, fy, fz: device float64 arrays (length n, caller order); epot and
+ * virial as for mdlj_compute_forces (host, may be NULL; given, the call
+ * synchronises).  The call computes exactly what mdlj_compute_forces
+ * computes, with the same kernels, but allocates nothing: the force
+ * kernels' per-workgroup energy/virial partials go to a static device array
+ * of 2^22 doubles (32 MiB, one per GPU, held until the process ends), and
+ * every other buffer is the context's own.  When the call would have to
+ * create or grow one of those (the first force call of a context, a rebuild
+ * that needs more list, record or cell memory than earlier calls sized, a
+ * timing event) it returns MDLJ_ERR_NOMEM and allocates nothing; one
+ * mdlj_compute_forces call sizes the context, after which the neighbour
+ * structure is rebuilt on the next call.  A configuration whose energy
+ * partials exceed the scratch array (contexts beyond about two million
+ * particles) gives MDLJ_ERR_ARG.  Every call on one GPU uses that GPU's
+ * array, and each launch writes all the partials it reads, so nothing has
+ * to be cleared between calls; calls that overlap on one GPU (two streams
+ * or threads at once) race on the array.
+ */
+mdlj_status mdlj_compute_forces_noalloc(mdlj_ctx *ctx, double *fx, double *fy, double *fz,
+                                        double *epot, double *virial);
+
 /* Number of unordered pairs with r < rc (the pairs inside the cutoff of
  * section 2.1 that contribute to Eq. 1: the useful pairs), counted on the
  * device from the current positions (by a linked-cell binning at rc, which

@@ -11,7 +11,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
+#include <string>
 
 #include "internal.h"
 
@@ -34,6 +36,10 @@ mdlj_status ensure(mdlj_ctx *ctx, DevBuf &b, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     if (b.bytes >= bytes) return MDLJ_OK;
+    if (ctx->no_alloc)
+        return set_err(ctx, MDLJ_ERR_NOMEM,
+                       "the allocation-free call would have to grow a device buffer to " +
+                           std::to_string(bytes) + " bytes (call mdlj_compute_forces first)");
     if (b.p) {
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
         HIPCHK(ctx, hipFree(b.p));
@@ -47,6 +53,22 @@ mdlj_status ensure(mdlj_ctx *ctx, DevBuf &b, size_t bytes)
         return hip_check(ctx, e, "hipMalloc");
     }
     b.bytes = want;
+    return MDLJ_OK;
+}
+
+mdlj_status partial_buffer(mdlj_ctx *ctx, int64_t nvals, double **out)
+{
+    if (ctx->partial_ext) {
+        if (nvals > ctx->partial_ext_cap)
+            return set_err(ctx, MDLJ_ERR_ARG,
+                           "energy partials of " + std::to_string(nvals) +
+                               " doubles exceed the allocation-free scratch of " +
+                               std::to_string(ctx->partial_ext_cap));
+        *out = ctx->partial_ext;
+        return MDLJ_OK;
+    }
+    STCHK(ensure(ctx, ctx->b_partial, sizeof(double) * nvals));
+    *out = (double *)ctx->b_partial.p;
     return MDLJ_OK;
 }
 
@@ -326,6 +348,9 @@ static mdlj_status take_event(mdlj_ctx *ctx, hipEvent_t *e)
         ctx->ev_pending.pop_front();
     }
     if (ctx->ev_pool.empty()) {
+        if (ctx->no_alloc)
+            return set_err(ctx, MDLJ_ERR_NOMEM,
+                           "the allocation-free call would have to create a timing event");
         // timing only: no system-scope fence when recorded (no cache
         // write-back between the timed kernels)
         HIPCHK(ctx, hipEventCreateWithFlags(e, hipEventDisableSystemFence));
@@ -431,6 +456,37 @@ mdlj_status forces_internal(mdlj_ctx *ctx, bool positions_changed, double *UW, F
     ctx->steps_since_build++;
     ctx->forces_valid = to_caller;
     if (fo_out) *fo_out = fo;
+    return MDLJ_OK;
+}
+
+// ------------------------------------------------- allocation-free scratch
+
+// Device scratch of mdlj_compute_forces_noalloc: the per-workgroup (U, W)
+// partials of the force kernels, 2^22 doubles (32 MiB), enough for every
+// configuration of a context of up to about two million particles.  Each GPU
+// holds its own copy for the life of the process.  Host code never uses the
+// name itself (a host-side stand-in): the device address of each GPU's copy
+// is taken once with hipGetSymbolAddress while that GPU is current.
+#define MDLJ_SCRATCH_DOUBLES (1 << 22)
+#define MDLJ_SCRATCH_MAX_DEVICES 64
+static __device__ __align__(256) double scratch[MDLJ_SCRATCH_DOUBLES];
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[MDLJ_SCRATCH_MAX_DEVICES] = {};
+
+static mdlj_status scratch_address(mdlj_ctx *ctx, double **out)
+{
+    int dev = -1;
+    HIPCHK(ctx, hipGetDevice(&dev));
+    if (dev < 0 || dev >= MDLJ_SCRATCH_MAX_DEVICES)
+        return set_err(ctx, MDLJ_ERR_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_err(ctx, MDLJ_ERR_HIP, "no device address for the scratch array");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
     return MDLJ_OK;
 }
 
@@ -709,6 +765,34 @@ mdlj_status mdlj_compute_forces(mdlj_ctx *ctx, double *fx, double *fy, double *f
     STCHK(copy_out(ctx, fy, ctx->fy, mem_kind));
     STCHK(copy_out(ctx, fz, ctx->fz, mem_kind));
     if (mem_kind == MDLJ_MEM_HOST) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (epot) *epot = UW[0];
+    if (virial) *virial = UW[1];
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_compute_forces_noalloc(mdlj_ctx *ctx, double *fx, double *fy, double *fz,
+                                        double *epot, double *virial)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (!fx || !fy || !fz) return set_err(ctx, MDLJ_ERR_ARG, "bad output pointers");
+    double *scr = nullptr;
+    STCHK(scratch_address(ctx, &scr));
+    ctx->no_alloc = true;
+    ctx->partial_ext = scr;
+    ctx->partial_ext_cap = MDLJ_SCRATCH_DOUBLES;
+    double UW[2] = {0, 0};
+    const bool want = epot || virial;
+    mdlj_status st = forces_internal(ctx, ctx->pos_changed, want ? UW : nullptr);
+    if (st == MDLJ_OK) {
+        ctx->pos_changed = false;
+        st = copy_out(ctx, fx, ctx->fx, MDLJ_MEM_DEVICE);
+        if (st == MDLJ_OK) st = copy_out(ctx, fy, ctx->fy, MDLJ_MEM_DEVICE);
+        if (st == MDLJ_OK) st = copy_out(ctx, fz, ctx->fz, MDLJ_MEM_DEVICE);
+    }
+    ctx->no_alloc = false;
+    ctx->partial_ext = nullptr;
+    ctx->partial_ext_cap = 0;
+    if (st != MDLJ_OK) return st;
     if (epot) *epot = UW[0];
     if (virial) *virial = UW[1];
     return MDLJ_OK;

@@ -302,8 +302,7 @@ mdlj_status lc_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
         // partial buffer sized by the launch: one (U, W) per workgroup
         const Grid &g = ctx->grid;
         int64_t maxb = g.ncell_int;
-        STCHK(ensure(ctx, ctx->b_partial, sizeof(double) * 2 * maxb));
-        fo.partial = (double *)ctx->b_partial.p;
+        STCHK(partial_buffer(ctx, 2 * maxb, &fo.partial));
         if (ms) launch_lc<T, true, true>(ctx, cfg, tab, fo, &nb, remap);
         else launch_lc<T, true, false>(ctx, cfg, tab, fo, &nb, remap);
     } else {

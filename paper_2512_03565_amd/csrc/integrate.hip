@@ -350,6 +350,9 @@ mdlj_status save_reference(mdlj_ctx *ctx)
 mdlj_status ensure_host_flag(mdlj_ctx *ctx)
 {
     if (ctx->h_flag) return MDLJ_OK;
+    if (ctx->no_alloc)
+        return set_err(ctx, MDLJ_ERR_NOMEM,
+                       "the allocation-free call would have to allocate pinned host words");
     // coherent: the kernel's store reaches host memory without a cache
     // write-back
     HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocCoherent));

@@ -229,6 +229,14 @@ struct mdlj_ctx {
     // do not keep them clear it)
     bool fx_valid = false;
     double fx_c[3] = {0, 0, 0}, fx_s = 0.0;
+    // allocation-free calls (mdlj_compute_forces_noalloc): no device buffer,
+    // pinned word or timing event may be created or grown (ensure() and the
+    // others refuse), and the energy/virial partials of the force kernels go
+    // to partial_ext (partial_ext_cap doubles, the library's static scratch
+    // array) instead of b_partial
+    bool no_alloc = false;
+    double *partial_ext = nullptr;
+    int64_t partial_ext_cap = 0;
     double t_force_us = 0, t_build_us = 0, t_fused_us = 0;
     int64_t t_nforce = 0, t_nbuild = 0, t_nfused = 0;
     double last_force_us = 0, last_build_us = 0;
@@ -238,6 +246,10 @@ struct mdlj_ctx {
 mdlj_status set_err(mdlj_ctx *ctx, mdlj_status st, const std::string &msg);
 mdlj_status hip_check(mdlj_ctx *ctx, hipError_t e, const char *what);
 mdlj_status ensure(mdlj_ctx *ctx, DevBuf &b, size_t bytes);
+// Buffer for nvals doubles of per-workgroup (U, W) partials: the context's
+// b_partial, or in an allocation-free call the static scratch array (an
+// error when nvals exceeds it).
+mdlj_status partial_buffer(mdlj_ctx *ctx, int64_t nvals, double **out);
 
 #define HIPCHK(ctx, call)                                      \
     do {                                                       \

@@ -424,8 +424,7 @@ mdlj_status vcl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, For
     int64_t nw;
     if (energy) {
         const int64_t maxw = ctx->n_ext + 64;
-        STCHK(ensure(ctx, ctx->b_partial, sizeof(double) * 2 * maxw));
-        fo.partial = (double *)ctx->b_partial.p;
+        STCHK(partial_buffer(ctx, 2 * maxw, &fo.partial));
         nw = ms ? launch_vcl<T, true, true>(ctx, cfg, tab, fo, remap)
                 : launch_vcl<T, true, false>(ctx, cfg, tab, fo, remap);
     } else {

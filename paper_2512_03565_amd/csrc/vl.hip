@@ -1237,8 +1237,7 @@ mdlj_status vl_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
     int64_t nw;
     if (energy) {
         const int64_t maxw = std::max<int64_t>(ctx->n + 64, ctx->grid.ncell_int);
-        STCHK(ensure(ctx, ctx->b_partial, sizeof(double) * 2 * maxw));
-        fo.partial = (double *)ctx->b_partial.p;
+        STCHK(partial_buffer(ctx, 2 * maxw, &fo.partial));
         nw = ms ? launch_vl_n3<T, true, true>(ctx, cfg, tab, fo, remap, nullptr)
                 : launch_vl_n3<T, true, false>(ctx, cfg, tab, fo, remap, nullptr);
     } else {

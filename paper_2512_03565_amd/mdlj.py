@@ -120,6 +120,7 @@ _SIGS = {
                            C.POINTER(C.c_int32)],
     "mdlj_get_timing": [_ctxp, _d, _d, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "mdlj_get_timing_fused": [_ctxp, _d, C.POINTER(C.c_int64)],
+    "mdlj_compute_forces_noalloc": [_ctxp, _vp, _vp, _vp, _d, _d],
     "mdlj_get_cells": [_ctxp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "mdlj_get_pairs": [_ctxp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                        C.POINTER(C.c_int64)],
@@ -297,6 +298,19 @@ class System:
         else:
             f = out
         return f, U.value, W.value
+
+    def forces_noalloc(self, out, energy=True):
+        """mdlj_compute_forces_noalloc into three device tensors; returns
+        (out, U, W)."""
+        ptrs = [_ptr(o) for o in out]
+        if any(k != MEM_DEVICE for _, k in ptrs):
+            raise ValueError("outputs must be device tensors")
+        U = C.c_double()
+        W = C.c_double()
+        check(lib.mdlj_compute_forces_noalloc(self.ctx, ptrs[0][0], ptrs[1][0], ptrs[2][0],
+                                              C.byref(U) if energy else None,
+                                              C.byref(W) if energy else None), self.ctx)
+        return out, U.value, W.value
 
     def neighbor_stats(self):
         """(stored list entries incl. row padding, bytes per entry, records)."""
