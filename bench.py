@@ -15,11 +15,13 @@ staged Verlet lists the force kernel itself takes the kicks, the drift and
 the displacement test between rebuilds; the roofline line then describes
 that kernel (its time from the events around those launches).
 
-Before the timed region the configuration is chosen three ways: fixed
-(linked cells, i-per-lane -- the one-order baseline), exhaustive full search
-and the learned tuner; each is then run for --steps steps.  The headline
-value is the exhaustive choice's throughput in useful pairs (r < rc,
-unordered) per second.
+Before the timed region the configuration is chosen four ways: fixed
+(linked cells, i-per-lane -- the one-order baseline), exhaustive full search,
+the learned tuner and the early-stopping search; each is then run for
+--steps steps.  A fifth mode runs the full search's choice in all-FP64
+arithmetic.  The tuners score configurations by the MD step itself.  The
+headline value is the exhaustive choice's throughput in useful pairs
+(r < rc, unordered) per second.
 
 Prints one JSON line.  --gpus > 1 is refused: the library runs on one GPU.
 """
@@ -48,11 +50,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--samples", type=int, default=10, help="tuning samples per configuration")
+    ap.add_argument("--samples", type=int, default=4,
+                    help="tuning samples (cycles of rebuild-interval MD steps) per configuration")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", default=None, help="run one mode only: fixed|exhaustive|learned")
+    ap.add_argument("--only", default=None,
+                    help="run one mode only: fixed|exhaustive|learned|early_stop|fp64")
     ap.add_argument("--config", default=None,
                     help="run this configuration (by name) without tuning, e.g. for profiling")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -141,9 +145,40 @@ def cpu_model():
     return None
 
 
+def physical_cores():
+    """Physical cores among the CPUs this process may run on (Linux), or None."""
+    try:
+        allowed = os.sched_getaffinity(0)
+        cores = set()
+        cpu = phys = core = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k == "processor":
+                    cpu = int(v)
+                elif k == "physical id":
+                    phys = int(v)
+                elif k == "core id":
+                    core = int(v)
+                elif not k and cpu is not None:
+                    if cpu in allowed:
+                        cores.add((phys, core))
+                    cpu = phys = core = None
+        if cpu is not None and cpu in allowed:
+            cores.add((phys, core))
+        return len(cores) or None
+    except (OSError, ValueError):
+        return None
+
+
+def oracle_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)) or 1))
+
+
 def cpu_baseline(scene, budget_s):
     import oracle
-    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    nthreads = oracle_threads()
     t_total = 0.0
     reps = 0
     while t_total < budget_s and reps < 20:
@@ -152,6 +187,31 @@ def cpu_baseline(scene, budget_s):
         t_total += time.perf_counter() - t0
         reps += 1
     return t_total / reps, reps, nthreads
+
+
+def other_oracle_timings(nth):
+    """The oracle on the 100k scene (full evaluation) and on a seeded
+    50,000-particle sample of the 4M two-species scene (forces on the sample
+    only), with the GPU-side pair counts they cover."""
+    import oracle
+    from paper_2512_03565_amd import scenes
+    out = {}
+    s = scenes.config2()
+    t0 = time.perf_counter()
+    oracle.forces(s["pos"], s["box"], s["rc"], nthreads=nth)
+    t = time.perf_counter() - t0
+    pi, _, _ = oracle.pairs_within(s["pos"], s["box"], s["rc"])
+    out["100k_fcc_rho0.75"] = {"ms_per_eval": 1e3 * t, "mpairs_per_s": len(pi) / t / 1e6,
+                               "threads": nth}
+    s = scenes.config4()
+    idx = np.sort(np.random.default_rng(20251205).choice(len(s["pos"]), 50_000, replace=False))
+    t0 = time.perf_counter()
+    oracle.forces_subset(s["pos"], s["box"], s["rc"], idx, s["eps"], s["sig"], s["types"],
+                         nthreads=nth)
+    t = time.perf_counter() - t0
+    out["4M_two_species_50k_sample"] = {"ms_per_eval": 1e3 * t,
+                                        "particles_per_s": len(idx) / t, "threads": nth}
+    return out
 
 
 def main():
@@ -175,12 +235,13 @@ def main():
                        precision=mdlj.PREC_F32PAIR_F64ACC, stream=stream)
     pairs = sysm.count_pairs()
     results = {}
-    modes = ["fixed", "exhaustive", "learned"]
+    modes = ["fixed", "exhaustive", "learned", "early_stop", "fp64"]
     if args.only:
         modes = [args.only]
     if args.config:
         modes = ["given"]
     for mode in modes:
+        sysm.set_precision(mdlj.PREC_F64 if mode == "fp64" else mdlj.PREC_F32PAIR_F64ACC)
         sysm.set_positions(pos_d)
         vel = [torch.tensor(np.ascontiguousarray(vel0[:, k]), device="cuda") for k in range(3)]
         t0 = time.perf_counter()
@@ -197,6 +258,12 @@ def main():
             cfg, tune_us = sysm.tune(mdlj.TUNE_EXHAUSTIVE, args.samples)
             table = sysm.tune_results()
             space = [mdlj.config_name(c) for c in sysm.configs()]
+        elif mode == "fp64":
+            cfg, tune_us = sysm.tune(mdlj.TUNE_EXHAUSTIVE, args.samples)
+        elif mode == "early_stop":
+            if os.path.exists(TUNER_WEIGHTS):
+                sysm.mlp_load(TUNER_WEIGHTS)
+            cfg, tune_us = sysm.tune(mdlj.TUNE_EARLY_STOP, args.samples)
         else:
             if os.path.exists(TUNER_WEIGHTS):
                 sysm.mlp_load(TUNER_WEIGHTS)
@@ -212,6 +279,10 @@ def main():
             r["list_stream_GBps"] = sb / (t_us * 1e-6) / 1e9
         r["tuned_step_us"] = tune_us
         r["tuning_s"] = tune_s
+        if mode in ("exhaustive", "early_stop", "fp64"):
+            r["tuning_samples"] = int(sysm.tune_taken().sum())
+        if mode == "fp64":
+            r["precision"] = "all FP64"
         results[mode] = r
         print(f"# {mode}: {r}", file=sys.stderr, flush=True)
     if args.copy_probe:
@@ -292,10 +363,14 @@ def main():
             "kind": "oracle",
             "sample": f"{reps} full force evaluations of the same 1M-particle scene "
                       f"(FP64 linked-cell oracle, {t_step:.2f} s each)",
+            "threads_used": nth,
+            "physical_cores_available": physical_cores(),
+            "logical_cpus_available": len(os.sched_getaffinity(0)),
+            "host_logical_cpus": os.cpu_count(),
             "one_core": {"value": pairs / t_one / 1e6, "unit": "Mpairs/s", "cores": 1,
                          "sample": f"1 full force evaluation ({t_one:.2f} s)"},
             "cpu_model": cpu_model(),
-            "host_cpus": os.cpu_count(),
+            "other_scenes": other_oracle_timings(nth),
         }
     sysm.close()
     print(json.dumps(line), flush=True)

@@ -76,8 +76,10 @@ enum { MDLJ_ORD_I_PER_LANE = 0, MDLJ_ORD_CLUSTER_TILE = 1, MDLJ_ORD_WAVE_PER_I =
 /* Arithmetic: FP32 pair arithmetic with FP64 accumulation, or all FP64. */
 enum { MDLJ_PREC_F32PAIR_F64ACC = 0, MDLJ_PREC_F64 = 1 };
 
-/* Tuning strategy (section 2.3.2 full search; section 6 data-driven). */
-enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2 };
+/* Tuning strategy (section 2.3.2 full search; section 6 data-driven and
+ * cheaper searches). */
+enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2,
+       MDLJ_TUNE_EARLY_STOP = 3 };
 
 /*
  * One point of the search space.  Meaning of tile_i / tile_j per order:
@@ -275,22 +277,37 @@ mdlj_status mdlj_get_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj,
                            int64_t *count);
 
 /*
- * Choose a configuration.  FIXED keeps the current one; EXHAUSTIVE times
- * every valid configuration `samples` times (first sample dropped as
- * warm-up, the rest averaged; the lower index wins ties) on the amortised
- * step time force + rebuild / rebuild_every; LEARNED asks the network and
- * falls back to EXHAUSTIVE when its confidence is below the threshold set
- * by mdlj_mlp_set_threshold (default 0.6) or no network is loaded.  The
- * chosen configuration is made current; *chosen and *step_us (measured
- * amortised microseconds of the chosen one, may be NULL) are written.
+ * Choose a configuration by the cost of one MD step as mdlj_step_vv runs it
+ * (force kernel, integrator step, list upkeep, and a rebuild every
+ * rebuild_every steps or re-binning every step), measured on the current
+ * positions with HIP events: one sample is a cycle of rebuild_every (at most
+ * 50) velocity-Verlet steps with time step 0 from zero velocities, so the
+ * positions keep their values bit for bit while every kernel does its usual
+ * work; the first cycle (which also builds the structure) is a warm-up.
+ * FIXED keeps the current configuration; EXHAUSTIVE (section 2.3.2's full
+ * search) times every valid configuration `samples` cycles, drops the
+ * first and averages the rest, the lower index winning ties; LEARNED asks
+ * the network and falls back to EXHAUSTIVE when its confidence is below the
+ * threshold set by mdlj_mlp_set_threshold (default 0.6) or no network is
+ * loaded; EARLY_STOP is the full search with early stopping (the decision
+ * rule of mdlj_tune_select_early with warm_factor +inf, i.e. the warm-up
+ * cycle is not judged, and margin 0.1), the
+ * configurations visited by descending network probability when a network
+ * for this search space is loaded, else in config_at order.  The chosen
+ * configuration is made current; *chosen and *step_us (microseconds per MD
+ * step of the chosen one, may be NULL) are written.  The context's kernel
+ * timing (mdlj_set_timing) does not count the tuning steps.
  */
 mdlj_status mdlj_tune(mdlj_ctx *ctx, int32_t mode, int32_t samples, mdlj_config *chosen,
                       double *step_us);
 
-/* Per-configuration results of the last EXHAUSTIVE tuning: up to cap
- * entries of amortised microseconds in config_at order; *count = number of
- * configurations. */
+/* Per-configuration results of the last EXHAUSTIVE or EARLY_STOP search:
+ * up to cap entries of microseconds per step in config_at order (+inf where
+ * a configuration cannot run; for a configuration EARLY_STOP dropped, its
+ * last sample); *count = number of configurations.  mdlj_tune_taken: the
+ * samples each configuration used. */
 mdlj_status mdlj_tune_results(const mdlj_ctx *ctx, double *us, int32_t cap, int32_t *count);
+mdlj_status mdlj_tune_taken(const mdlj_ctx *ctx, int32_t *taken, int32_t cap, int32_t *count);
 
 /*
  * Decision rules of the tuner, as pure host functions (no context, no
@@ -308,6 +325,22 @@ mdlj_status mdlj_tune_results(const mdlj_ctx *ctx, double *us, int32_t cap, int3
  */
 mdlj_status mdlj_tune_select(const double *samples, int32_t k, int32_t s, int32_t mode,
                              double *values, int32_t *chosen);
+/*
+ * The early-stopping search as a pure host function over a table of
+ * samples [k][s] (row-major, microseconds; sample 0 is the warm-up cycle;
+ * +inf or NaN where a configuration cannot run), visiting configurations
+ * in `order` (a permutation of 0..k-1, or NULL for index order).  Once a
+ * configuration has been fully measured, a later one is dropped when its
+ * warm-up sample exceeds warm_factor (>= 1, +inf allowed) times the best mean so far or
+ * its first timed sample exceeds (1 + margin) times it (margin >= 0).
+ * values[q] = mean of samples 1..s-1 of a fully measured configuration (all
+ * s when s == 1), else its last sample taken (+inf if it cannot run);
+ * taken[q] = samples used; *chosen = the smallest fully measured mean,
+ * lower index on ties, or -1.
+ */
+mdlj_status mdlj_tune_select_early(const double *samples, int32_t k, int32_t s,
+                                   const int32_t *order, double warm_factor, double margin,
+                                   double *values, int32_t *taken, int32_t *chosen);
 mdlj_status mdlj_retune_needed(const float *before8, const float *now8, double threshold,
                                int32_t *needed);
 

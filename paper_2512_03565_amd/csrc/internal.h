@@ -174,13 +174,14 @@ struct mdlj_ctx {
     DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
         b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart, b_vsort,
-        b_vsort2, b_xrsort, b_tinv, b_sorted2, b_fxrec, b_fxrec2, b_fxspec;
+        b_vsort2, b_xrsort, b_tinv, b_sorted2, b_fxrec, b_fxrec2, b_fxspec, b_tunev;
     int64_t nhalo = 0;            // entries of b_halo
     int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 
     // tuner state
     std::vector<mdlj_config> space;
     std::vector<double> tune_us;
+    std::vector<int> tune_taken;  // samples each configuration used in the last search
     // learned tuner
     std::vector<float> mlp_w, mlp_m, mlp_v;
     float mlp_mean[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -339,6 +340,10 @@ bool needs_fold(const mdlj_config &c);
 mdlj_status tune_exhaustive(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *best_us);
 mdlj_status tune_measure_current(mdlj_ctx *ctx, int samples, double *us);
 mdlj_status tune_learned(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *us);
+mdlj_status tune_early(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *us);
+// Configuration indices by descending network probability for the current
+// scene; empty when no network for this search space is loaded.
+mdlj_status mlp_rank(mdlj_ctx *ctx, std::vector<int> &order);
 
 // --- force kernels ----------------------------------------------------------
 mdlj_status lc_forces(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, ForceOut &fo,

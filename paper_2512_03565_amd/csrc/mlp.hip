@@ -317,6 +317,22 @@ mdlj_status features_dev(mdlj_ctx *ctx, float *f8)
     return MDLJ_OK;
 }
 
+mdlj_status mlp_rank(mdlj_ctx *ctx, std::vector<int> &order)
+{
+    order.clear();
+    if (!ctx->mlp_loaded || ctx->mlp_k != (int)ctx->space.size()) return MDLJ_OK;
+    float f[DIN];
+    STCHK(features_dev(ctx, f));
+    std::vector<float> xn;
+    normalise(ctx, f, 1, xn);
+    std::vector<float> p(ctx->mlp_k);
+    STCHK(forward_host(ctx, xn.data(), 1, p.data()));
+    order.resize(ctx->mlp_k);
+    for (int k = 0; k < ctx->mlp_k; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p[a] > p[b]; });
+    return MDLJ_OK;
+}
+
 mdlj_status tune_learned(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *us)
 {
     if (!ctx->mlp_loaded || ctx->mlp_k != (int)ctx->space.size())

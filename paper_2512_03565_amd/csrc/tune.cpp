@@ -2,20 +2,28 @@
 // search, extended by the interaction order as in section 4).
 //
 // Full search: every valid configuration of the search space is run for
-// `samples` force evaluations on the current positions; the samples are
-// reduced to one value (the mean, first sample dropped as warm-up) and the
-// configuration with the smallest value is kept (lower index on ties).  The
-// value is the amortised cost of one MD step with that configuration:
-//   linked cells:  re-binning + force kernel          (every step)
-//   lists:         force kernel + (R-1)/R * upkeep + rebuild / R
-// where R is the rebuild interval and upkeep the per-step displacement
-// check and record refresh.  Times come from HIP events on the context's
-// stream.
+// `samples` cycles of R velocity-Verlet steps on the current positions (R
+// the rebuild interval); the samples are reduced to one value (the mean,
+// the first cycle dropped as warm-up) and the configuration with the
+// smallest value is kept (lower index on ties).  The value is the cost of
+// one MD step as the integrator runs it with that configuration: re-binning
+// (linked cells) or list upkeep and a rebuild every R steps (lists), the
+// force kernel and the integrator step.  The steps use a time step of 0, so
+// the caller's positions do not move.  Times come from HIP events on the
+// context's stream.
+//
+// Early-stopping search (a cheaper alternative; the paper names full
+// search as wasteful, section 2.3.2, and cheaper strategies as future work,
+// section 6): the same samples, but a configuration is dropped after its
+// warm-up cycle or its first timed cycle when those are well above the best
+// value so far, and the configurations are visited most promising first.
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
 #include <limits>
+#include <memory>
+#include <vector>
 
 #include "internal.h"
 
@@ -66,60 +74,147 @@ mdlj_status elapsed_us(mdlj_ctx *ctx, Events &ev, double *us)
     return MDLJ_OK;
 }
 
-// Amortised microseconds per step of configuration c (positions fixed).
+// The MD step of configuration c as the velocity-Verlet loop runs it: the
+// force kernel, the integrator step (fused into the staged Verlet-list
+// kernel, or a kernel of its own), the list upkeep between rebuilds and a
+// rebuild every R steps, with the host waits of the loop.  The steps take a
+// time step of 0 from zero velocities: positions and velocities keep their
+// values bit for bit (x + 0 v = x) while every kernel does its usual work.
+// One sample is one cycle of R steps (capped at 50), timed with events
+// around one step call; sample 0 also builds the structure.
+struct Cycles {
+    mdlj_ctx *ctx;
+    const mdlj_config &c;
+    Events ev;
+    int R;
+    double *v;
+    mdlj_status start()
+    {
+        HIPCHK(ctx, hipEventCreate(&ev.a));
+        HIPCHK(ctx, hipEventCreate(&ev.b));
+        const int64_t n = ctx->n;
+        STCHK(ensure(ctx, ctx->b_tunev, sizeof(double) * 3 * n));
+        v = (double *)ctx->b_tunev.p;
+        HIPCHK(ctx, hipMemsetAsync(v, 0, sizeof(double) * 3 * n, ctx->stream));
+        ctx->cfg = c;
+        ctx->built = false;
+        ctx->forces_valid = false;
+        R = std::max(1, std::min(ctx->rebuild_every, 50));
+        return MDLJ_OK;
+    }
+    // microseconds per step of one more cycle
+    mdlj_status sample(double *us)
+    {
+        const int64_t n = ctx->n;
+        HIPCHK(ctx, hipEventRecord(ev.a, ctx->stream));
+        STCHK(vv_steps(ctx, v, v + n, v + 2 * n, 0.0, R));
+        HIPCHK(ctx, hipEventRecord(ev.b, ctx->stream));
+        double t = 0;
+        STCHK(elapsed_us(ctx, ev, &t));
+        *us = t / R;
+        return MDLJ_OK;
+    }
+};
+
+// Runs `measure_body` with the context's own kernel timing switched off
+// (tuning steps are not the caller's) and restores it.
+template <typename F>
+mdlj_status untimed(mdlj_ctx *ctx, F &&body)
+{
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    const mdlj_status st = body();
+    ctx->timing = timing;
+    return st;
+}
+
+// Mean microseconds per MD step of configuration c over samples - 1 cycles
+// after the warm-up cycle (all of one cycle when samples == 1).
 mdlj_status measure(mdlj_ctx *ctx, const mdlj_config &c, int samples, double *out)
 {
-    Events ev;
-    HIPCHK(ctx, hipEventCreate(&ev.a));
-    HIPCHK(ctx, hipEventCreate(&ev.b));
-    ctx->cfg = c;
-    ctx->built = false;
-    bool rebuilt = false;
-    double build_us = 0, upkeep_us = 0;
-    HIPCHK(ctx, hipEventRecord(ev.a, ctx->stream));
-    STCHK(prepare(ctx, c, true, &rebuilt));
-    HIPCHK(ctx, hipEventRecord(ev.b, ctx->stream));
-    STCHK(elapsed_us(ctx, ev, &build_us));
-    if (c.nbr_algo != MDLJ_NBR_LC) {
-        // per-step upkeep between rebuilds: displacement check + refresh
-        HIPCHK(ctx, hipEventRecord(ev.a, ctx->stream));
-        bool far = false;
-        STCHK(moved_too_far(ctx, &far));
-        STCHK(refresh_records(ctx));
-        HIPCHK(ctx, hipEventRecord(ev.b, ctx->stream));
-        STCHK(elapsed_us(ctx, ev, &upkeep_us));
-    }
-    std::vector<double> t(samples);
-    for (int s = 0; s < samples; ++s) {
-        ForceOut fo;
-        int64_t nb = 0;
-        HIPCHK(ctx, hipEventRecord(ev.a, ctx->stream));
-        STCHK(run_force_kernel(ctx, c, false, fo, &nb));
-        if (needs_fold(c)) STCHK(fold_forces(ctx, fo));
-        STCHK(unpermute_forces(ctx, fo, ctx->fx, ctx->fy, ctx->fz));
-        HIPCHK(ctx, hipEventRecord(ev.b, ctx->stream));
-        STCHK(elapsed_us(ctx, ev, &t[s]));
-    }
-    double force_us = 0;
-    select_config(t.data(), 1, samples, 0, &force_us);
-    if (c.nbr_algo == MDLJ_NBR_LC) {
-        *out = force_us + build_us;
-    } else {
-        const double R = ctx->rebuild_every;
-        *out = force_us + upkeep_us * (R - 1.0) / R + build_us / R;
-    }
-    ctx->forces_valid = true;
-    ctx->steps_since_build = 1;
-    return MDLJ_OK;
+    return untimed(ctx, [&]() -> mdlj_status {
+        Cycles cy{ctx, c, {}, 1, nullptr};
+        STCHK(cy.start());
+        std::vector<double> t(samples);
+        for (int s = 0; s < samples; ++s) STCHK(cy.sample(&t[s]));
+        select_config(t.data(), 1, samples, 0, out);
+        return MDLJ_OK;
+    });
 }
 
 }  // namespace
+
+// Early-stopping decision of the cheaper search: after sample j of a
+// configuration (j = 0 is the warm-up cycle, which also builds the
+// structure), whether its next sample is taken, given the best fully
+// measured value so far: a configuration whose warm-up cycle is slower than
+// warm_factor times the best, or whose first timed cycle is slower than
+// (1 + margin) times the best, is dropped.
+static bool take_next(int j, double sample, double best, double warm_factor, double margin)
+{
+    if (!(best < std::numeric_limits<double>::infinity())) return true;
+    if (j == 0) return sample <= warm_factor * best;
+    if (j == 1) return sample <= (1.0 + margin) * best;
+    return true;
+}
+
+// The early-stopping search over K configurations visited in `order` (all
+// in index order when null), S samples each at most.  fetch(k, j, &x)
+// returns sample j of configuration k (called with j = 0, 1, ... in turn;
+// x = +inf when the configuration cannot run).  values[k] = the mean of
+// samples 1..S-1 of a fully measured configuration (all S when S == 1), the
+// last sample of a dropped one (+inf if it cannot run); taken[k] = samples
+// used.  Returns the index of the smallest fully measured value (the lower
+// index on ties), or -1.
+template <typename Fetch>
+static mdlj_status search_early(int K, int S, const int *order, double warm_factor,
+                                double margin, Fetch &&fetch, double *values, int *taken,
+                                int *chosen)
+{
+    const double inf = std::numeric_limits<double>::infinity();
+    int best = -1;
+    for (int k = 0; k < K; ++k) {
+        values[k] = inf;
+        taken[k] = 0;
+    }
+    std::vector<double> row(S);
+    for (int q = 0; q < K; ++q) {
+        const int k = order ? order[q] : q;
+        const double bv = best >= 0 ? values[best] : inf;
+        bool full = true;
+        int j = 0;
+        while (j < S) {
+            double x = inf;
+            STCHK(fetch(k, j, &x));
+            row[j] = x;
+            ++j;
+            if (!(x < inf)) {
+                full = false;
+                break;
+            }
+            if (j < S && !take_next(j - 1, x, bv, warm_factor, margin)) {
+                full = false;
+                values[k] = x;
+                break;
+            }
+        }
+        taken[k] = j;
+        if (!full) continue;
+        double v = 0;
+        select_config(row.data(), 1, S, 0, &v);
+        values[k] = v;
+        if (best < 0 || v < values[best] || (v == values[best] && k < best)) best = k;
+    }
+    *chosen = best;
+    return MDLJ_OK;
+}
 
 mdlj_status tune_exhaustive(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *best_us)
 {
     const mdlj_config saved = ctx->cfg;
     const size_t K = ctx->space.size();
     ctx->tune_us.assign(K, std::numeric_limits<double>::infinity());
+    ctx->tune_taken.assign(K, 0);
     size_t best = K;
     for (size_t k = 0; k < K; ++k) {
         double us = 0;
@@ -131,6 +226,7 @@ mdlj_status tune_exhaustive(mdlj_ctx *ctx, int samples, mdlj_config *chosen, dou
             return st;
         }
         ctx->tune_us[k] = us;
+        ctx->tune_taken[k] = samples;
         if (best == K || us < ctx->tune_us[best]) best = k;
     }
     ctx->built = false;
@@ -143,6 +239,69 @@ mdlj_status tune_exhaustive(mdlj_ctx *ctx, int samples, mdlj_config *chosen, dou
     ctx->err.clear();
     *chosen = ctx->cfg;
     *best_us = ctx->tune_us[best];
+    return MDLJ_OK;
+}
+
+// Early-stopping constants of the live search: a configuration is dropped
+// when its first timed cycle is more than 10% above the best step time so
+// far.  Its warm-up cycle is not judged: besides the structure build it
+// carries one-time costs (device buffers allocated the first time a
+// structure of that kind is built) that outweigh the steps of small scenes.
+constexpr double EARLY_WARM = std::numeric_limits<double>::infinity();
+constexpr double EARLY_MARGIN = 0.10;
+
+mdlj_status tune_early(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *best_us)
+{
+    const mdlj_config saved = ctx->cfg;
+    const int K = (int)ctx->space.size();
+    // most promising first: the network's ranking when one for this search
+    // space is loaded, else the search-space order
+    std::vector<int> order;
+    STCHK(mlp_rank(ctx, order));
+    if ((int)order.size() != K) {
+        order.resize(K);
+        for (int k = 0; k < K; ++k) order[k] = k;
+    }
+    std::vector<double> values(K);
+    std::vector<int> taken(K);
+    std::unique_ptr<Cycles> cur;
+    const double inf = std::numeric_limits<double>::infinity();
+    auto fetch = [&](int k, int j, double *x) -> mdlj_status {
+        return untimed(ctx, [&]() -> mdlj_status {
+            mdlj_status st = MDLJ_OK;
+            if (j == 0) {
+                cur.reset(new Cycles{ctx, ctx->space[k], {}, 1, nullptr});
+                st = cur->start();
+            }
+            if (st == MDLJ_OK) st = cur->sample(x);
+            if (st == MDLJ_ERR_GEOMETRY || st == MDLJ_ERR_ARG) {  // not valid for this box
+                *x = inf;
+                ctx->err.clear();
+                return MDLJ_OK;
+            }
+            return st;
+        });
+    };
+    int best = -1;
+    const mdlj_status st = search_early(K, samples, order.data(), EARLY_WARM, EARLY_MARGIN, fetch,
+                                        values.data(), taken.data(), &best);
+    cur.reset();
+    ctx->built = false;
+    if (st != MDLJ_OK) {
+        ctx->cfg = saved;
+        return st;
+    }
+    ctx->tune_us = values;
+    ctx->tune_taken = taken;
+    if (best < 0) {
+        ctx->cfg = saved;
+        return set_err(ctx, MDLJ_ERR_GEOMETRY, "no configuration is valid for this system");
+    }
+    ctx->cfg = ctx->space[best];
+    ctx->forces_valid = false;
+    ctx->err.clear();
+    *chosen = ctx->cfg;
+    *best_us = values[best];
     return MDLJ_OK;
 }
 
@@ -173,6 +332,9 @@ mdlj_status mdlj_tune(mdlj_ctx *ctx, int32_t mode, int32_t samples, mdlj_config 
     case MDLJ_TUNE_LEARNED:
         STCHK(tune_learned(ctx, samples, &c, &us));
         break;
+    case MDLJ_TUNE_EARLY_STOP:
+        STCHK(tune_early(ctx, samples, &c, &us));
+        break;
     default:
         return set_err(ctx, MDLJ_ERR_ARG, "unknown tuning mode");
     }
@@ -187,6 +349,41 @@ mdlj_status mdlj_tune_select(const double *samples, int32_t k, int32_t s, int32_
     if (!samples || !values || !chosen || k < 1 || s < 1 || (mode != 0 && mode != 1))
         return MDLJ_ERR_ARG;
     *chosen = select_config(samples, k, s, mode, values);
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_tune_select_early(const double *samples, int32_t k, int32_t s,
+                                   const int32_t *order, double warm_factor, double margin,
+                                   double *values, int32_t *taken, int32_t *chosen)
+{
+    if (!samples || !values || !taken || !chosen || k < 1 || s < 1 || !(warm_factor >= 1.0) ||
+        !(margin >= 0.0) || warm_factor != warm_factor)
+        return MDLJ_ERR_ARG;
+    if (order) {
+        std::vector<char> seen(k, 0);
+        for (int32_t q = 0; q < k; ++q) {
+            if (order[q] < 0 || order[q] >= k || seen[order[q]]) return MDLJ_ERR_ARG;
+            seen[order[q]] = 1;
+        }
+    }
+    auto fetch = [&](int kk, int j, double *x) -> mdlj_status {
+        *x = samples[(size_t)kk * s + j];
+        if (!(*x == *x)) *x = std::numeric_limits<double>::infinity();
+        return MDLJ_OK;
+    };
+    std::vector<int> tk(k);
+    int best = -1;
+    STCHK(search_early(k, s, order, warm_factor, margin, fetch, values, tk.data(), &best));
+    for (int32_t q = 0; q < k; ++q) taken[q] = tk[q];
+    *chosen = best;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_tune_taken(const mdlj_ctx *ctx, int32_t *taken, int32_t cap, int32_t *count)
+{
+    if (!ctx || !count || (cap > 0 && !taken)) return MDLJ_ERR_ARG;
+    *count = (int32_t)ctx->tune_taken.size();
+    for (int32_t k = 0; k < cap && k < *count; ++k) taken[k] = ctx->tune_taken[k];
     return MDLJ_OK;
 }
 

@@ -24,7 +24,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 NBR_LC, NBR_VL, NBR_VCL = 0, 1, 2
 ORD_I_PER_LANE, ORD_CLUSTER_TILE, ORD_WAVE_PER_I = 0, 1, 2
 PREC_F32PAIR_F64ACC, PREC_F64 = 0, 1
-TUNE_FIXED, TUNE_EXHAUSTIVE, TUNE_LEARNED = 0, 1, 2
+TUNE_FIXED, TUNE_EXHAUSTIVE, TUNE_LEARNED, TUNE_EARLY_STOP = 0, 1, 2, 3
 NBR_NAMES = {0: "LC", 1: "VL", 2: "VCL"}
 ORD_NAMES = {0: "i-per-lane", 1: "cluster-tile", 2: "wave-per-i"}
 
@@ -97,6 +97,9 @@ _SIGS = {
                             C.POINTER(C.c_int64)],
     "mdlj_tune": [_ctxp, C.c_int32, C.c_int32, C.POINTER(mdlj_config), _d],
     "mdlj_tune_results": [_ctxp, _d, C.c_int32, C.POINTER(C.c_int32)],
+    "mdlj_tune_taken": [_ctxp, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)],
+    "mdlj_tune_select_early": [_d, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_double,
+                               C.c_double, _d, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "mdlj_step_vv": [_ctxp, _vp, _vp, _vp, C.c_double, C.c_int32],
     "mdlj_set_mass": [_ctxp, C.c_int32, C.c_double],
     "mdlj_features": [_ctxp, C.POINTER(C.c_float)],
@@ -358,6 +361,12 @@ class System:
         check(lib.mdlj_tune_results(self.ctx, buf, 256, C.byref(n)), self.ctx)
         return np.array(buf[: n.value])
 
+    def tune_taken(self):
+        n = C.c_int32()
+        buf = (C.c_int32 * 256)()
+        check(lib.mdlj_tune_taken(self.ctx, buf, 256, C.byref(n)), self.ctx)
+        return np.array(buf[: n.value])
+
     def step_vv(self, vel_cols, dt, nsteps):
         ptrs = [_ptr(v) for v in vel_cols]
         if any(k != MEM_DEVICE for _, k in ptrs):
@@ -461,6 +470,23 @@ def tune_select(samples, mode=0):
     check(lib.mdlj_tune_select(a.ctypes.data_as(_d), a.shape[0], a.shape[1], int(mode),
                                vals.ctypes.data_as(_d), C.byref(ch)))
     return vals, ch.value
+
+
+def tune_select_early(samples, order=None, warm_factor=2.0, margin=0.1):
+    """The early-stopping search over a [K, S] table (sample 0 = warm-up):
+    (values, samples taken, chosen index)."""
+    a = np.ascontiguousarray(np.atleast_2d(samples), np.float64)
+    k, s = a.shape
+    vals = np.empty(k)
+    taken = np.empty(k, np.int32)
+    ch = C.c_int32()
+    i32 = C.POINTER(C.c_int32)
+    o = None if order is None else np.ascontiguousarray(order, np.int32)
+    check(lib.mdlj_tune_select_early(a.ctypes.data_as(_d), k, s,
+                                     None if o is None else o.ctypes.data_as(i32),
+                                     float(warm_factor), float(margin), vals.ctypes.data_as(_d),
+                                     taken.ctypes.data_as(i32), C.byref(ch)))
+    return vals, taken, ch.value
 
 
 def retune_needed(before, now, threshold=0.1):

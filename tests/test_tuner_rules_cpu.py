@@ -63,3 +63,65 @@ def test_retune_trigger(m):
     f3 = f0.copy()
     f3[0] += 1
     assert not m.retune_needed(f0, f3, 0.1)
+
+
+# ------------------------------------------------------- early-stopping search
+
+def _table():
+    # [K, S]: sample 0 = warm-up cycle, samples 1..3 timed cycles
+    return np.array([[20.0, 10.0, 10.0, 10.0],   # the best
+                     [18.0, 25.0, 25.0, 25.0],   # warm-up within 2x, first cycle far off
+                     [90.0, 50.0, 50.0, 50.0],   # warm-up beyond 2x the best
+                     [19.0, 10.5, 10.4, 10.6],   # close to the best: measured in full
+                     [np.inf, np.inf, np.inf, np.inf]])  # cannot run
+
+
+def test_early_stop_best_first_drops_the_rest(m):
+    vals, taken, k = m.tune_select_early(_table())
+    assert k == 0
+    # 0 and 3 measured in full, 1 dropped after its first timed cycle, 2 after
+    # its warm-up, 4 after its (infinite) first sample
+    assert list(taken) == [4, 2, 1, 4, 1]
+    assert vals[0] == pytest.approx(10.0) and vals[3] == pytest.approx(10.5)
+    assert vals[1] == 25.0 and vals[2] == 90.0 and np.isinf(vals[4])
+
+
+def test_early_stop_equals_full_search_when_nothing_is_dropped(m):
+    t = _table()
+    full_vals, full_k = m.tune_select(t, mode=0)
+    # a generous margin keeps every runnable configuration
+    vals, taken, k = m.tune_select_early(t, warm_factor=1e9, margin=1e9)
+    assert k == full_k
+    assert np.allclose(vals[:4], full_vals[:4])
+    assert list(taken[:4]) == [4, 4, 4, 4]
+
+
+def test_early_stop_order_changes_cost_not_choice(m):
+    t = _table()
+    # the best visited last: everything before it is measured in full
+    vals, taken, k = m.tune_select_early(t, order=[2, 1, 3, 4, 0])
+    assert k == 0
+    assert taken[2] == 4 and taken[1] == 4 and taken[3] == 4
+    # the best visited first: fewer samples in total
+    _, taken_first, k_first = m.tune_select_early(t, order=[0, 3, 1, 2, 4])
+    assert k_first == 0 and taken_first.sum() < taken.sum()
+
+
+def test_early_stop_can_miss_a_configuration_with_a_slow_warmup(m):
+    # a configuration whose warm-up cycle (which includes the structure
+    # build) is slow but whose steps are fastest is dropped once a good one
+    # has been measured: the price of stopping early
+    t = np.array([[20.0, 10.0, 10.0, 10.0],
+                  [45.0, 8.0, 8.0, 8.0]])
+    assert m.tune_select(t)[1] == 1
+    vals, taken, k = m.tune_select_early(t)
+    assert k == 0 and list(taken) == [4, 1]
+
+
+def test_early_stop_ties_and_bad_arguments(m):
+    t = np.array([[5.0, 3.0, 3.0], [5.0, 3.0, 3.0]])
+    assert m.tune_select_early(t, order=[1, 0])[2] == 0
+    with pytest.raises(m.MdljError):
+        m.tune_select_early(t, order=[0, 0])
+    with pytest.raises(m.MdljError):
+        m.tune_select_early(t, warm_factor=0.5)
