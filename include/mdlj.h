@@ -111,6 +111,16 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2,
  * step would exceed 1e-7 of the smallest sigma (beyond about 310 sigma)
  * for the FP32-pair staged ones.  staged = 0 reads
  * every j-particle from global memory.
+ * Linked cells with newton3 = 1 (staged = 1): a wavefront per cell pairs
+ * its own particles with those of its 13 forward neighbour cells (a half
+ * shell) and with each other, every pair once; both forces are added in LDS
+ * and flushed with one atomic per staged record.  swap chooses which side
+ * of those cell pairs is the i-list (the traversal's choice, section 5):
+ * swap = 0, the cell's own particles (WAVE_PER_I 1x64, CLUSTER_TILE 4x16 or
+ * 16x4: tile_i i's per step, tile_j lanes each over its partners); swap =
+ * 1, the partners (I_PER_LANE, tile_i = 1: each lane one partner, the own
+ * particles broadcast to all lanes).  swap is 0 for every other
+ * configuration.
  */
 typedef struct {
     int32_t nbr_algo;
@@ -120,6 +130,7 @@ typedef struct {
     int32_t cluster_size;
     int32_t newton3;
     int32_t staged;
+    int32_t swap;
 } mdlj_config;
 
 /*

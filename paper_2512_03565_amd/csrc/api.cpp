@@ -110,7 +110,7 @@ static bool cfg_eq(const mdlj_config &a, const mdlj_config &b)
 {
     return a.nbr_algo == b.nbr_algo && a.order == b.order && a.tile_i == b.tile_i &&
            a.tile_j == b.tile_j && a.cluster_size == b.cluster_size && a.newton3 == b.newton3 &&
-           a.staged == b.staged;
+           a.staged == b.staged && a.swap == b.swap;
 }
 
 // The search space: neighbour algorithm x interaction order x tile shape x
@@ -127,6 +127,11 @@ static std::vector<mdlj_config> build_space()
         for (int g : {1, 2, 4})
             v.push_back({MDLJ_NBR_LC, MDLJ_ORD_WAVE_PER_I, g, 64 / g, 0, 0, st});
     }
+    // linked cells, Newton 3 over a half shell of neighbour cells: the own
+    // particles as the i-list (three lane grids) or the partners (swap)
+    v.push_back({MDLJ_NBR_LC, MDLJ_ORD_WAVE_PER_I, 1, 64, 0, 1, 1, 0});
+    for (int ai : {4, 16}) v.push_back({MDLJ_NBR_LC, MDLJ_ORD_CLUSTER_TILE, ai, 64 / ai, 0, 1, 1, 0});
+    v.push_back({MDLJ_NBR_LC, MDLJ_ORD_I_PER_LANE, 1, 1, 0, 1, 1, 1});
     // Verlet lists
     for (int n3 : {0, 1}) {
         v.push_back({MDLJ_NBR_VL, MDLJ_ORD_I_PER_LANE, 0, 0, 0, n3, 0});

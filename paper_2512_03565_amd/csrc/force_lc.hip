@@ -197,6 +197,176 @@ __global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
     if (E) wave_partial(bu, bw, 0.5, fo.partial, blockIdx.x);
 }
 
+// Newton 3 over linked cells (section 2.1's F_ji = -F_ij; section 4.1.3):
+// a cell pairs its own particles with those of its 13 forward neighbour
+// cells -- the half of the 26 with dz = +1, or dz = 0 and dy = +1, or
+// dz = dy = 0 and dx = +1 -- and with each other, so that every pair inside
+// the cutoff is computed once.  One wavefront per cell stages its own
+// records followed by those of the forward cells in LDS (five runs of sorted
+// records: the own cell with its right neighbour, the row dy = +1, dz = 0,
+// and the three rows dz = +1), with an FP64 force accumulator per staged
+// record.  The pairs are (a, b) with a an own record and b > a any staged
+// one.  Both forces of a pair are added in LDS; at the end every staged
+// record adds its force to the sorted force array with one atomic per
+// component (forces on halo images are folded onto their particles
+// afterwards).
+// Two assignments of the cell pair's roles (the traversal's choice of
+// which cell provides the i-list):
+//   SWAP = false  the own particles are the i's: AI of them per step, AJ
+//                 lanes per i striding over its partners b; F_i is summed
+//                 over the AJ lanes, F_b added to LDS per lane.
+//   SWAP = true   the partners are the i's: a lane takes one b and walks
+//                 the own particles a < b as j, read from LDS by every lane
+//                 at once (a broadcast); F_b stays in the lane, F_a is summed
+//                 over the wavefront and added by one lane.
+constexpr int HALF_RUNS = 5;
+
+template <typename T, bool E, bool MS, int AI, bool SWAP>
+__global__ __launch_bounds__(64) void k_lc_half(const PosT *__restrict__ rec,
+                                                const int32_t *__restrict__ start, Grid g,
+                                                LJTable<T> tab, ForceOut fo, int remap, int cmax)
+{
+    extern __shared__ double stage[];
+    constexpr int AJ = MDLJ_WAVE / AI;
+    __shared__ int seg_b[HALF_RUNS];
+    __shared__ int seg_c[HALF_RUNS + 1];
+    __shared__ LdsTable<T> lt;
+    const double rc2 = tab.rc2d;
+    const int lane = threadIdx.x;
+    if (MS) lds_table_load(lt, tab, lane, MDLJ_WAVE);
+    const int64_t nb = gridDim.x;
+    const int64_t c = remap ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
+    const int cx = (int)((uint32_t)c % (uint32_t)g.n[0]);
+    const int cy = (int)(((uint32_t)c / (uint32_t)g.n[0]) % (uint32_t)g.n[1]);
+    const int cz = (int)((uint32_t)c / ((uint32_t)g.n[0] * (uint32_t)g.n[1]));
+    const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
+                       cx + g.h[0];
+    if (lane < HALF_RUNS) {
+        // run 0: the own cell and its right neighbour; run 1: row dy = +1,
+        // dz = 0; runs 2..4: rows dz = +1, dy = -1, 0, +1 (cells cx-1..cx+1)
+        int64_t b, e;
+        if (lane == 0) {
+            b = ei;
+            e = ei + 2;
+        } else {
+            const int dy = lane == 1 ? 1 : lane - 3, dz = lane == 1 ? 0 : 1;
+            b = ei + dy * g.stride[1] + dz * g.stride[2] - 1;
+            e = b + 3;
+        }
+        seg_b[lane] = start[b];
+        seg_c[lane + 1] = start[e] - start[b];
+    }
+    __syncthreads();
+    if (lane == 0) {
+        seg_c[0] = 0;
+        for (int r = 0; r < HALF_RUNS; ++r) seg_c[r + 1] += seg_c[r];
+    }
+    __syncthreads();
+    const int C = seg_c[HALF_RUNS];
+    const int nown = start[ei + 1] - start[ei];
+    double *sx = stage, *sy = stage + cmax, *sz = stage + 2 * cmax;
+    double *sfx = stage + 3 * cmax, *sfy = stage + 4 * cmax, *sfz = stage + 5 * cmax;
+    int *st = (int *)(stage + 6 * cmax);
+    for (int k = lane; k < C; k += MDLJ_WAVE) {
+        int r = 0;
+        while (k >= seg_c[r + 1]) ++r;
+        const PosT p = rec[seg_b[r] + (k - seg_c[r])];
+        sx[k] = p.x;
+        sy[k] = p.y;
+        sz[k] = p.z;
+        if (MS) st[k] = p.t;
+        sfx[k] = 0.0;
+        sfy[k] = 0.0;
+        sfz[k] = 0.0;
+    }
+    __syncthreads();
+    double bu = 0.0, bw = 0.0;
+    if constexpr (!SWAP) {
+        const int ii = lane / AJ, jl = lane % AJ;
+        for (int a0 = 0; a0 < nown; a0 += AI) {
+            const int a = a0 + ii;
+            const bool act = a < nown;
+            const int aa = act ? a : 0;
+            const double xa = sx[aa], ya = sy[aa], za = sz[aa];
+            const int ta = MS ? st[aa] : 0;
+            Acc acc;
+            acc_zero(acc);
+            for (int b = aa + 1 + jl; b < C; b += AJ) {
+                const PairP<T> p = pair_params<T, MS>(tab, lt, ta, MS ? st[b] : 0);
+                double fxp, fyp, fzp;
+                if (lj_pair<T, E>(xa, ya, za, sx[b], sy[b], sz[b], act, p, rc2, acc, fxp, fyp,
+                                  fzp)) {
+                    atomicAdd(&sfx[b], -fxp);
+                    atomicAdd(&sfy[b], -fyp);
+                    atomicAdd(&sfz[b], -fzp);
+                }
+            }
+            acc.fx = seg_sum(acc.fx, AJ);
+            acc.fy = seg_sum(acc.fy, AJ);
+            acc.fz = seg_sum(acc.fz, AJ);
+            if (act && jl == 0) {
+                atomicAdd(&sfx[a], acc.fx);
+                atomicAdd(&sfy[a], acc.fy);
+                atomicAdd(&sfz[a], acc.fz);
+            }
+            if (E) {
+                bu += acc.u;
+                bw += acc.w;
+            }
+        }
+    } else {
+        for (int b0 = 0; b0 < C; b0 += MDLJ_WAVE) {
+            const int b = b0 + lane;
+            const bool act = b < C;
+            const int bb = act ? b : 0;
+            const double xb = sx[bb], yb = sy[bb], zb = sz[bb];
+            const int tb = MS ? st[bb] : 0;
+            Acc acc;
+            acc_zero(acc);
+            // own particles a < b: every lane walks the same a
+            const int amax = min(nown, b0 + MDLJ_WAVE);
+            for (int a = 0; a < amax; ++a) {
+                const PairP<T> p = pair_params<T, MS>(tab, lt, tb, MS ? st[a] : 0);
+                double fxp, fyp, fzp;
+                lj_pair<T, E>(xb, yb, zb, sx[a], sy[a], sz[a], act && a < b, p, rc2, acc, fxp,
+                              fyp, fzp);
+                // F_a = -sum over the lanes' F_b contributions
+                fxp = seg_sum(fxp, MDLJ_WAVE);
+                fyp = seg_sum(fyp, MDLJ_WAVE);
+                fzp = seg_sum(fzp, MDLJ_WAVE);
+                if (lane == 0) {
+                    sfx[a] -= fxp;
+                    sfy[a] -= fyp;
+                    sfz[a] -= fzp;
+                }
+            }
+            if (act) {
+                atomicAdd(&sfx[b], acc.fx);
+                atomicAdd(&sfy[b], acc.fy);
+                atomicAdd(&sfz[b], acc.fz);
+            }
+            if (E) {
+                bu += acc.u;
+                bw += acc.w;
+            }
+        }
+    }
+    __syncthreads();
+    // one atomic per component of every staged record that took a force
+    for (int k = lane; k < C; k += MDLJ_WAVE) {
+        const double fx = sfx[k], fy = sfy[k], fz = sfz[k];
+        if (fx != 0.0 || fy != 0.0 || fz != 0.0) {
+            int r = 0;
+            while (k >= seg_c[r + 1]) ++r;
+            const int slot = seg_b[r] + (k - seg_c[r]);
+            atomicAdd(&fo.fx[slot], fx);
+            atomicAdd(&fo.fy[slot], fy);
+            atomicAdd(&fo.fz[slot], fz);
+        }
+    }
+    if (E) wave_partial(bu, bw, 1.0, fo.partial, blockIdx.x);
+}
+
 // Unordered pairs {i, j} with r < rc, each counted once (from the particle
 // with the smaller caller index), in FP64.
 __global__ __launch_bounds__(64) void k_lc_count(const PosT *__restrict__ rec,
@@ -252,6 +422,32 @@ void launch_lc(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, For
     const PosT *rec = (const PosT *)ctx->b_sorted.p;
     const int32_t *start = (const int32_t *)ctx->b_start.p;
     hipStream_t s = ctx->stream;
+    if (cfg.newton3) {
+        const int64_t nb = g.ncell_int;
+        *nblocks = nb;
+        // own + 13 forward cells, x, y, z, three force sums and the species
+        const int cmax = 14 * ctx->max_cell;
+        const size_t lds = (size_t)cmax * (6 * sizeof(double) + (MS ? sizeof(int) : 0));
+        if (lds > (size_t)STAGE_LDS_BYTES) {
+            *nblocks = -2;
+            return;
+        }
+        if (cfg.swap) {
+            if (cfg.order != MDLJ_ORD_I_PER_LANE) {
+                *nblocks = -1;
+                return;
+            }
+            k_lc_half<T, E, MS, 64, true><<<nb, 64, lds, s>>>(rec, start, g, tab, fo, remap, cmax);
+            return;
+        }
+        switch (cfg.tile_i) {
+        case 1: k_lc_half<T, E, MS, 1, false><<<nb, 64, lds, s>>>(rec, start, g, tab, fo, remap, cmax); break;
+        case 4: k_lc_half<T, E, MS, 4, false><<<nb, 64, lds, s>>>(rec, start, g, tab, fo, remap, cmax); break;
+        case 16: k_lc_half<T, E, MS, 16, false><<<nb, 64, lds, s>>>(rec, start, g, tab, fo, remap, cmax); break;
+        default: *nblocks = -1;
+        }
+        return;
+    }
     if (cfg.order == MDLJ_ORD_I_PER_LANE) {
         const int K = cfg.tile_i;
         const int tiles_x = (int)ceil_div(g.n[0], K);
@@ -298,6 +494,8 @@ mdlj_status lc_forces_t(mdlj_ctx *ctx, const mdlj_config &cfg, bool energy, Forc
     const bool ms = ctx->nspec > 1;
     const int remap = 1;
     int64_t nb = 0;
+    // Newton-3 kernels add both forces of a pair with atomics
+    if (cfg.newton3) STCHK(zero_forces(ctx, fo, ctx->n_ext + 1));
     if (energy) {
         // partial buffer sized by the launch: one (U, W) per workgroup
         const Grid &g = ctx->grid;

@@ -121,7 +121,7 @@ struct mdlj_ctx {
     int rebuild_every = 10;
     int shift_on = 1;
     int prec = MDLJ_PREC_F32PAIR_F64ACC;
-    mdlj_config cfg = {MDLJ_NBR_LC, MDLJ_ORD_I_PER_LANE, 1, 1, 0, 0, 0};
+    mdlj_config cfg = {MDLJ_NBR_LC, MDLJ_ORD_I_PER_LANE, 1, 1, 0, 0, 0, 0};
     std::string err;
 
     // caller-order particle state (device)
@@ -152,7 +152,7 @@ struct mdlj_ctx {
 
     // neighbour structure state
     bool built = false;           // structure matches cfg/positions
-    mdlj_config built_cfg = {-1, -1, -1, -1, -1, -1, -1};
+    mdlj_config built_cfg = {-1, -1, -1, -1, -1, -1, -1, -1};
     int steps_since_build = 0;
     double built_box[3] = {0, 0, 0};
     double built_rc = -1, built_skin = -1;

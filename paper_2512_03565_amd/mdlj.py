@@ -32,11 +32,11 @@ ORD_NAMES = {0: "i-per-lane", 1: "cluster-tile", 2: "wave-per-i"}
 class mdlj_config(C.Structure):
     _fields_ = [("nbr_algo", C.c_int32), ("order", C.c_int32), ("tile_i", C.c_int32),
                 ("tile_j", C.c_int32), ("cluster_size", C.c_int32), ("newton3", C.c_int32),
-                ("staged", C.c_int32)]
+                ("staged", C.c_int32), ("swap", C.c_int32)]
 
     def astuple(self):
         return (self.nbr_algo, self.order, self.tile_i, self.tile_j, self.cluster_size,
-                self.newton3, self.staged)
+                self.newton3, self.staged, self.swap)
 
     def __repr__(self):
         return config_name(self)
@@ -44,14 +44,14 @@ class mdlj_config(C.Structure):
 
 def config_name(c) -> str:
     t = c.astuple() if hasattr(c, "astuple") else tuple(c)
-    t = tuple(t) + (0,) * (7 - len(t))
-    nb, o, ti, tj, m, n3, st = t
+    t = tuple(t) + (0,) * (8 - len(t))
+    nb, o, ti, tj, m, n3, st, sw = t
     s = NBR_NAMES[nb] + (str(m) if nb == NBR_VCL else "") + "/" + ORD_NAMES[o]
-    if o == ORD_I_PER_LANE and nb == NBR_LC:
+    if o == ORD_I_PER_LANE and nb == NBR_LC and not n3:
         s += f"/k{ti}"
     elif o != ORD_I_PER_LANE:
         s += f"/{ti}x{tj}"
-    return s + ("/n3" if n3 else "") + ("/lds" if st else "")
+    return s + ("/n3" if n3 else "") + ("/lds" if st else "") + ("/swap" if sw else "")
 
 
 class MdljError(RuntimeError):

@@ -1,7 +1,8 @@
 """Timing tables beside the benchmark.
 
 orders: the 100,000-particle FCC scene (rho 0.75, rc 2.5, skin 0.3, lists
-rebuilt every 10 steps, FP32 pair arithmetic): every configuration of the
+rebuilt every 10 steps), or with --scene 1M the 1,000,000-particle headline
+scene, in FP32 pair arithmetic (or --prec f64): every configuration of the
 search space runs --steps velocity-Verlet steps; ms per step, force-kernel
 and rebuild times from the library's events.
 
@@ -23,16 +24,19 @@ import time
 import numpy as np
 
 
-def orders(steps):
+def orders(steps, scene="100k", prec="f32"):
     import torch
     from paper_2512_03565_amd import mdlj, scenes
-    s = scenes.config2()
+    s = scenes.config2() if scene == "100k" else scenes.headline()
+    workload = ("100k FCC rho0.75 rc2.5 skin0.3" if scene == "100k"
+                else "1M FCC 50x50x100 rho0.75 rc2.5 skin0.3")
     n = len(s["pos"])
     vel0 = scenes.mb_velocities(n, s["T"], 1.0, seed=1012)
     pos = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     with mdlj.System(pos, s["box"], s["rc"], skin=s["skin"], rebuild_every=s["rebuild_every"],
-                     stream=stream) as sysm:
+                     stream=stream,
+                     precision=mdlj.PREC_F64 if prec == "f64" else mdlj.PREC_F32PAIR_F64ACC) as sysm:
         pairs = sysm.count_pairs()
         for cfg in sysm.configs():
             sysm.set_positions(pos)
@@ -47,7 +51,7 @@ def orders(steps):
             wall = time.perf_counter() - t0
             f_us, b_us, nf, nb = sysm.get_timing()
             sysm.set_timing(False)
-            print(json.dumps({"table": "orders", "workload": "100k FCC rho0.75 rc2.5 skin0.3",
+            print(json.dumps({"table": "orders", "workload": workload, "precision": prec,
                               "config": mdlj.config_name(cfg), "steps": steps,
                               "ms_per_step": 1e3 * wall / steps,
                               "mpairs_per_s": pairs * steps / wall / 1e6,
@@ -98,8 +102,10 @@ def main(argv=None):
     ap.add_argument("table", choices=["orders", "precision"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--scene", choices=["100k", "1M"], default="100k")
+    ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
     a = ap.parse_args(argv)
-    orders(a.steps) if a.table == "orders" else precision(a.reps)
+    orders(a.steps, a.scene, a.prec) if a.table == "orders" else precision(a.reps)
     return 0
 
 

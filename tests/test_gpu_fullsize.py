@@ -35,8 +35,10 @@ def test_headline_1m_every_particle(m, orc):
     pos, box, rc = s["pos"], s["box"], s["rc"]
     ref = orc.forces(pos, box, rc)
     runs = {0: ["VL/wave-per-i/16x4/lds", "VL/wave-per-i/8x8", "VL/wave-per-i/16x4",
-                "LC/cluster-tile/16x4/lds", "VCL4/cluster-tile/4x16", "VL/wave-per-i/16x4/n3"],
-            1: ["VL/wave-per-i/16x4/lds", "LC/i-per-lane/k1"]}
+                "LC/cluster-tile/16x4/lds", "VCL4/cluster-tile/4x16", "VL/wave-per-i/16x4/n3",
+                "LC/cluster-tile/4x16/n3/lds", "LC/i-per-lane/n3/lds/swap"],
+            1: ["VL/wave-per-i/16x4/lds", "LC/i-per-lane/k1", "LC/wave-per-i/1x64/n3/lds",
+                "LC/cluster-tile/16x4/n3/lds"]}
     with m.System(pos, box, rc, skin=s["skin"], rebuild_every=s["rebuild_every"]) as sysm:
         for prec, names in runs.items():
             band = P.fx_band(box, rc, s["skin"]) if prec == 0 else P.F64_BAND

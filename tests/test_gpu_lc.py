@@ -28,7 +28,16 @@ def lc_configs(m):
     for st in (0, 1):
         out += [(m.NBR_LC, m.ORD_CLUSTER_TILE, a, 64 // a, 0, 0, st) for a in (8, 16)]
         out += [(m.NBR_LC, m.ORD_WAVE_PER_I, g, 64 // g, 0, 0, st) for g in (1, 2, 4)]
-    return out
+    return out + lc_n3_configs(m)
+
+
+def lc_n3_configs(m):
+    """Newton 3 over a half shell of cells: the own particles as the i-list
+    (three lane grids) and the roles swapped."""
+    return [(m.NBR_LC, m.ORD_WAVE_PER_I, 1, 64, 0, 1, 1, 0),
+            (m.NBR_LC, m.ORD_CLUSTER_TILE, 4, 16, 0, 1, 1, 0),
+            (m.NBR_LC, m.ORD_CLUSTER_TILE, 16, 4, 0, 1, 1, 0),
+            (m.NBR_LC, m.ORD_I_PER_LANE, 1, 1, 0, 1, 1, 1)]
 
 
 def check_scene(m, orc, s, configs, precs=(0, 1), label=""):
@@ -143,3 +152,24 @@ def test_errors_geometry_state_nonfinite(m):
         # the context stays usable after a rejected call
         f, U, W = sysm.forces()
         assert np.isfinite(f).all()
+
+
+def test_lc_newton3_three_cells_per_axis(m, orc):
+    # 3 cells per axis: a cell's forward neighbours across the periodic
+    # boundary are images of cells whose own forward shell reaches it too;
+    # each pair must still be computed exactly once
+    pos, box = scenes.sc_lattice(7, 7, 8, 1.1, 0.08, seed=23)
+    assert all(int(L // 2.5) == 3 for L in box)
+    s = dict(pos=pos, box=box, rc=2.5, eps=[1.0], sig=[1.0], types=None)
+    check_scene(m, orc, s, lc_n3_configs(m), label="3 cells")
+
+
+def test_lc_newton3_net_force_vanishes(m, orc):
+    # Newton's third law: the computed forces sum to zero to rounding
+    s = scenes.config2()
+    with m.System(s["pos"], s["box"], s["rc"], precision=1) as sysm:
+        for cfg in lc_n3_configs(m):
+            sysm.set_config(cfg)
+            f, U, W = sysm.forces()
+            net = np.abs(f.sum(0)).max()
+            assert net <= 1e-11 * P.frms(f) * np.sqrt(len(f)), (cfg, net)
