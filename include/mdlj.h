@@ -76,6 +76,10 @@ enum { MDLJ_ORD_I_PER_LANE = 0, MDLJ_ORD_CLUSTER_TILE = 1, MDLJ_ORD_WAVE_PER_I =
 /* Arithmetic: FP32 pair arithmetic with FP64 accumulation, or all FP64. */
 enum { MDLJ_PREC_F32PAIR_F64ACC = 0, MDLJ_PREC_F64 = 1 };
 
+/* What the tuner minimises: time per MD step, or energy per MD step
+ * (section 2.3.3; read from the GPU's energy counter). */
+enum { MDLJ_METRIC_TIME = 0, MDLJ_METRIC_ENERGY = 1 };
+
 /* Tuning strategy (section 2.3.2 full search; section 6 data-driven and
  * cheaper searches). */
 enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2,
@@ -319,6 +323,35 @@ mdlj_status mdlj_tune(mdlj_ctx *ctx, int32_t mode, int32_t samples, mdlj_config 
  * samples each configuration used. */
 mdlj_status mdlj_tune_results(const mdlj_ctx *ctx, double *us, int32_t cap, int32_t *count);
 mdlj_status mdlj_tune_taken(const mdlj_ctx *ctx, int32_t *taken, int32_t cap, int32_t *count);
+
+/*
+ * Energy as the tuning metric (section 2.3.3).  set_tune_metric: TIME
+ * (default) or ENERGY for the following mdlj_tune calls.  Under ENERGY a
+ * configuration's value is microjoules per MD step: its steps run (as for
+ * the time metric, time step 0) while the GPU's energy counter, which the
+ * firmware refreshes about once a second, is read between runs of at least
+ * 5 ms; `samples` is then the number of refresh intervals the measured
+ * window spans (>= 1, so about `samples` seconds per configuration), and
+ * the value is the mean power over that window times the mean step time
+ * of the steps run in it.  FIXED and EXHAUSTIVE measure by energy; LEARNED
+ * falls back to EXHAUSTIVE (the network predicts the fastest
+ * configuration); EARLY_STOP gives MDLJ_ERR_ARG.  mdlj_tune_results then
+ * reports microjoules per step and mdlj_tune_power the mean watts of each
+ * configuration (NaN under TIME).  The counter is read through AMD SMI
+ * (libamd_smi, loaded on first use): MDLJ_ERR_NOTFOUND without it, and
+ * MDLJ_ERR_STATE when the counter is not refreshed.
+ * mdlj_gpu_energy: the counter now, in joules, and the time of its last
+ * refresh in seconds (the firmware's clock).
+ * mdlj_tune_select_energy (pure host function): energy per step
+ * us[q] * watts[q] (microjoules; +inf where either is not a positive
+ * number) into uj[q] and the smallest, lower index on ties (-1 if none):
+ * a configuration that runs faster but draws more power can lose.
+ */
+mdlj_status mdlj_set_tune_metric(mdlj_ctx *ctx, int32_t metric);
+mdlj_status mdlj_tune_power(const mdlj_ctx *ctx, double *watts, int32_t cap, int32_t *count);
+mdlj_status mdlj_gpu_energy(mdlj_ctx *ctx, double *joules, double *seconds);
+mdlj_status mdlj_tune_select_energy(const double *us, const double *watts, int32_t k, double *uj,
+                                    int32_t *chosen);
 
 /*
  * Decision rules of the tuner, as pure host functions (no context, no

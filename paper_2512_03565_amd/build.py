@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdlj.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["api.cpp", "bin.hip", "force_lc.hip", "vl.hip", "vcl.hip", "integrate.hip", "tune.cpp", "mlp.hip"]
+SOURCES = ["api.cpp", "bin.hip", "force_lc.hip", "vl.hip", "vcl.hip", "integrate.hip", "tune.cpp",
+           "mlp.hip", "energy.cpp"]
 ARCH = os.environ.get("MDLJ_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
@@ -42,7 +43,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-ldl"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -182,6 +182,8 @@ struct mdlj_ctx {
     std::vector<mdlj_config> space;
     std::vector<double> tune_us;
     std::vector<int> tune_taken;  // samples each configuration used in the last search
+    std::vector<double> tune_watts;  // mean power per configuration (energy metric)
+    int tune_metric = MDLJ_METRIC_TIME;
     // learned tuner
     std::vector<float> mlp_w, mlp_m, mlp_v;
     float mlp_mean[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -341,6 +343,8 @@ mdlj_status tune_exhaustive(mdlj_ctx *ctx, int samples, mdlj_config *chosen, dou
 mdlj_status tune_measure_current(mdlj_ctx *ctx, int samples, double *us);
 mdlj_status tune_learned(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *us);
 mdlj_status tune_early(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *us);
+// The GPU's energy counter (AMD SMI): joules and the refresh timestamp (ns).
+mdlj_status energy_read(mdlj_ctx *ctx, double *joules, uint64_t *ts_ns);
 // Configuration indices by descending network probability for the current
 // scene; empty when no network for this search space is loaded.
 mdlj_status mlp_rank(mdlj_ctx *ctx, std::vector<int> &order);

@@ -335,7 +335,10 @@ mdlj_status mlp_rank(mdlj_ctx *ctx, std::vector<int> &order)
 
 mdlj_status tune_learned(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *us)
 {
-    if (!ctx->mlp_loaded || ctx->mlp_k != (int)ctx->space.size())
+    // the network predicts the fastest configuration: under the energy
+    // metric the full search decides
+    if (!ctx->mlp_loaded || ctx->mlp_k != (int)ctx->space.size() ||
+        ctx->tune_metric != MDLJ_METRIC_TIME)
         return tune_exhaustive(ctx, samples, chosen, us);
     float f[DIN];
     STCHK(features_dev(ctx, f));

@@ -21,6 +21,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cmath>
 #include <limits>
 #include <memory>
 #include <vector>
@@ -142,6 +144,79 @@ mdlj_status measure(mdlj_ctx *ctx, const mdlj_config &c, int samples, double *ou
     });
 }
 
+// Energy per MD step of configuration c (section 2.3.3): its steps run in
+// chunks of whole cycles (each chunk at least 5 ms, so the counter reads
+// between chunks idle the GPU little) until the energy counter has been
+// refreshed `windows` + 1 times; the mean power between the first and the
+// last refresh (joules over their timestamps) times the mean step time of
+// the chunks run between them is the energy per step.  *uj = microjoules
+// per step, *watts = that mean power, *us = microseconds per step.
+mdlj_status measure_energy(mdlj_ctx *ctx, const mdlj_config &c, int windows, double *uj,
+                           double *watts, double *us)
+{
+    return untimed(ctx, [&]() -> mdlj_status {
+        Cycles cy{ctx, c, {}, 1, nullptr};
+        STCHK(cy.start());
+        double warm = 0;
+        STCHK(cy.sample(&warm));
+        const int per = std::max(1, (int)std::ceil(5000.0 / std::max(warm * cy.R, 1.0)));
+        double e = 0, ea = 0, eb = 0;
+        uint64_t t = 0, tlast = 0, ta = 0, tb = 0;
+        STCHK(energy_read(ctx, &e, &tlast));
+        int seen = 0;
+        double chunk_us = 0;
+        int64_t steps = 0;
+        const auto t_start = std::chrono::steady_clock::now();
+        while (seen <= windows) {
+            double sum = 0;
+            for (int k = 0; k < per; ++k) {
+                double s_us = 0;
+                STCHK(cy.sample(&s_us));
+                sum += s_us * cy.R;
+            }
+            if (seen >= 1) {
+                chunk_us += sum;
+                steps += (int64_t)per * cy.R;
+            }
+            STCHK(energy_read(ctx, &e, &t));
+            if (t != tlast) {
+                if (seen == 0) {
+                    ea = e;
+                    ta = t;
+                } else {
+                    eb = e;
+                    tb = t;
+                }
+                ++seen;
+                tlast = t;
+            }
+            const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() -
+                                                              t_start).count();
+            if (wall > 4.0 + 2.0 * windows)
+                return set_err(ctx, MDLJ_ERR_STATE, "the energy counter is not being refreshed");
+        }
+        if (!(tb > ta) || steps == 0)
+            return set_err(ctx, MDLJ_ERR_STATE, "no energy window");
+        *watts = (eb - ea) / ((double)(tb - ta) * 1e-9);
+        *us = chunk_us / (double)steps;
+        *uj = *watts * *us;
+        return MDLJ_OK;
+    });
+}
+
+// The tuner's value of configuration c: microseconds per step (time
+// metric) or microjoules per step (energy metric; then also its power).
+mdlj_status measure_metric(mdlj_ctx *ctx, const mdlj_config &c, int samples, double *value,
+                           double *watts)
+{
+    *watts = std::numeric_limits<double>::quiet_NaN();
+    if (ctx->tune_metric == MDLJ_METRIC_ENERGY) {
+        double us = 0;
+        return measure_energy(ctx, c, samples, value, watts, &us);
+    }
+    return measure(ctx, c, samples, value);
+}
+
 }  // namespace
 
 // Early-stopping decision of the cheaper search: after sample j of a
@@ -215,10 +290,11 @@ mdlj_status tune_exhaustive(mdlj_ctx *ctx, int samples, mdlj_config *chosen, dou
     const size_t K = ctx->space.size();
     ctx->tune_us.assign(K, std::numeric_limits<double>::infinity());
     ctx->tune_taken.assign(K, 0);
+    ctx->tune_watts.assign(K, std::numeric_limits<double>::quiet_NaN());
     size_t best = K;
     for (size_t k = 0; k < K; ++k) {
-        double us = 0;
-        mdlj_status st = measure(ctx, ctx->space[k], samples, &us);
+        double us = 0, w = 0;
+        mdlj_status st = measure_metric(ctx, ctx->space[k], samples, &us, &w);
         if (st == MDLJ_ERR_GEOMETRY || st == MDLJ_ERR_ARG) continue;  // not valid for this box
         if (st != MDLJ_OK) {
             ctx->cfg = saved;
@@ -226,6 +302,7 @@ mdlj_status tune_exhaustive(mdlj_ctx *ctx, int samples, mdlj_config *chosen, dou
             return st;
         }
         ctx->tune_us[k] = us;
+        ctx->tune_watts[k] = w;
         ctx->tune_taken[k] = samples;
         if (best == K || us < ctx->tune_us[best]) best = k;
     }
@@ -252,6 +329,9 @@ constexpr double EARLY_MARGIN = 0.10;
 
 mdlj_status tune_early(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *best_us)
 {
+    if (ctx->tune_metric != MDLJ_METRIC_TIME)
+        return set_err(ctx, MDLJ_ERR_ARG, "early stopping compares time cycles; the energy metric "
+                                          "takes EXHAUSTIVE or FIXED");
     const mdlj_config saved = ctx->cfg;
     const int K = (int)ctx->space.size();
     // most promising first: the network's ranking when one for this search
@@ -307,7 +387,8 @@ mdlj_status tune_early(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double *
 
 mdlj_status tune_measure_current(mdlj_ctx *ctx, int samples, double *us)
 {
-    mdlj_status st = measure(ctx, ctx->cfg, samples, us);
+    double w = 0;
+    mdlj_status st = measure_metric(ctx, ctx->cfg, samples, us, &w);
     ctx->built = false;
     ctx->forces_valid = false;
     return st;
@@ -376,6 +457,35 @@ mdlj_status mdlj_tune_select_early(const double *samples, int32_t k, int32_t s,
     STCHK(search_early(k, s, order, warm_factor, margin, fetch, values, tk.data(), &best));
     for (int32_t q = 0; q < k; ++q) taken[q] = tk[q];
     *chosen = best;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_tune_metric(mdlj_ctx *ctx, int32_t metric)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (metric != MDLJ_METRIC_TIME && metric != MDLJ_METRIC_ENERGY)
+        return set_err(ctx, MDLJ_ERR_ARG, "unknown tuning metric");
+    ctx->tune_metric = metric;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_tune_power(const mdlj_ctx *ctx, double *watts, int32_t cap, int32_t *count)
+{
+    if (!ctx || !count || (cap > 0 && !watts)) return MDLJ_ERR_ARG;
+    *count = (int32_t)ctx->tune_watts.size();
+    for (int32_t k = 0; k < cap && k < *count; ++k) watts[k] = ctx->tune_watts[k];
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_tune_select_energy(const double *us, const double *watts, int32_t k,
+                                    double *uj, int32_t *chosen)
+{
+    if (!us || !watts || !uj || !chosen || k < 1) return MDLJ_ERR_ARG;
+    for (int32_t q = 0; q < k; ++q) {
+        const double e = us[q] * watts[q];
+        uj[q] = (e == e && us[q] > 0 && watts[q] > 0) ? e : std::numeric_limits<double>::infinity();
+    }
+    *chosen = select_config(uj, k, 1, 0, uj);
     return MDLJ_OK;
 }
 

@@ -25,6 +25,7 @@ NBR_LC, NBR_VL, NBR_VCL = 0, 1, 2
 ORD_I_PER_LANE, ORD_CLUSTER_TILE, ORD_WAVE_PER_I = 0, 1, 2
 PREC_F32PAIR_F64ACC, PREC_F64 = 0, 1
 TUNE_FIXED, TUNE_EXHAUSTIVE, TUNE_LEARNED, TUNE_EARLY_STOP = 0, 1, 2, 3
+METRIC_TIME, METRIC_ENERGY = 0, 1
 NBR_NAMES = {0: "LC", 1: "VL", 2: "VCL"}
 ORD_NAMES = {0: "i-per-lane", 1: "cluster-tile", 2: "wave-per-i"}
 
@@ -123,6 +124,10 @@ _SIGS = {
                            C.POINTER(C.c_int32)],
     "mdlj_get_timing": [_ctxp, _d, _d, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "mdlj_get_timing_fused": [_ctxp, _d, C.POINTER(C.c_int64)],
+    "mdlj_set_tune_metric": [_ctxp, C.c_int32],
+    "mdlj_tune_power": [_ctxp, _d, C.c_int32, C.POINTER(C.c_int32)],
+    "mdlj_gpu_energy": [_ctxp, _d, _d],
+    "mdlj_tune_select_energy": [_d, _d, C.c_int32, _d, C.POINTER(C.c_int32)],
     "mdlj_compute_forces_noalloc": [_ctxp, _vp, _vp, _vp, _d, _d],
     "mdlj_get_cells": [_ctxp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "mdlj_get_pairs": [_ctxp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -361,6 +366,21 @@ class System:
         check(lib.mdlj_tune_results(self.ctx, buf, 256, C.byref(n)), self.ctx)
         return np.array(buf[: n.value])
 
+    def set_tune_metric(self, metric):
+        check(lib.mdlj_set_tune_metric(self.ctx, int(metric)), self.ctx)
+
+    def tune_power(self):
+        n = C.c_int32()
+        buf = (C.c_double * 256)()
+        check(lib.mdlj_tune_power(self.ctx, buf, 256, C.byref(n)), self.ctx)
+        return np.array(buf[: n.value])
+
+    def gpu_energy(self):
+        """(joules, seconds) of the GPU's energy counter and its last refresh."""
+        j, s = C.c_double(), C.c_double()
+        check(lib.mdlj_gpu_energy(self.ctx, C.byref(j), C.byref(s)), self.ctx)
+        return j.value, s.value
+
     def tune_taken(self):
         n = C.c_int32()
         buf = (C.c_int32 * 256)()
@@ -487,6 +507,17 @@ def tune_select_early(samples, order=None, warm_factor=2.0, margin=0.1):
                                      float(warm_factor), float(margin), vals.ctypes.data_as(_d),
                                      taken.ctypes.data_as(i32), C.byref(ch)))
     return vals, taken, ch.value
+
+
+def tune_select_energy(us, watts):
+    """Energy per step (microjoules) of each configuration and the chosen index."""
+    u = np.ascontiguousarray(us, np.float64)
+    w = np.ascontiguousarray(watts, np.float64)
+    out = np.empty(len(u))
+    ch = C.c_int32()
+    check(lib.mdlj_tune_select_energy(u.ctypes.data_as(_d), w.ctypes.data_as(_d), len(u),
+                                      out.ctypes.data_as(_d), C.byref(ch)))
+    return out, ch.value
 
 
 def retune_needed(before, now, threshold=0.1):

@@ -125,3 +125,23 @@ def test_early_stop_ties_and_bad_arguments(m):
         m.tune_select_early(t, order=[0, 0])
     with pytest.raises(m.MdljError):
         m.tune_select_early(t, warm_factor=0.5)
+
+
+# ------------------------------------------------------- energy as the metric
+
+def test_energy_optimum_can_differ_from_time_optimum(m):
+    # section 2.3.3: tuning for energy instead of runtime.  Energy per step
+    # is power times time: the fastest configuration draws the most power
+    us = np.array([100.0, 110.0, 140.0, np.inf])
+    watts = np.array([900.0, 700.0, 600.0, 500.0])
+    uj, k = m.tune_select_energy(us, watts)
+    assert np.allclose(uj[:3], [90000.0, 77000.0, 84000.0]) and np.isinf(uj[3])
+    assert k == 1
+    assert m.tune_select(us[:, None])[1] == 0
+
+
+def test_energy_rule_ties_and_invalid(m):
+    uj, k = m.tune_select_energy([2.0, 1.0, 4.0], [1.0, 2.0, 0.5])
+    assert k == 0 and np.allclose(uj, [2.0, 2.0, 2.0])
+    uj, k = m.tune_select_energy([np.nan, 1.0], [1.0, -3.0])
+    assert k == -1 and np.all(np.isinf(uj))
