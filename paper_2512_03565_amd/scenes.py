@@ -81,59 +81,110 @@ def random_box(n, box, seed=0):
     return rng.uniform(0.0, 1.0, (n, 3)) * box
 
 
-def rsa_points(box, count, dmin, seed, inside=None, existing=None, batch=4096,
-               max_tries=400):
-    """Random sequential addition: uniform darts kept when no accepted point
-    lies closer than dmin (periodic); ``inside(p)->bool mask`` restricts the
-    region.  Returns the new points (count, 3).  A uniform hash grid of edge
-    >= dmin bounds the neighbour test to 27 cells."""
+def rsa_points(box, count, dmin, seed, inside=None, existing=None, region=None,
+               batch=1 << 18, progress=None, max_batches=200000):
+    """Random sequential addition (Poisson-disk darts): uniform darts, kept
+    when no accepted point lies closer than dmin (periodic box);
+    ``inside(p) -> bool mask`` restricts the region, ``region = (lo, hi)``
+    the sub-box the darts are drawn in; ``existing`` points count as
+    accepted.  Returns the new points (count, 3).
+
+    Vectorised on a grid of cells of edge dmin / sqrt(3), which hold at most
+    one point each: a batch of darts is tested against the accepted points
+    of the 5 x 5 x 5 cells around it, then against the earlier darts of the
+    same batch (a dart near an earlier surviving one is dropped, whether or
+    not that one survives its own tests, so the batch keeps the minimum
+    spacing; this drops slightly more darts than one-at-a-time addition)."""
     rng = np.random.default_rng(seed)
     box = np.asarray(box, np.float64)
-    nc = np.maximum(np.floor(box / dmin).astype(np.int64), 1)
+    nc = np.maximum(np.floor(box / (dmin / math.sqrt(3.0))).astype(np.int64), 1)
     edge = box / nc
-    cells: dict = {}
-    pts = []
+    ne = 0 if existing is None else len(existing)
+    grid = np.full(int(nc[0] * nc[1] * nc[2]), -1, np.int64)
+    store = np.empty((count + ne, 3))
 
-    def key(p):
-        c = np.minimum((p / edge).astype(np.int64), nc - 1)
-        return (int(c[0]), int(c[1]), int(c[2]))
+    def cells(p):
+        return np.minimum((p / edge).astype(np.int64), nc - 1)
 
-    def ok(p):
-        c = key(p)
-        for dz in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dx in (-1, 0, 1):
-                    k = ((c[0] + dx) % nc[0], (c[1] + dy) % nc[1], (c[2] + dz) % nc[2])
-                    for q in cells.get(k, ()):
-                        d = p - q
-                        d -= box * np.rint(d / box)
-                        if d @ d < dmin * dmin:
-                            return False
-        return True
+    def lin(c):
+        c = c % nc
+        return c[..., 0] + nc[0] * (c[..., 1] + nc[1] * c[..., 2])
 
-    if existing is not None:
-        for q in existing:
-            cells.setdefault(key(q), []).append(q)
-    tries = 0
-    while len(pts) < count:
-        cand = rng.uniform(0.0, 1.0, (batch, 3)) * box
+    if ne:
+        ex = np.asarray(existing, np.float64)
+        grid[lin(cells(ex))] = np.arange(ne)
+        store[:ne] = ex
+    npts = ne
+    offs = np.array([(dx, dy, dz) for dz in range(-2, 3) for dy in range(-2, 3)
+                     for dx in range(-2, 3)])
+    gap = np.maximum(np.abs(offs) - 1, 0) * edge
+    offs = offs[(gap ** 2).sum(1) < dmin * dmin]
+    d2 = dmin * dmin
+    lo, hi = (np.zeros(3), box) if region is None else (np.asarray(region[0], np.float64),
+                                                          np.asarray(region[1], np.float64))
+    nb = 0
+    while npts - ne < count:
+        nb += 1
+        if nb > max_batches:
+            raise RuntimeError("RSA did not reach the requested count")
+        cand = lo + rng.uniform(0.0, 1.0, (batch, 3)) * (hi - lo)
+        cand -= box * np.floor(cand / box)
         if inside is not None:
             cand = cand[inside(cand)]
-        for p in cand:
-            if ok(p):
-                pts.append(p)
-                cells.setdefault(key(p), []).append(p)
-                if len(pts) == count:
-                    break
-        tries += 1
-        if tries > max_tries * max(1, count // batch + 1):
-            raise RuntimeError("RSA did not reach the requested count")
-    return np.array(pts, np.float64).reshape(-1, 3)
+        c = cells(cand)
+        ok = grid[lin(c)] < 0
+        cand, c = cand[ok], c[ok]
+        for o in offs:
+            if len(cand) == 0:
+                break
+            j = grid[lin(c + o)]
+            hit = j >= 0
+            if hit.any():
+                d = cand[hit] - store[j[hit]]
+                d -= box * np.rint(d / box)
+                bad = np.zeros(len(cand), bool)
+                bad[np.flatnonzero(hit)[(d * d).sum(1) < d2]] = True
+                cand, c = cand[~bad], c[~bad]
+        if len(cand) == 0:
+            continue
+        # one dart per cell (the first), then no dart near an earlier one
+        L = lin(c)
+        order = np.argsort(L, kind="stable")
+        first = np.ones(len(cand), bool)
+        sl = L[order]
+        first[order[np.r_[False, sl[1:] == sl[:-1]]]] = False
+        cand, c, L = cand[first], c[first], L[first]
+        keep = np.ones(len(cand), bool)
+        grid[L] = -(np.arange(len(cand)) + 2)
+        for o in offs:
+            if (o == 0).all():
+                continue
+            j = grid[lin(c + o)]
+            m = j <= -2
+            if m.any():
+                k = -(j[m] + 2)
+                me = np.flatnonzero(m)
+                e = k < me
+                me, k = me[e], k[e]
+                d = cand[me] - cand[k]
+                d -= box * np.rint(d / box)
+                keep[me[(d * d).sum(1) < d2]] = False
+        grid[L] = -1
+        room = count - (npts - ne)
+        cand, L = cand[keep][:room], L[keep][:room]
+        grid[L] = np.arange(npts, npts + len(cand))
+        store[npts:npts + len(cand)] = cand
+        npts += len(cand)
+        if progress is not None and nb % 50 == 0:
+            progress(npts - ne, count)
+    return store[ne:npts].copy()
 
 
-def droplet_scene(n_total, r_drop, rho_drop, rho_vap, dmin, seed):
-    """Spherical droplet at rho_drop in vapour at rho_vap, periodic cube; RSA
-    darts with minimum spacing dmin, droplet first, then vapour outside it."""
+def droplet_scene(n_total, r_drop, rho_drop, rho_vap, dmin, seed, progress=None):
+    """Spherical droplet at rho_drop in vapour at rho_vap, periodic cube of
+    edge (V_drop + N_vap / rho_vap)^(1/3); Poisson-disk darts (random
+    sequential addition) with minimum spacing dmin, droplet first (darts
+    drawn in its bounding cube), then vapour outside it."""
     v_drop = 4.0 / 3.0 * math.pi * r_drop ** 3
     n_drop = int(round(rho_drop * v_drop))
     n_vap = n_total - n_drop
@@ -147,8 +198,10 @@ def droplet_scene(n_total, r_drop, rho_drop, rho_vap, dmin, seed):
     def out_drop(p):
         return ~in_drop(p)
 
-    drop = rsa_points(box, n_drop, dmin, seed, inside=in_drop)
-    vap = rsa_points(box, n_vap, dmin, seed + 1, inside=out_drop, existing=drop)
+    drop = rsa_points(box, n_drop, dmin, seed, inside=in_drop, region=(c - r_drop, c + r_drop),
+                      progress=progress)
+    vap = rsa_points(box, n_vap, dmin, seed + 1, inside=out_drop, existing=drop,
+                     progress=progress)
     return np.concatenate([drop, vap]), box
 
 
@@ -235,18 +288,30 @@ def config4(seed=1004, ncell=100):
                   name=f"{len(pos)} two-species FCC rho0.7 rc3.0")
 
 
-def config3(seed=1003, n_total=1_000_000, r_drop=40.0):
+def config3(seed=1003, n_total=1_000_000, r_drop=40.0, progress=None):
     """Droplet of radius r_drop at rho 0.8 inside vapour at rho 0.05 in a
-    periodic cube, about n_total particles, rc 3.0, T = 0.9.  The droplet is
-    a jittered FCC lattice cut to the sphere and the vapour a jittered simple
-    cubic lattice (minimum spacing above 0.9 in both); random sequential
-    addition at rho 0.8 with spacing 0.9 is too close to its jamming limit to
-    be practical at this size."""
-    n_drop = 0.8 * 4.0 / 3.0 * math.pi * r_drop ** 3
-    pos, box = lattice_droplet(n_total, 0.8, frac_drop=n_drop / n_total, rho_vap=0.05,
-                               jitter=0.05, seed=seed)
+    periodic cube (edge 251.87 for 1M particles), positions by Poisson-disk
+    sampling (random sequential addition) with minimum spacing 0.9, droplet
+    first; rc 3.0, T = 0.9, skin 0.3, lists rebuilt every 10 steps."""
+    pos, box = droplet_scene(n_total, r_drop, 0.8, 0.05, 0.9, seed, progress=progress)
     return _scene(pos, box, rc=3.0, skin=0.3, rebuild_every=10, T=0.9, dt=0.002,
                   name=f"{len(pos)} droplet r{r_drop}")
+
+
+def exploding_block(ncell=(50, 50, 100), rho=0.75, box_factor=3.0, T=5.0, seed=1006):
+    """A dense block released into vacuum (the paper's exploding-liquid
+    benchmark, with synthetic sizes): jittered FCC of ncell unit cells at
+    density rho (1M particles by default), centred in a periodic box
+    box_factor times its size along every axis, Maxwell-Boltzmann
+    velocities at the high temperature T, so the block expands into the
+    empty space and the particle density changes across the run; rc 2.5,
+    skin 0.3, lists rebuilt every 10 steps (earlier when a particle moves
+    more than skin/2)."""
+    pos, blk = fcc_lattice(ncell[0], ncell[1], ncell[2], rho, 0.05, seed)
+    box = box_factor * blk
+    pos = pos + 0.5 * (box - blk)
+    return _scene(pos, box, rc=2.5, skin=0.3, rebuild_every=10, T=T, dt=0.002,
+                  name=f"{len(pos)} exploding block T{T}")
 
 
 def tuning_scene(index, n_min=1e4, n_max=4e6):

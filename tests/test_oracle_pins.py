@@ -362,3 +362,18 @@ def test_adam_first_step_closed_form(orc):
         prev = w.copy()
         orc.adam_step(w, g, m, v, t, lr=1e-2, eps=1e-8)
         assert np.allclose(prev - w, 1e-2 * np.sign(g), rtol=1e-6)
+
+
+# ---------------------------------------------------------------- inputs
+
+def test_poisson_disk_droplet_spacing_and_counts():
+    # the droplet workload's sampler: exact counts inside and outside the
+    # sphere, and no two points (periodic) closer than the spacing
+    from scipy.spatial import cKDTree
+    pos, box = scenes.droplet_scene(20_000, 10.0, 0.8, 0.05, 0.9, seed=7)
+    c = box / 2
+    inside = ((pos - c) ** 2).sum(1) < 100.0
+    assert inside.sum() == int(round(0.8 * 4.0 / 3.0 * math.pi * 1000.0))
+    assert len(pos) == 20_000
+    tree = cKDTree(pos, boxsize=box)
+    assert len(tree.query_pairs(0.9 * (1 - 1e-12))) == 0
