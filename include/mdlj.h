@@ -123,8 +123,10 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2,
  * swap = 0, the cell's own particles (WAVE_PER_I 1x64, CLUSTER_TILE 4x16 or
  * 16x4: tile_i i's per step, tile_j lanes each over its partners); swap =
  * 1, the partners (I_PER_LANE, tile_i = 1: each lane one partner, the own
- * particles broadcast to all lanes).  swap is 0 for every other
- * configuration.
+ * particles broadcast to all lanes).  VCL CLUSTER_TILE: swap = 0 runs the
+ * lanes over j fastest (the 2/(VL/2) fill widened to 64 lanes), swap = 1
+ * over i fastest (the (VL/2)/2 fill), both cluster_size i's by
+ * 64/cluster_size j's.  swap is 0 for every other configuration.
  */
 typedef struct {
     int32_t nbr_algo;
@@ -259,6 +261,26 @@ mdlj_status mdlj_count_pairs(mdlj_ctx *ctx, int64_t *n_useful_pairs);
  */
 mdlj_status mdlj_neighbor_stats(mdlj_ctx *ctx, int64_t *list_entries, int32_t *entry_bytes,
                                 int64_t *records);
+
+/*
+ * Which pair each lane computes in one step of an interaction order
+ * (section 4.1.1, the register fills of Fig. "vec_patterns"), as offsets
+ * (*i, *j) from the step's first i and first j.  Pure host functions.
+ *   lane_map: a vector of `width` lanes holding ai i's (ai divides width).
+ *     layout 0 (j fastest): lane -> (lane / (width/ai), lane % (width/ai));
+ *     ai = 1 is 1/VectorLength, ai = 2 is 2/VectorLengthDiv2.
+ *     layout 1 (i fastest): lane -> (lane % ai, lane / ai); ai = width is
+ *     VectorLength/1, ai = width/2 is VectorLengthDiv2/2.
+ *   config_lane_map: the map the kernel of configuration *cfg uses on its
+ *     64-lane wavefronts (*layout receives 0 or 1): i-per-lane orders take
+ *     layout 1 with 64 i's; wave-per-i and the linked-cell tiles layout 0
+ *     with tile_i i's; the VCL cluster tiles layout swap with cluster_size
+ *     i's.  The kernels take their lane offsets from the same function.
+ */
+mdlj_status mdlj_lane_map(int32_t layout, int32_t ai, int32_t width, int32_t lane, int32_t *i,
+                          int32_t *j);
+mdlj_status mdlj_config_lane_map(const mdlj_config *cfg, int32_t lane, int32_t *layout,
+                                 int32_t *i, int32_t *j);
 
 /*
  * Index views of the neighbour structure, for checking it against a plain

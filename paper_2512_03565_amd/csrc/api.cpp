@@ -16,6 +16,7 @@
 #include <string>
 
 #include "internal.h"
+#include "lanemap.h"
 
 #define MDLJ_VERSION_STR "mdlj 0.1 gfx950"
 
@@ -146,6 +147,8 @@ static std::vector<mdlj_config> build_space()
         for (int n3 : {0, 1}) {
             v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_I_PER_LANE, 0, 0, m, n3, 0});
             v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_CLUSTER_TILE, m, 64 / m, m, n3, 0});
+            // the same tile with the lanes running over i fastest
+            v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_CLUSTER_TILE, m, 64 / m, m, n3, 0, 1});
         }
     return v;
 }
@@ -867,6 +870,42 @@ mdlj_status mdlj_neighbor_stats(mdlj_ctx *ctx, int64_t *list_entries, int32_t *e
         STCHK(vl_list_entries(ctx, list_entries));
         *entry_bytes = b.staged ? 2 : 4;
     }
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_lane_map(int32_t layout, int32_t ai, int32_t width, int32_t lane, int32_t *i,
+                          int32_t *j)
+{
+    if (!i || !j || (layout != LANE_I_MAJOR && layout != LANE_J_MAJOR) || width < 1 || ai < 1 ||
+        ai > width || width % ai != 0 || lane < 0 || lane >= width)
+        return MDLJ_ERR_ARG;
+    const LanePair p = lane_pair(layout, ai, width, lane);
+    *i = p.i;
+    *j = p.j;
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_config_lane_map(const mdlj_config *cfg, int32_t lane, int32_t *layout,
+                                 int32_t *i, int32_t *j)
+{
+    if (!cfg || !layout || !i || !j || lane < 0 || lane >= MDLJ_WAVE) return MDLJ_ERR_ARG;
+    int lay = LANE_I_MAJOR, ai = 1;
+    const bool ipl = cfg->order == MDLJ_ORD_I_PER_LANE;
+    if (ipl) {
+        // every lane its own i, one j for all (within a cluster for VCL)
+        lay = LANE_J_MAJOR;
+        ai = MDLJ_WAVE;
+    } else if (cfg->nbr_algo == MDLJ_NBR_VCL) {
+        lay = cfg->swap ? LANE_J_MAJOR : LANE_I_MAJOR;
+        ai = cfg->cluster_size;
+    } else {
+        ai = cfg->tile_i;
+    }
+    if (ai < 1 || ai > MDLJ_WAVE || MDLJ_WAVE % ai != 0) return MDLJ_ERR_ARG;
+    const LanePair p = lane_pair(lay, ai, MDLJ_WAVE, lane);
+    *layout = lay;
+    *i = p.i;
+    *j = p.j;
     return MDLJ_OK;
 }
 

@@ -52,7 +52,8 @@ __global__ __launch_bounds__(64) void k_lc_ipl(const PosT *__restrict__ rec,
     double bu = 0.0, bw = 0.0;
     __syncthreads();
     for (int i0 = ib; i0 < ie; i0 += MDLJ_WAVE) {
-        const int i = i0 + lane;
+        // every lane its own i, one j for all (VectorLength/1)
+        const int i = i0 + lane_pair(LANE_J_MAJOR, MDLJ_WAVE, MDLJ_WAVE, lane).i;
         const bool act = i < ie;
         const PosT pi = rec[act ? i : ib];
         Acc a;
@@ -133,7 +134,9 @@ __global__ __launch_bounds__(64) void k_lc_tile(const PosT *__restrict__ rec,
     }
     // local index of the cell's own first particle in the staged order
     const int own0 = seg_c[4] + (ib - seg_b[4]);
-    const int ii = lane / AJ, jl = lane % AJ;
+    // AI i's, AJ lanes each striding over the candidates, j fastest
+    const LanePair lp = lane_pair(LANE_I_MAJOR, AI, MDLJ_WAVE, lane);
+    const int ii = lp.i, jl = lp.j;
     double bu = 0.0, bw = 0.0;
     for (int i0 = ib; i0 < ie; i0 += AI) {
         const int i = i0 + ii;
@@ -282,7 +285,8 @@ __global__ __launch_bounds__(64) void k_lc_half(const PosT *__restrict__ rec,
     __syncthreads();
     double bu = 0.0, bw = 0.0;
     if constexpr (!SWAP) {
-        const int ii = lane / AJ, jl = lane % AJ;
+        const LanePair lp = lane_pair(LANE_I_MAJOR, AI, MDLJ_WAVE, lane);
+        const int ii = lp.i, jl = lp.j;
         for (int a0 = 0; a0 < nown; a0 += AI) {
             const int a = a0 + ii;
             const bool act = a < nown;

@@ -16,6 +16,7 @@
 
 #include "atomics.h"
 #include "internal.h"
+#include "lanemap.h"
 
 template <typename T>
 __device__ __forceinline__ T rcp_t(T x);

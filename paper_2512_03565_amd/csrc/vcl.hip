@@ -213,8 +213,12 @@ struct BoxL {
     double L[3];
 };
 
-// Cluster tile: M x (64/M) lanes; one wavefront per cluster I.
-template <typename T, bool E, bool MS, bool N3, int M>
+// Cluster tile: M x (64/M) lanes; one wavefront per cluster I.  JMAJOR =
+// false: lanes run over j fastest (the 2/(VL/2) fill widened: lane l takes
+// i = l / (64/M) and j-lane l % (64/M)); JMAJOR = true: over i fastest (the
+// (VL/2)/2 fill widened: i = l % M, j-lane l / M).  A j-lane b covers list
+// entry b / M of the step and member b % M of that entry's cluster.
+template <typename T, bool E, bool MS, bool N3, int M, bool JMAJOR>
 __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
                                                   const int32_t *__restrict__ list,
                                                   const int32_t *__restrict__ len, int64_t nclu,
@@ -232,8 +236,10 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
     const int64_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int64_t I = b * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
     const int lane = threadIdx.x & (MDLJ_WAVE - 1);
-    const int a = lane / AJ;             // i within the cluster
-    const int bj = lane % AJ;            // j lane
+    constexpr int LAYOUT = JMAJOR ? LANE_J_MAJOR : LANE_I_MAJOR;
+    const LanePair lp = lane_pair(LAYOUT, M, MDLJ_WAVE, lane);
+    const int a = lp.i;                  // i within the cluster
+    const int bj = lp.j;                 // j lane
     const int eo = bj / M;               // which list entry of the step
     const int m = bj % M;                // j within its cluster
     Acc acc;
@@ -272,9 +278,11 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
             lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x + sx[u], pj[u].y + sy[u], pj[u].z + sz[u], valid,
                           p, rc2, acc, fxp, fyp, fzp);
             if (N3) {
-                // -F on j summed over the M i-lanes that share it
+                // -F on j summed over the M i-lanes that share it (lanes
+                // AJ apart for j fastest, adjacent lanes for i fastest)
                 double gx = -fxp, gy = -fyp, gz = -fzp;
-                for (int o = AJ; o < MDLJ_WAVE; o <<= 1) {
+                const int o0 = JMAJOR ? 1 : AJ, o1 = JMAJOR ? M : MDLJ_WAVE;
+                for (int o = o0; o < o1; o <<= 1) {
                     gx += __shfl_xor(gx, o, MDLJ_WAVE);
                     gy += __shfl_xor(gy, o, MDLJ_WAVE);
                     gz += __shfl_xor(gz, o, MDLJ_WAVE);
@@ -288,9 +296,13 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
             }
         }
     }
-    acc.fx = seg_sum(acc.fx, AJ);
-    acc.fy = seg_sum(acc.fy, AJ);
-    acc.fz = seg_sum(acc.fz, AJ);
+    // F on i summed over its AJ j-lanes: adjacent lanes for j fastest,
+    // lanes M apart for i fastest
+    for (int o = JMAJOR ? M : 1; o < (JMAJOR ? MDLJ_WAVE : AJ); o <<= 1) {
+        acc.fx += __shfl_xor(acc.fx, o, MDLJ_WAVE);
+        acc.fy += __shfl_xor(acc.fy, o, MDLJ_WAVE);
+        acc.fz += __shfl_xor(acc.fz, o, MDLJ_WAVE);
+    }
     if (live && bj == 0) {
         if (N3) {
             atomicAdd(&fo.fx[islot], acc.fx);
@@ -390,7 +402,12 @@ int64_t launch_vcl_m(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &ta
     const int TB = 256;
     if (cfg.order == MDLJ_ORD_CLUSTER_TILE) {
         const int64_t nb = ceil_div(nclu, TB / MDLJ_WAVE);
-        k_vcl_tile<T, E, MS, N3, M><<<nb, TB, 0, s>>>(crec, list, len, nclu, cap, bl, tab, fo, remap);
+        if (cfg.swap)
+            k_vcl_tile<T, E, MS, N3, M, true><<<nb, TB, 0, s>>>(crec, list, len, nclu, cap, bl, tab,
+                                                               fo, remap);
+        else
+            k_vcl_tile<T, E, MS, N3, M, false><<<nb, TB, 0, s>>>(crec, list, len, nclu, cap, bl,
+                                                                tab, fo, remap);
         return nb * (TB / MDLJ_WAVE);
     }
     const int64_t nb = ceil_div(nclu * M, TB);

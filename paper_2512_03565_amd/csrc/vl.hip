@@ -694,7 +694,9 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     // compact index of the tile's first particle (cells of a tile are consecutive)
     const int64_t c0 = (int64_t)cx0 + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz);
     const int64_t t0 = ibase[c0];
-    const int l = lane % SEG;
+    // G i's per wavefront, SEG lanes each over the i's list (j fastest)
+    const LanePair lp = lane_pair(LANE_I_MAJOR, G, MDLJ_WAVE, lane);
+    const int l = lp.j;
     // list rows of the tile's particles (t0 onwards) through one buffer
     // resource; lane offsets in bytes
     const __amdgpu_buffer_rsrc_t lr = __builtin_amdgcn_make_buffer_rsrc(
@@ -707,7 +709,7 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     // lanes read the tile's first row and list length; what those reads
     // return is never used.
     int i0 = ib + wv * G;
-    int i = i0 + lane / SEG;
+    int i = i0 + lp.i;
     bool act = i < ie;
     int64_t t = t0 + (act ? i - ib : 0);
     // i's record: FP64 coordinates and species, or (fixed point) the words
@@ -800,7 +802,7 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     double bu = 0.0, bw = 0.0;
     for (bool first = true; i0 < ie; i0 += NW * G, first = false) {
         if (!first) {
-            i = i0 + lane / SEG;
+            i = i0 + lp.i;
             act = i < ie;
             t = t0 + (act ? i - ib : 0);
             load_i(act ? i : ib);
@@ -1008,8 +1010,9 @@ __global__ __launch_bounds__(256) void k_vl_wpi(const PosT *__restrict__ rec,
     const int64_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int lane = threadIdx.x & (MDLJ_WAVE - 1);
     const int64_t wave = b * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
-    const int64_t t = wave * G + lane / SEG;
-    const int l = lane % SEG;
+    const LanePair lp = lane_pair(LANE_I_MAJOR, G, MDLJ_WAVE, lane);
+    const int64_t t = wave * G + lp.i;
+    const int l = lp.j;
     Acc a;
     acc_zero(a);
     int32_t i = 0;

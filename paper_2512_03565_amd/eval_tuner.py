@@ -8,8 +8,12 @@ For every held-out scene of the sweep (scene index >= --first), on the GPU:
   * both the learned choice and the sweep's fastest configuration are timed
     again with --samples samples each (amortised step time, the tuner's own
     objective), and regret = t(learned) / t(fastest) - 1;
-  * the fixed one-order baseline (linked cells, i-per-lane) is timed the
-    same way;
+  * the fixed one-order baseline (linked cells, i-per-lane) and the best
+    single configuration of the training scenes (smallest geometric-mean
+    step-time ratio to the fastest over the sweep's training rows) are
+    timed the same way;
+  * the early-stopping search runs (visiting configurations in the
+    network's order) and its choice is timed the same way;
   * on every --full-every-th scene the full search is run as well, for the
     cost of tuning without the network.
 
@@ -42,7 +46,10 @@ def main(argv=None):
     from paper_2512_03565_amd import mdlj, scenes
     from paper_2512_03565_amd.train_tuner import load
 
+    from paper_2512_03565_amd.train_tuner import best_fixed
     F, T, meta, names = load(a.sweeps)
+    train_rows = [k for k in range(len(meta)) if meta[k, 0] < a.first]
+    kb, name_b, _ = best_fixed(T[train_rows], names)
     idx = [k for k in range(len(meta)) if meta[k, 0] >= a.first][: a.count]
     rows = []
     t0 = time.time()
@@ -72,6 +79,13 @@ def main(argv=None):
             us_l = timed(ci)
             us_b = us_l if best == ci else timed(best)
             us_f = timed(space.index("LC/i-per-lane/k1"))
+            us_s = timed(kb)
+            c0 = time.perf_counter()
+            early, _ = sysm.tune(mdlj.TUNE_EARLY_STOP, a.tune_samples)
+            t_early = time.perf_counter() - c0
+            taken_early = int(sysm.tune_taken().sum())
+            ei = space.index(mdlj.config_name(early))
+            us_e = us_l if ei == ci else (us_b if ei == best else timed(ei))
             t_full = None
             if q % a.full_every == 0:
                 c0 = time.perf_counter()
@@ -79,13 +93,17 @@ def main(argv=None):
                 t_full = time.perf_counter() - c0
         rows.append(dict(scene=sid, n=int(meta[k, 1]), chosen=space[ci], best=space[best],
                          confidence=conf, fallback=bool(fb1 > fb0), us_learned=us_l,
-                         us_best=us_b, us_fixed=us_f, tune_s_learned=t_learn,
+                         us_best=us_b, us_fixed=us_f, us_best_single=us_s,
+                         early=space[ei], us_early=us_e, tune_s_early=t_early,
+                         samples_early=taken_early, tune_s_learned=t_learn,
                          tune_s_full=t_full))
         if q % 20 == 0:
             print(f"[eval] {q}/{len(idx)} scene {sid} {space[ci]} vs {space[best]} "
                   f"ratio {us_l / us_b:.3f} elapsed {time.time() - t0:.0f}s", flush=True)
     r = np.array([x["us_learned"] / x["us_best"] for x in rows])
     fx = np.array([x["us_fixed"] / x["us_best"] for x in rows])
+    bs = np.array([x["us_best_single"] / x["us_best"] for x in rows])
+    re = np.array([x["us_early"] / x["us_best"] for x in rows])
     tl = np.array([x["tune_s_learned"] for x in rows])
     full = [x for x in rows if x["tune_s_full"] is not None]
     summary = {
@@ -99,6 +117,13 @@ def main(argv=None):
         "fallback_rate": float(np.mean([x["fallback"] for x in rows])),
         "same_as_best": float(np.mean([x["chosen"] == x["best"] for x in rows])),
         "fixed_over_best_geomean": float(np.exp(np.log(fx).mean())),
+        "best_single_config": name_b,
+        "best_single_over_best_geomean": float(np.exp(np.log(bs).mean())),
+        "learned_gain_over_best_single_geomean": float(np.exp(np.log(bs / r).mean())),
+        "early_stop_regret_geomean": float(np.exp(np.log(re).mean()) - 1),
+        "early_stop_within_5pct": float((re <= 1.05).mean()),
+        "tune_s_early_mean": float(np.mean([x["tune_s_early"] for x in rows])),
+        "samples_early_mean": float(np.mean([x["samples_early"] for x in rows])),
         "tune_s_learned_mean": float(tl.mean()),
         "tune_s_full_mean": float(np.mean([x["tune_s_full"] for x in full])) if full else None,
         "tune_s_learned_on_full_scenes": float(np.mean([x["tune_s_learned"] for x in full]))

@@ -125,6 +125,10 @@ _SIGS = {
     "mdlj_get_timing": [_ctxp, _d, _d, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "mdlj_get_timing_fused": [_ctxp, _d, C.POINTER(C.c_int64)],
     "mdlj_set_tune_metric": [_ctxp, C.c_int32],
+    "mdlj_lane_map": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                      C.POINTER(C.c_int32)],
+    "mdlj_config_lane_map": [C.POINTER(mdlj_config), C.c_int32, C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "mdlj_tune_power": [_ctxp, _d, C.c_int32, C.POINTER(C.c_int32)],
     "mdlj_gpu_energy": [_ctxp, _d, _d],
     "mdlj_tune_select_energy": [_d, _d, C.c_int32, _d, C.POINTER(C.c_int32)],
@@ -507,6 +511,31 @@ def tune_select_early(samples, order=None, warm_factor=2.0, margin=0.1):
                                      float(warm_factor), float(margin), vals.ctypes.data_as(_d),
                                      taken.ctypes.data_as(i32), C.byref(ch)))
     return vals, taken, ch.value
+
+
+def lane_map(layout, ai, width):
+    """(i offsets, j offsets) of the lanes of one step: layout 0 j fastest,
+    1 i fastest, ai i's in a vector of width lanes."""
+    i, j = C.c_int32(), C.c_int32()
+    out = []
+    for lane in range(width):
+        check(lib.mdlj_lane_map(int(layout), int(ai), int(width), lane, C.byref(i), C.byref(j)))
+        out.append((i.value, j.value))
+    return np.array(out, np.int32).T
+
+
+def config_lane_map(cfg):
+    """(layout, i offsets, j offsets) of the 64 lanes of one step of a
+    configuration's kernel."""
+    if not isinstance(cfg, mdlj_config):
+        cfg = mdlj_config(*cfg)
+    lay, i, j = C.c_int32(), C.c_int32(), C.c_int32()
+    out = []
+    for lane in range(64):
+        check(lib.mdlj_config_lane_map(C.byref(cfg), lane, C.byref(lay), C.byref(i), C.byref(j)))
+        out.append((i.value, j.value))
+    a = np.array(out, np.int32).T
+    return lay.value, a[0], a[1]
 
 
 def tune_select_energy(us, watts):

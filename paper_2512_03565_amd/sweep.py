@@ -7,6 +7,11 @@ run the exhaustive tuner, which times every valid configuration.  Writes an
 configuration does not apply), the configuration names and scene metadata.
 
     python -m paper_2512_03565_amd.sweep --start 0 --count 2000 --out sweep.npz
+
+With --configs NAME,NAME,... only those configurations are timed (each one
+set and measured like the full search measures it); the other columns are
++inf.  Tables of the same scenes are merged column by column by
+``train_tuner.load``.
 """
 import argparse
 import sys
@@ -15,7 +20,7 @@ import time
 import numpy as np
 
 
-def run(start, count, samples, out, n_max):
+def run(start, count, samples, out, n_max, only=None):
     import torch  # noqa: F401  (one HIP runtime: torch's)
     from paper_2512_03565_amd import mdlj, scenes
     feats, tables, meta = [], [], []
@@ -30,8 +35,19 @@ def run(start, count, samples, out, n_max):
                 if names is None:
                     names = [mdlj.config_name(c) for c in sysm.configs()]
                 f = sysm.features()
-                sysm.tune(mdlj.TUNE_EXHAUSTIVE, samples)
-                tab = sysm.tune_results()
+                if only:
+                    cfgs = sysm.configs()
+                    tab = np.full(len(cfgs), np.inf)
+                    for name in only:
+                        k = names.index(name)
+                        sysm.set_config(cfgs[k])
+                        try:
+                            tab[k] = sysm.tune(mdlj.TUNE_FIXED, samples)[1]
+                        except mdlj.MdljError:
+                            pass  # not valid for this scene
+                else:
+                    sysm.tune(mdlj.TUNE_EXHAUSTIVE, samples)
+                    tab = sysm.tune_results()
         except mdlj.MdljError as e:
             print(f"scene {k}: skipped ({e})", flush=True)
             continue
@@ -54,8 +70,10 @@ def main(argv=None):
     ap.add_argument("--samples", type=int, default=4)
     ap.add_argument("--n-max", type=float, default=4e6)
     ap.add_argument("--out", default="sweep.npz")
+    ap.add_argument("--configs", default=None, help="comma-separated configuration names")
     a = ap.parse_args(argv)
-    run(a.start, a.count, a.samples, a.out, a.n_max)
+    run(a.start, a.count, a.samples, a.out, a.n_max,
+        a.configs.split(",") if a.configs else None)
     return 0
 
 

@@ -23,20 +23,41 @@ import numpy as np
 
 
 def load(paths):
-    F, T, M = [], [], []
-    names = None
-    for p in paths:
-        d = np.load(p, allow_pickle=False)
-        F.append(d["features"])
-        T.append(d["table_us"])
-        M.append(d["meta"])
-        nm = list(d["names"])
-        if names is not None and nm != names:
-            raise ValueError("sweeps were taken with different configuration spaces")
-        names = nm
-    meta = np.concatenate(M)
-    order = np.argsort(meta[:, 0])  # by scene index
-    return (np.concatenate(F)[order], np.concatenate(T)[order], meta[order], names)
+    """Features, tables, metadata and configuration names of the sweeps,
+    one row per scene (by scene index).  Columns are matched by
+    configuration name: the longest name list is the space; a sweep of the
+    same scenes that timed other configurations fills their columns (a
+    value already present is kept)."""
+    data = [np.load(p, allow_pickle=False) for p in paths]
+    names = max((list(d["names"]) for d in data), key=len)
+    rows = {}
+    for d in data:
+        cols = [names.index(nm) for nm in list(d["names"])]
+        for f, t, mt in zip(d["features"], d["table_us"], d["meta"]):
+            sid = int(mt[0])
+            if sid not in rows:
+                rows[sid] = [f, np.full(len(names), np.inf), mt]
+            row = rows[sid][1]
+            for c, v in zip(cols, t):
+                if not np.isfinite(row[c]) and np.isfinite(v):
+                    row[c] = v
+    sids = sorted(rows)
+    F = np.array([rows[s][0] for s in sids], np.float32)
+    T = np.array([rows[s][1] for s in sids])
+    M = np.array([rows[s][2] for s in sids], np.float64)
+    return F, T, M, names
+
+
+def best_fixed(table, names):
+    """The single configuration with the smallest geometric-mean
+    t(config) / t(fastest) over the rows of table (configurations that cannot
+    run on some scene are left out): what one fixed choice gets."""
+    best = np.min(table, axis=1)
+    ok = np.isfinite(table).all(0)
+    g = np.full(table.shape[1], np.inf)
+    g[ok] = np.exp(np.log(table[:, ok] / best[:, None]).mean(0))
+    k = int(np.argmin(g))
+    return k, names[k], float(g[k])
 
 
 def evaluate(probs, table, threshold):
@@ -93,12 +114,15 @@ def main(argv=None):
         p_tr = sysm.mlp_predict(Ftr)
         p_te = sysm.mlp_predict(F[ntr:])
     fixed = names.index("LC/i-per-lane/k1")
+    kb, name_b, _ = best_fixed(T[:ntr], names)
     res = {
         "scenes": int(len(F)), "train": int(ntr), "test": int(len(F) - ntr),
         "configs": names, "final_loss": loss, "threshold": a.threshold,
         "train_eval": evaluate(p_tr, T[:ntr], a.threshold),
         "test_eval": evaluate(p_te, T[ntr:], a.threshold),
         "test_fixed_geomean_ratio": float(np.exp(np.log(T[ntr:, fixed] / T[ntr:].min(1)).mean())),
+        "best_single_config": name_b,
+        "test_best_single_geomean_ratio": float(np.exp(np.log(T[ntr:, kb] / T[ntr:].min(1)).mean())),
         "label_histogram": {names[k]: int(c) for k, c in zip(*np.unique(y, return_counts=True))},
     }
     print(json.dumps(res["test_eval"]), flush=True)

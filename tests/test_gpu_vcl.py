@@ -24,6 +24,7 @@ def vcl_configs(m):
         for n3 in (0, 1):
             out.append((m.NBR_VCL, m.ORD_I_PER_LANE, 0, 0, M, n3))
             out.append((m.NBR_VCL, m.ORD_CLUSTER_TILE, M, 64 // M, M, n3))
+            out.append((m.NBR_VCL, m.ORD_CLUSTER_TILE, M, 64 // M, M, n3, 0, 1))
     return out
 
 
