@@ -170,6 +170,20 @@ mdlj_status mdlj_set_cutoff(mdlj_ctx *ctx, double rc);
  * and are also rebuilt early once any particle has moved more than skin/2. */
 mdlj_status mdlj_set_skin(mdlj_ctx *ctx, double skin, int32_t rebuild_every);
 
+/* Pruned inner list of the staged Verlet-list kernels: on (1, default) or
+ * off (0).  The Verlet lists of section 2.1.1 hold the pairs within
+ * rc + skin; the list build also keeps, per particle and in list order, the
+ * entries closer than rc + 2 skin / 3, and force evaluations read that
+ * shorter list while no particle has moved more than skin / 3 since the
+ * build (the skin/2 argument with the smaller skin), then the full one until
+ * the next build.  Forces agree with the unpruned ones up to the order of
+ * the FP64 sums.  Only tiled builds of the staged kernels' lists write it.
+ * Changing the setting marks the lists for rebuilding.
+ * mdlj_pruning_state (synchronises the stream): 0 no inner list for the
+ * current lists, 1 valid, 2 no longer valid. */
+mdlj_status mdlj_set_pruning(mdlj_ctx *ctx, int32_t on);
+mdlj_status mdlj_pruning_state(mdlj_ctx *ctx, int32_t *state);
+
 /* Parameters of species s for the Lennard-Jones 12-6 pair law (section 4.1
  * names the potential, section 2.1 Eq. 1 sums it over pairs): epsilon > 0,
  * sigma > 0.  Unlike species mix by the Lorentz-Berthelot rule (the paper

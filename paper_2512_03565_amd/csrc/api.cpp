@@ -207,6 +207,7 @@ static void invalidate(mdlj_ctx *ctx)
 {
     ctx->built = false;
     ctx->forces_valid = false;
+    ctx->inner = 0;
 }
 
 // ------------------------------------------------------------------ build
@@ -226,6 +227,7 @@ static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
     // a build that fails part-way (a buffer that cannot grow) leaves nothing
     // marked as current
     ctx->built = false;
+    ctx->inner = 0;
     STCHK(check_geometry(ctx, c));
     if (c.nbr_algo == MDLJ_NBR_VCL) {
         STCHK(vcl_build(ctx, c));
@@ -602,7 +604,7 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
                       &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo,    &ctx->b_hstart,
                       &ctx->b_vsort,   &ctx->b_vsort2,  &ctx->b_xrsort,  &ctx->b_tinv,
                       &ctx->b_sorted2, &ctx->b_fxrec, &ctx->b_fxrec2, &ctx->b_fxspec,
-                      &ctx->b_tunev};
+                      &ctx->b_tunev,   &ctx->b_nbr_in,  &ctx->b_nlen_in};
     for (DevBuf *b : bufs) free_buf(*b);
     delete ctx;
     return MDLJ_OK;
@@ -638,6 +640,30 @@ mdlj_status mdlj_set_skin(mdlj_ctx *ctx, double skin, int32_t rebuild_every)
     ctx->skin = skin;
     ctx->rebuild_every = rebuild_every;
     invalidate(ctx);
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_set_pruning(mdlj_ctx *ctx, int32_t on)
+{
+    if (!ctx) return MDLJ_ERR_ARG;
+    if (on != 0 && on != 1) return set_err(ctx, MDLJ_ERR_ARG, "pruning is 0 or 1");
+    ctx->prune = on != 0;
+    ctx->inner = 0;
+    invalidate(ctx);
+    return MDLJ_OK;
+}
+
+mdlj_status mdlj_pruning_state(mdlj_ctx *ctx, int32_t *state)
+{
+    if (!ctx || !state) return MDLJ_ERR_ARG;
+    *state = 0;
+    if (ctx->inner != 1) return MDLJ_OK;
+    int32_t w = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&w, (const int32_t *)ctx->b_flags.p + FLAG_INNER_STATE +
+                                       ctx->inner_par,
+                               sizeof w, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *state = w != 0 ? 2 : 1;
     return MDLJ_OK;
 }
 

@@ -98,7 +98,29 @@ struct KickArgs {
     // fx_s) to a second word array; null otherwise
     FxWords *fxr_out;
     double fx_c[3], fx_s;
+    // the pruned inner list's validity word for the next launch: set to 1
+    // when the current word is set or a particle moved more than
+    // sqrt(thr_in2) since the list build (null: no inner list)
+    int32_t *in_bad;
+    double thr_in2;
 };
+
+// The pruned inner Verlet list of the staged kernels, written by the list
+// build: the entries of each row whose pair was closer than r_in at the
+// build, in list order (same row layout and capacity as the list, rows
+// padded to 8 with the padding entry).  It holds every pair inside the
+// cutoff while no particle has moved more than (r_in - rc) / 2 since the
+// build.  Two validity words take turns: a launch reads one (cur) and
+// anything that moves particles writes the other, so that no launch reads a
+// word it also writes; both are cleared at the build and only ever set
+// afterwards.  A force launch reads the inner rows when *cur == 0.
+struct InnerList {
+    const uint16_t *nbr;
+    const int32_t *len;
+    const int32_t *cur;  // null: no inner list
+};
+// first of the two validity words in the flag block
+constexpr int FLAG_INNER_STATE = 48;
 
 // Device buffers that grow on demand.
 struct DevBuf {
@@ -174,7 +196,8 @@ struct mdlj_ctx {
     DevBuf b_cell_of, b_rank, b_count, b_start, b_slot_of, b_sorted, b_scan_part, b_fsorted,
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
         b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart, b_vsort,
-        b_vsort2, b_xrsort, b_tinv, b_sorted2, b_fxrec, b_fxrec2, b_fxspec, b_tunev;
+        b_vsort2, b_xrsort, b_tinv, b_sorted2, b_fxrec, b_fxrec2, b_fxspec, b_tunev, b_nbr_in,
+        b_nlen_in;
     int64_t nhalo = 0;            // entries of b_halo
     int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 
@@ -232,6 +255,12 @@ struct mdlj_ctx {
     // do not keep them clear it)
     bool fx_valid = false;
     double fx_c[3] = {0, 0, 0}, fx_s = 0.0;
+    // pruned inner list of the staged Verlet-list kernels (b_nbr_in,
+    // b_nlen_in; validity words FLAG_INNER_STATE + 0/1): prune enables it;
+    // inner: 1 when the list build wrote one for the current lists;
+    // inner_par: the word launches read
+    bool prune = true;
+    int inner = 0, inner_par = 0;
     // allocation-free calls (mdlj_compute_forces_noalloc): no device buffer,
     // pinned word or timing event may be created or grown (ensure() and the
     // others refuse), and the energy/virial partials of the force kernels go
@@ -265,6 +294,14 @@ mdlj_status partial_buffer(mdlj_ctx *ctx, int64_t nvals, double **out);
         mdlj_status _s = (call);          \
         if (_s != MDLJ_OK) return _s;     \
     } while (0)
+
+// --- pruned inner list (vl.hip) -------------------------------------------
+// Validity words of the inner list for a kernel that moves particles:
+// *cur the one launches read now, *next the one it writes (both null when
+// there is no inner list); thr_in2 the squared displacement bound.  The
+// caller calls inner_flip after queueing that kernel.
+void inner_words(mdlj_ctx *ctx, const int32_t **cur, int32_t **next, double *thr_in2);
+void inner_flip(mdlj_ctx *ctx);
 
 // --- binning (bin.hip) ----------------------------------------------------
 // Bins the caller-order positions into g (wrapping them in place), writes

@@ -119,14 +119,25 @@ struct Cycles {
 };
 
 // Runs `measure_body` with the context's own kernel timing switched off
-// (tuning steps are not the caller's) and restores it.
+// (tuning steps are not the caller's) and restores it.  The pruned inner
+// list is off too: the measuring steps do not move the particles, so it
+// would stay valid through every step of a cycle, where in a run it lasts
+// only part of each list period.  Configurations are compared by their
+// steps on the full lists; afterwards the lists are marked for a rebuild
+// that writes the inner list again.
 template <typename F>
 mdlj_status untimed(mdlj_ctx *ctx, F &&body)
 {
-    const bool timing = ctx->timing;
+    const bool timing = ctx->timing, prune = ctx->prune;
     ctx->timing = false;
+    ctx->prune = false;
     const mdlj_status st = body();
     ctx->timing = timing;
+    ctx->prune = prune;
+    if (prune) {
+        ctx->built = false;
+        ctx->inner = 0;
+    }
     return st;
 }
 

@@ -24,6 +24,10 @@
 
 namespace {
 
+// Pruned inner list: r_in = rc + PRUNE_FRACTION skin; it stays valid while
+// no particle has moved more than PRUNE_FRACTION skin / 2 since the build
+constexpr double PRUNE_FRACTION = 2.0 / 3.0;
+
 // candidates per trip of the force loops
 constexpr int UNROLL = 4;
 
@@ -237,14 +241,19 @@ static_assert(9 * (STAGE_K + 3) <= 2 * MDLJ_WAVE, "tile too wide for the set-up"
 static_assert(2 * MDLJ_WAVE + 9 * (STAGE_K + 2) <= BUILD_TB, "tile too wide for the set-up");
 static_assert(2 * STAGE_K <= 16, "tile too wide for the set-up");
 
-template <bool LOCAL, bool HALF, bool ELL>
+// INNER (local lists only): the pruned inner list too, the entries closer
+// than sqrt(rin2) in list order, into rows of in_nbr (same layout) and
+// lengths in_len.
+template <bool LOCAL, bool HALF, bool ELL, bool INNER>
 __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     const PosT *__restrict__ rec, const int32_t *__restrict__ start,
     const int32_t *__restrict__ hstart, const int32_t *__restrict__ ibase, Grid g, int tiles_x,
     double rl2, int trim, int cmax, int ccand, int64_t n, int32_t cap, int32_t pad,
     void *__restrict__ nbr_out, int32_t *__restrict__ len, int32_t *__restrict__ maxlen,
-    int32_t *__restrict__ maxnb, int32_t *__restrict__ maxnc, int remap)
+    int32_t *__restrict__ maxnb, int32_t *__restrict__ maxnc, int remap,
+    uint16_t *__restrict__ in_nbr, int32_t *__restrict__ in_len, double rin2)
 {
+    static_assert(!INNER || (LOCAL && !HALF && !ELL), "inner lists are local full lists");
     constexpr int NW = BUILD_TB / MDLJ_WAVE;
     constexpr int RC = STAGE_K + 3;  // cell starts per row: STAGE_K + 2 cells and the end
     // staged record: x, y, z (a stride of 6 dwords keeps 64-bit LDS reads of
@@ -429,7 +438,8 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
             const int64_t t = t0 + (i - ib);
             uint16_t *row16 = (uint16_t *)nbr_out + t * cap;
             int32_t *row32 = (int32_t *)nbr_out + (ELL ? t : t * cap);
-            uint32_t cnt = 0;
+            uint16_t *irow = INNER ? in_nbr + t * cap : nullptr;
+            uint32_t cnt = 0, icnt = 0;
             // two trips of 64 candidates in flight; the list is padded to
             // whole trips with the padding record, which no test passes
             for (int p0 = pb; p0 < pe; p0 += CAND_TRIP) {
@@ -444,8 +454,25 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
                 // itself, wraps to the largest value): a single compare
                 // feeds the ballot directly
                 const uint64_t lim = (uint64_t)__double_as_longlong(rl2) - 1;
-                bool ha = (uint64_t)__double_as_longlong(ax * ax + ay * ay + az * az) - 1 < lim;
-                bool hb = (uint64_t)__double_as_longlong(bx * bx + by * by + bz * bz) - 1 < lim;
+                const uint64_t ra = (uint64_t)__double_as_longlong(ax * ax + ay * ay + az * az) - 1;
+                const uint64_t rb = (uint64_t)__double_as_longlong(bx * bx + by * by + bz * bz) - 1;
+                bool ha = ra < lim;
+                bool hb = rb < lim;
+                if constexpr (INNER) {
+                    // the same order over the candidates, the smaller radius
+                    const uint64_t lin = (uint64_t)__double_as_longlong(rin2) - 1;
+                    const bool ia = ra < lin, ib = rb < lin;
+                    const uint64_t ma = __builtin_amdgcn_ballot_w64(ia);
+                    const uint64_t mb = __builtin_amdgcn_ballot_w64(ib);
+                    const uint32_t na = (uint32_t)__builtin_popcountll(ma);
+                    const uint32_t qa = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, icnt));
+                    const uint32_t qb = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, icnt + na));
+                    if (ia) *(uint16_t *)((char *)irow + 2u * qa) = (uint16_t)ka;
+                    if (ib) *(uint16_t *)((char *)irow + 2u * qb) = (uint16_t)kb;
+                    icnt += na + (uint32_t)__builtin_popcountll(mb);
+                }
                 if (HALF) {
                     ha &= sorig[ka] > oi;
                     hb &= sorig[kb] > oi;
@@ -483,6 +510,12 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
                     row32[ELL ? (int64_t)q * n : q] = pad;
             }
             if (lane == 0) len[t] = (int32_t)cnt;
+            if constexpr (INNER) {
+                const int32_t ie8 = min((int32_t)((icnt + 7) & ~7u), cap);
+                const int32_t qi = (int32_t)icnt + lane;
+                if (qi < ie8) irow[qi] = (uint16_t)C;
+                if (lane == 0) in_len[t] = (int32_t)icnt;
+            }
             wmax = max(wmax, (int32_t)cnt);
         }
     }
@@ -645,13 +678,26 @@ template <typename T, bool E, bool MS, int G, int V, bool KD>
 __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
                                             const int32_t *__restrict__ start,
                                             const int32_t *__restrict__ ibase, const Grid &g,
-                                            int tiles_x, const uint16_t *__restrict__ nbr,
-                                            const int32_t *__restrict__ len, int32_t cap,
+                                            int tiles_x, const uint16_t *__restrict__ nbr_full,
+                                            const int32_t *__restrict__ len_full, int32_t cap,
                                             int64_t n, int cmax, const LJTable<T> &tab,
                                             const ForceOut &fo, int remap, double fxs,
                                             const FxWords *__restrict__ fxr,
-                                            const int32_t *__restrict__ fxspec, const KickArgs &ka)
+                                            const int32_t *__restrict__ fxspec, const KickArgs &ka,
+                                            const InnerList &il)
 {
+    // the list this launch reads: the pruned inner rows while they hold every
+    // pair inside the cutoff (a uniform decision, from a word that earlier
+    // launches wrote), else the full rows
+    bool use_in = false, in_bad0 = false;
+    if (il.cur) {
+        in_bad0 = __builtin_amdgcn_readfirstlane(*il.cur) != 0;
+        use_in = !in_bad0;
+    }
+    // fused step: a word already set stays set in the next one
+    if (KD && in_bad0 && ka.in_bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(ka.in_bad, 1);
+    const uint16_t *__restrict__ nbr = use_in ? il.nbr : nbr_full;
+    const int32_t *__restrict__ len = use_in ? il.len : len_full;
     // FP32 pair law: fixed-point staged records; fxs is their scale and tab
     // holds sig^2 fxs^2, 24 eps fxs and rc^2 fxs^2, so that every pair
     // quantity comes out in its own units.  FP64 law: FP64 coordinates.
@@ -850,9 +896,10 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
             }
         };
         // two trips in flight.  Both reloads are unconditional, so every
-        // path through the loop issues the same loads in the same order and
-        // each wait covers only the load its trip needs (a load inside the
-        // branch would make the loop head wait for all of them).
+        // path through the loop issues the same loads in the same order
+        // and each wait covers only the load its trip needs (a load
+        // inside the branch would make the loop head wait for all of
+        // them).
         for (int32_t k0 = V * l; k0 < L; k0 += 2 * KS, vo += 4 * KS) {
             trip(wa);
             wa = list_words<V>(lr, vo + 4 * KS);
@@ -872,7 +919,13 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
                                         kv, kr, species_i());
             if (act && l == 3) ((double *)(ka.rec_out + i))[3] = kx;
             const double dy = __shfl_down(d, 1, SEG), dz = __shfl_down(d, 2, SEG);
-            if (act && l == 0 && !(d * d + dy * dy + dz * dz <= ka.thr2)) atomicOr(ka.flag, 1);
+            const double d2 = d * d + dy * dy + dz * dz;
+            if (act && l == 0 && !(d2 <= ka.thr2)) atomicOr(ka.flag, 1);
+            // the inner list's bound, once per wavefront until it is crossed
+            if (ka.in_bad && !in_bad0) {
+                const uint64_t m = __builtin_amdgcn_ballot_w64(act && l == 0 && !(d2 <= ka.thr_in2));
+                if (m != 0 && lane == 0) atomicOr(ka.in_bad, 1);
+            }
         } else if (act && l == 0) {
             fo.fx[i] = a.fx;
             fo.fy[i] = a.fy;
@@ -909,13 +962,13 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
         const int32_t *__restrict__ ibase, Grid g, int tiles_x, const uint16_t *__restrict__ nbr, \
         const int32_t *__restrict__ len, int32_t cap, int64_t n, int cmax, LJTable<T> tab,      \
         ForceOut fo, int remap, double fxs, const FxWords *__restrict__ fxr,                     \
-        const int32_t *__restrict__ fxspec, KickArgs ka
+        const int32_t *__restrict__ fxspec, KickArgs ka, InnerList il
 
 template <typename T, bool E, bool MS, int G, int V, bool KD>
 __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(VL_LDS_PARAMS)
 {
     vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, len, cap, n, cmax, tab, fo,
-                                    remap, fxs, fxr, fxspec, ka);
+                                    remap, fxs, fxr, fxspec, ka, il);
 }
 
 // The same, held to 64 registers so that eight wavefronts share a SIMD:
@@ -927,7 +980,7 @@ __global__ __launch_bounds__(VL_LDS_TB) __attribute__((amdgpu_waves_per_eu(8, 8)
 k_vl_lds_w8(VL_LDS_PARAMS)
 {
     vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, len, cap, n, cmax, tab, fo,
-                                    remap, fxs, fxr, fxspec, ka);
+                                    remap, fxs, fxr, fxspec, ka, il);
 }
 #undef VL_LDS_PARAMS
 
@@ -1102,6 +1155,7 @@ static mdlj_status fx_words(mdlj_ctx *ctx, double *scale)
     return MDLJ_OK;
 }
 
+
 template <typename T, bool E, bool MS, bool N3>
 int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, ForceOut &fo,
                   int remap, const KickArgs *kdp)
@@ -1155,14 +1209,27 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
             tx.rc2d = tab.rc2d * fxs * fxs;
             tx.rc2 = (T)tx.rc2d;
         }
+        const int key = cfg.tile_i * 100 + cfg.tile_j;
+        if (key != 802 && key != 804 && key != 1602 && key != 1604 && key != 408) return -1;
         const int tiles_x = (int)ceil_div(g.n[0], STAGE_K);
         const int64_t nbt = (int64_t)tiles_x * g.n[1] * g.n[2];
         const int32_t *ibase = (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1;
         const uint16_t *nbr16 = (const uint16_t *)ctx->b_nbr.p;
         const int32_t *start = (const int32_t *)ctx->b_start.p;
-        const KickArgs none = {};
         // the fused integrator step only with forces alone (no energies)
         const bool kd = kdp != nullptr && !E;
+        // the pruned inner list, written by the list build, while valid
+        InnerList il = {};
+        if (ctx->inner == 1) {
+            il.nbr = (uint16_t *)ctx->b_nbr_in.p;
+            il.len = (int32_t *)ctx->b_nlen_in.p;
+            il.cur = (const int32_t *)ctx->b_flags.p + FLAG_INNER_STATE + ctx->inner_par;
+        }
+        if (kd) {
+            const int32_t *cur = nullptr;
+            inner_words(ctx, &cur, &kk.in_bad, &kk.thr_in2);
+        }
+        const KickArgs none = {};
 #define VL_LDS(GG, VV)                                                                          \
     do {                                                                                        \
         bool done = false;                                                                      \
@@ -1170,7 +1237,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
             if (kd) {                                                                           \
                 k_vl_lds_w8<T, false, MS, GG, VV, true><<<nbt, VL_LDS_TB, lds, s>>>(            \
                     rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, \
-                    fxr, fxspec, kk);                                                           \
+                    fxr, fxspec, kk, il);                                                       \
                 done = true;                                                                    \
             }                                                                                   \
         }                                                                                       \
@@ -1178,13 +1245,12 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         if (kd)                                                                                 \
             k_vl_lds<T, false, MS, GG, VV, true><<<nbt, VL_LDS_TB, lds, s>>>(                   \
                 rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr,   \
-                fxspec, kk);                                                                    \
+                fxspec, kk, il);                                                                \
         else                                                                                    \
             k_vl_lds<T, E, MS, GG, VV, false><<<nbt, VL_LDS_TB, lds, s>>>(                      \
                 rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr,   \
-                fxspec, none);                                                                  \
+                fxspec, none, il);                                                              \
     } while (0)
-        const int key = cfg.tile_i * 100 + cfg.tile_j;
         switch (key) {
         case 802: VL_LDS(8, 2); break;
         case 804: VL_LDS(8, 4); break;
@@ -1194,6 +1260,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         default: return -1;
         }
 #undef VL_LDS
+        if (kd) inner_flip(ctx);
         ctx->kd_done = kd;
         ctx->kd_fx = kd && FX;
         return nbt;
@@ -1265,7 +1332,7 @@ size_t build_tile_lds(bool local, bool half, int cmax, int ccand)
 }
 
 mdlj_status launch_build_tile(mdlj_ctx *ctx, bool local, bool half, bool ell, double rl2,
-                              bool trim, int cmax, int ccand, int32_t cap)
+                              bool trim, int cmax, int ccand, int32_t cap, bool inner, double rin2)
 {
     const Grid &g = ctx->grid;
     const int tiles_x = (int)ceil_div(g.n[0], STAGE_K);
@@ -1283,13 +1350,20 @@ mdlj_status launch_build_tile(mdlj_ctx *ctx, bool local, bool half, bool ell, do
     const int32_t pad = (int32_t)ctx->n_ext;
     const int64_t n = ctx->n;
     hipStream_t s = ctx->stream;
+    uint16_t *in_nbr = inner ? (uint16_t *)ctx->b_nbr_in.p : nullptr;
+    int32_t *in_len = inner ? (int32_t *)ctx->b_nlen_in.p : nullptr;
 #define VL_BT(L, H, E)                                                                          \
-    k_vl_build_tile<L, H, E><<<nbt, BUILD_TB, lds, s>>>(rec, start, hstart, ibase, g, tiles_x,   \
-                                                        rl2, trim ? 1 : 0, cmax, ccand, n, cap, \
-                                                        pad, nbr, len, maxlen, maxnb, maxnc, 1)
+    k_vl_build_tile<L, H, E, false><<<nbt, BUILD_TB, lds, s>>>(                                 \
+        rec, start, hstart, ibase, g, tiles_x, rl2, trim ? 1 : 0, cmax, ccand, n, cap, pad, nbr, \
+        len, maxlen, maxnb, maxnc, 1, nullptr, nullptr, 0.0)
     if (local) {
         if (half || ell) return set_err(ctx, MDLJ_ERR_ARG, "local lists are full row-major lists");
-        VL_BT(true, false, false);
+        if (inner)
+            k_vl_build_tile<true, false, false, true><<<nbt, BUILD_TB, lds, s>>>(
+                rec, start, hstart, ibase, g, tiles_x, rl2, trim ? 1 : 0, cmax, ccand, n, cap, pad,
+                nbr, len, maxlen, maxnb, maxnc, 1, in_nbr, in_len, rin2);
+        else
+            VL_BT(true, false, false);
     } else if (ell) {
         if (half)
             VL_BT(false, true, true);
@@ -1395,6 +1469,24 @@ mdlj_status vl_list_entries(mdlj_ctx *ctx, int64_t *entries)
     return MDLJ_OK;
 }
 
+void inner_words(mdlj_ctx *ctx, const int32_t **cur, int32_t **next, double *thr_in2)
+{
+    *cur = nullptr;
+    *next = nullptr;
+    *thr_in2 = 0.0;
+    if (ctx->inner != 1) return;
+    int32_t *w = (int32_t *)ctx->b_flags.p + FLAG_INNER_STATE;
+    *cur = w + ctx->inner_par;
+    *next = w + (ctx->inner_par ^ 1);
+    const double h = 0.5 * PRUNE_FRACTION * ctx->skin;
+    *thr_in2 = h * h;
+}
+
+void inner_flip(mdlj_ctx *ctx)
+{
+    if (ctx->inner == 1) ctx->inner_par ^= 1;
+}
+
 mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
 {
     const Grid &g = ctx->grid;
@@ -1458,9 +1550,22 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         const int64_t sk = rowmajor ? 1 : n;
         const int64_t st = rowmajor ? cap : 1;
         const bool tiled = tile_ok;
+        // the pruned inner list, written by the tiled build of the staged
+        // kernels' lists (an allocation-free call goes without it rather
+        // than grow its buffers)
+        bool inner = false;
+        if (tiled && local && !cfg.newton3 && ctx->prune && ctx->skin > 0.0) {
+            const size_t ib = esize * (size_t)(n * cap + slack), lb = sizeof(int32_t) * (size_t)n;
+            if (!ctx->no_alloc || (ctx->b_nbr_in.bytes >= ib && ctx->b_nlen_in.bytes >= lb)) {
+                STCHK(ensure(ctx, ctx->b_nbr_in, ib));
+                STCHK(ensure(ctx, ctx->b_nlen_in, lb));
+                inner = true;
+            }
+        }
+        const double rin = ctx->rc + PRUNE_FRACTION * ctx->skin;
         if (tiled) {
             STCHK(launch_build_tile(ctx, local, cfg.newton3 != 0, !rowmajor, rl * rl, trim, cmax,
-                                    ccand, (int32_t)cap));
+                                    ccand, (int32_t)cap, inner, rin * rin));
         } else if (local) {
             k_vl_build_local<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
                 (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
@@ -1506,6 +1611,12 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
             return set_err(ctx, MDLJ_ERR_ARG, "neighbourhood too large for 16-bit local lists");
         if (hmax[0] <= cap) {
             ctx->nbr_cap = cap;
+            if (inner) {
+                int32_t *w = (int32_t *)ctx->b_flags.p + FLAG_INNER_STATE;
+                HIPCHK(ctx, hipMemsetAsync(w, 0, 2 * sizeof(int32_t), ctx->stream));
+                ctx->inner = 1;
+                ctx->inner_par = 0;
+            }
             return MDLJ_OK;
         }
         cap = ((int64_t)(hmax[0] * 1.1) + 8 + 7) & ~(int64_t)7;

@@ -84,6 +84,8 @@ _SIGS = {
     "mdlj_set_skin": [_ctxp, C.c_double, C.c_int32],
     "mdlj_set_species": [_ctxp, C.c_int32, C.c_double, C.c_double],
     "mdlj_set_energy_shift": [_ctxp, C.c_int32],
+    "mdlj_set_pruning": [_ctxp, C.c_int32],
+    "mdlj_pruning_state": [_ctxp, C.POINTER(C.c_int32)],
     "mdlj_set_precision": [_ctxp, C.c_int32],
     "mdlj_set_positions": [_ctxp, _vp, _vp, _vp, C.c_int32],
     "mdlj_get_positions": [_ctxp, _vp, _vp, _vp, C.c_int32],
@@ -369,6 +371,15 @@ class System:
         buf = (C.c_double * 256)()
         check(lib.mdlj_tune_results(self.ctx, buf, 256, C.byref(n)), self.ctx)
         return np.array(buf[: n.value])
+
+    def set_pruning(self, on):
+        check(lib.mdlj_set_pruning(self.ctx, int(bool(on))), self.ctx)
+
+    def pruning_state(self):
+        """0 no inner list, 1 pending, 2 written and valid, 3 no longer valid."""
+        v = C.c_int32()
+        check(lib.mdlj_pruning_state(self.ctx, C.byref(v)), self.ctx)
+        return v.value
 
     def set_tune_metric(self, metric):
         check(lib.mdlj_set_tune_metric(self.ctx, int(metric)), self.ctx)
