@@ -59,8 +59,8 @@ def parse():
                     help="run one mode only: fixed|exhaustive|learned|early_stop|fp64")
     ap.add_argument("--config", default=None,
                     help="run this configuration (by name) without tuning, e.g. for profiling")
-    ap.add_argument("--no-prune", action="store_true",
-                    help="switch the pruned inner Verlet list off (for comparison)")
+    ap.add_argument("--prune", action="store_true",
+                    help="switch the pruned inner Verlet list on (for comparison)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="afterwards, copy a MIB-MiB device buffer 5 times (a plain copy of "
                          "known size, to scale hardware byte counters)")
@@ -235,8 +235,8 @@ def main():
     pos_d = torch.tensor(s["pos"], dtype=torch.float64, device="cuda")
     sysm = mdlj.System(pos_d, s["box"], s["rc"], skin=s["skin"], rebuild_every=s["rebuild_every"],
                        precision=mdlj.PREC_F32PAIR_F64ACC, stream=stream)
-    if args.no_prune:
-        sysm.set_pruning(False)
+    if args.prune:
+        sysm.set_pruning(True)
     pairs = sysm.count_pairs()
     results = {}
     modes = ["fixed", "exhaustive", "learned", "early_stop", "fp64"]
@@ -328,7 +328,7 @@ def main():
             "useful_pairs": pairs,
             "precision": "FP32 pair arithmetic, FP64 accumulation",
             "chosen": head["config"],
-            "pruned_inner_list": not args.no_prune,
+            "pruned_inner_list": bool(args.prune),
         },
         "modes": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in results.items()},

@@ -170,8 +170,8 @@ mdlj_status mdlj_set_cutoff(mdlj_ctx *ctx, double rc);
  * and are also rebuilt early once any particle has moved more than skin/2. */
 mdlj_status mdlj_set_skin(mdlj_ctx *ctx, double skin, int32_t rebuild_every);
 
-/* Pruned inner list of the staged Verlet-list kernels: on (1, default) or
- * off (0).  The Verlet lists of section 2.1.1 hold the pairs within
+/* Pruned inner list of the staged Verlet-list kernels: on (1) or off (0,
+ * default).  The Verlet lists of section 2.1.1 hold the pairs within
  * rc + skin; the list build also keeps, per particle and in list order, the
  * entries closer than rc + 2 skin / 3, and force evaluations read that
  * shorter list while no particle has moved more than skin / 3 since the
@@ -179,10 +179,15 @@ mdlj_status mdlj_set_skin(mdlj_ctx *ctx, double skin, int32_t rebuild_every);
  * the next build.  Forces agree with the unpruned ones up to the order of
  * the FP64 sums.  Only tiled builds of the staged kernels' lists write it.
  * Changing the setting marks the lists for rebuilding.
+ * Validity is kept per tile (four cells along x, the staged kernels' unit
+ * of work): a tile falls back to the full list once a particle in it or in
+ * one of the 26 tiles around it has crossed the bound.
  * mdlj_pruning_state (synchronises the stream): 0 no inner list for the
- * current lists, 1 valid, 2 no longer valid. */
+ * current lists, 1 valid in every tile, 2 given up in some tiles, 3 given up
+ * in every tile; the count of tiles that gave it up into *tiles_out when not
+ * null. */
 mdlj_status mdlj_set_pruning(mdlj_ctx *ctx, int32_t on);
-mdlj_status mdlj_pruning_state(mdlj_ctx *ctx, int32_t *state);
+mdlj_status mdlj_pruning_state(mdlj_ctx *ctx, int32_t *state, int64_t *tiles_out);
 
 /* Parameters of species s for the Lennard-Jones 12-6 pair law (section 4.1
  * names the potential, section 2.1 Eq. 1 sums it over pairs): epsilon > 0,

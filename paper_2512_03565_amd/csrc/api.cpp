@@ -604,7 +604,7 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
                       &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo,    &ctx->b_hstart,
                       &ctx->b_vsort,   &ctx->b_vsort2,  &ctx->b_xrsort,  &ctx->b_tinv,
                       &ctx->b_sorted2, &ctx->b_fxrec, &ctx->b_fxrec2, &ctx->b_fxspec,
-                      &ctx->b_tunev,   &ctx->b_nbr_in,  &ctx->b_nlen_in};
+                      &ctx->b_tunev,   &ctx->b_nbr_in,  &ctx->b_nlen_in, &ctx->b_tilebad};
     for (DevBuf *b : bufs) free_buf(*b);
     delete ctx;
     return MDLJ_OK;
@@ -653,17 +653,21 @@ mdlj_status mdlj_set_pruning(mdlj_ctx *ctx, int32_t on)
     return MDLJ_OK;
 }
 
-mdlj_status mdlj_pruning_state(mdlj_ctx *ctx, int32_t *state)
+mdlj_status mdlj_pruning_state(mdlj_ctx *ctx, int32_t *state, int64_t *tiles_out)
 {
     if (!ctx || !state) return MDLJ_ERR_ARG;
     *state = 0;
+    if (tiles_out) *tiles_out = 0;
     if (ctx->inner != 1) return MDLJ_OK;
-    int32_t w = 0;
-    HIPCHK(ctx, hipMemcpyAsync(&w, (const int32_t *)ctx->b_flags.p + FLAG_INNER_STATE +
-                                       ctx->inner_par,
-                               sizeof w, hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<int32_t> tw((size_t)ctx->inner_ntiles);
+    HIPCHK(ctx, hipMemcpyAsync(tw.data(), (const int32_t *)ctx->b_tilebad.p +
+                                              ctx->inner_par * ctx->inner_ntiles,
+                               sizeof(int32_t) * tw.size(), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    *state = w != 0 ? 2 : 1;
+    int64_t bad = 0;
+    for (int32_t v : tw) bad += v != 0;
+    if (tiles_out) *tiles_out = bad;
+    *state = bad == 0 ? 1 : (bad < (int64_t)tw.size() ? 2 : 3);
     return MDLJ_OK;
 }
 

@@ -86,19 +86,6 @@ __global__ void k_kick_drift_sorted(int64_t n, double *__restrict__ x, double *_
     z[i] += dt * uz;
 }
 
-// The pruned inner list's validity word for the next force launch: set
-// when the current word is set or the particle moved more than
-// sqrt(thr_in2) since the list build; one atomic per wavefront (next null:
-// no inner list).
-__device__ __forceinline__ void inner_test(const int32_t *cur, int32_t *next, double d2,
-                                           double thr_in2)
-{
-    if (!next) return;
-    const bool c = *cur != 0;
-    const uint64_t m = __builtin_amdgcn_ballot_w64(c || !(d2 <= thr_in2));
-    if (m != 0 && (int)(threadIdx.x & (MDLJ_WAVE - 1)) == __builtin_ctzll(m)) atomicOr(next, 1);
-}
-
 // The same step for Verlet lists between rebuilds, in sorted order: thread
 // t takes the t-th interior record (ilist), its sorted force and its
 // velocity and list-build reference position by compact index, so every
@@ -112,9 +99,9 @@ __global__ void k_kick_drift_compact(int64_t n, const int32_t *__restrict__ ilis
                                      const double *__restrict__ fy,
                                      const double *__restrict__ fz, InvMass im, double dt,
                                      const double *__restrict__ xrs, double thr2,
-                                     int32_t *__restrict__ flag, const int32_t *in_cur,
-                                     int32_t *in_next, double thr_in2)
+                                     int32_t *__restrict__ flag, InnerMark imk)
 {
+    inner_carry(imk);
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int32_t s = ilist[t];
@@ -134,7 +121,7 @@ __global__ void k_kick_drift_compact(int64_t n, const int32_t *__restrict__ ilis
     const double dx = r.x - xrs[t], dy = r.y - xrs[n + t], dz = r.z - xrs[2 * n + t];
     const double d2 = dx * dx + dy * dy + dz * dz;
     if (!(d2 <= thr2)) atomicOr(flag, 1);
-    inner_test(in_cur, in_next, d2, thr_in2);
+    inner_mark(imk, r.orig, d2);
 }
 
 // The step before a list rebuild, from the sorted-order state: the same
@@ -343,15 +330,15 @@ __global__ void k_kick_sorted(int64_t n, double *__restrict__ vx, double *__rest
 __global__ void k_displacement(int64_t n, const double *__restrict__ x,
                                const double *__restrict__ y, const double *__restrict__ z,
                                const double *__restrict__ xr, double thr2,
-                               int32_t *__restrict__ flag, const int32_t *in_cur,
-                               int32_t *in_next, double thr_in2)
+                               int32_t *__restrict__ flag, InnerMark imk)
 {
+    inner_carry(imk);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double dx = x[i] - xr[i], dy = y[i] - xr[n + i], dz = z[i] - xr[2 * n + i];
     const double d2 = dx * dx + dy * dy + dz * dz;
     if (!(d2 <= thr2)) atomicOr(flag, 1);
-    inner_test(in_cur, in_next, d2, thr_in2);
+    inner_mark(imk, i, d2);
 }
 
 }  // namespace
@@ -388,13 +375,9 @@ mdlj_status launch_displacement_check(mdlj_ctx *ctx)
     int32_t *flag = (int32_t *)ctx->b_flags.p + 13;
     if (!ctx->dflag_zero) HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
     const double h = 0.5 * ctx->skin;
-    const int32_t *in_cur;
-    int32_t *in_next;
-    double thr_in2;
-    inner_words(ctx, &in_cur, &in_next, &thr_in2);
     k_displacement<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(n, ctx->x, ctx->y, ctx->z,
                                                              (const double *)ctx->b_xref.p, h * h,
-                                                             flag, in_cur, in_next, thr_in2);
+                                                             flag, inner_marker(ctx));
     HIPCHK(ctx, hipGetLastError());
     inner_flip(ctx);
     ctx->flag_seq_disp = ++ctx->flag_seq;
@@ -595,8 +578,7 @@ mdlj_status kd_args(mdlj_ctx *ctx, KickArgs *ka)
     const double h = 0.5 * ctx->skin;
     ka->thr2 = h * h;
     ka->pad_slot = ctx->n_ext;
-    ka->in_bad = nullptr;  // set by the launch
-    ka->thr_in2 = 0.0;
+    ka->thr_in2 = 0.0;  // set by the launch
     return MDLJ_OK;
 }
 
@@ -668,14 +650,10 @@ static mdlj_status vv_loop(mdlj_ctx *ctx, double *vx, double *vy, double *vz, do
             const double h = 0.5 * ctx->skin;
             if (!ctx->dflag_zero) HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
             ctx->dflag_zero = false;
-            const int32_t *in_cur;
-            int32_t *in_next;
-            double thr_in2;
-            inner_words(ctx, &in_cur, &in_next, &thr_in2);
             k_kick_drift_compact<<<nb, TB, 0, ctx->stream>>>(
                 n, (const int32_t *)ctx->b_ilist.p, (PosT *)ctx->b_sorted.p,
                 (double *)ctx->b_vsort.p, fo.fx, fo.fy, fo.fz, im, dt,
-                (const double *)ctx->b_xrsort.p, h * h, flag, in_cur, in_next, thr_in2);
+                (const double *)ctx->b_xrsort.p, h * h, flag, inner_marker(ctx));
             inner_flip(ctx);
             ctx->upkeep_fused = true;
             ctx->rec_at_build = false;

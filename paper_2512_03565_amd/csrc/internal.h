@@ -98,29 +98,83 @@ struct KickArgs {
     // fx_s) to a second word array; null otherwise
     FxWords *fxr_out;
     double fx_c[3], fx_s;
-    // the pruned inner list's validity word for the next launch: set to 1
-    // when the current word is set or a particle moved more than
-    // sqrt(thr_in2) since the list build (null: no inner list)
-    int32_t *in_bad;
+    // the pruned inner list's squared displacement bound (InnerList)
     double thr_in2;
 };
+
+// Staged Verlet-list kernels: a tile is STAGE_K consecutive cells along x
+// of one (y, z) cell row (tiles_x = ceil(n_x / STAGE_K) per row, numbered
+// x-fastest); its workgroup stages the nine cell rows around it.
+constexpr int STAGE_K = 4;
 
 // The pruned inner Verlet list of the staged kernels, written by the list
 // build: the entries of each row whose pair was closer than r_in at the
 // build, in list order (same row layout and capacity as the list, rows
-// padded to 8 with the padding entry).  It holds every pair inside the
-// cutoff while no particle has moved more than (r_in - rc) / 2 since the
-// build.  Two validity words take turns: a launch reads one (cur) and
-// anything that moves particles writes the other, so that no launch reads a
-// word it also writes; both are cleared at the build and only ever set
-// afterwards.  A force launch reads the inner rows when *cur == 0.
+// padded to 8 with the padding entry).  A tile's inner rows hold every pair
+// inside the cutoff while no particle of its staged neighbourhood has moved
+// more than (r_in - rc) / 2 since the build.  One validity word per tile, in
+// two copies that take turns: a launch reads one (cur) and anything that
+// moves particles writes the other (next), so that no launch reads a word it
+// also writes.  Both are cleared at the build and only ever set afterwards:
+// a particle that crosses the bound sets the words of the 27 tiles around
+// its own (every tile whose staged rows include its cell), and each mover
+// carries the words already set over.  A tile reads the inner rows while its
+// word is clear.
 struct InnerList {
     const uint16_t *nbr;
     const int32_t *len;
-    const int32_t *cur;  // null: no inner list
+    const int32_t *tile_cur;  // null: no inner list
+    int32_t *tile_next;       // written by the fused integrator step
 };
-// first of the two validity words in the flag block
-constexpr int FLAG_INNER_STATE = 48;
+
+// What a kernel that moves particles outside the force kernel needs to
+// keep the tile words: cur / next as above (null: no inner list), the
+// extended cell of each caller index at the build (the cell its record is
+// staged in), the grid and the bound.
+struct InnerMark {
+    const int32_t *cur;
+    int32_t *next;
+    const int32_t *cell_of;
+    Grid g;
+    int tiles_x;
+    int64_t ntiles;
+    double thr2;
+};
+
+// Set the words of the 27 tiles around tile (tx, ty, tz), periodically (the
+// fused force kernel does the same with one thread per tile).
+__device__ __forceinline__ void inner_mark_tiles(int32_t *next, int tx, int ty, int tz,
+                                                 int tiles_x, const Grid &g)
+{
+    for (int k = 0; k < 27; ++k) {
+        const int nx = (tx + k % 3 - 1 + tiles_x) % tiles_x;
+        const int ny = (ty + (k / 3) % 3 - 1 + g.n[1]) % g.n[1];
+        const int nz = (tz + k / 9 - 1 + g.n[2]) % g.n[2];
+        int32_t *w = next + nx + (int64_t)tiles_x * (ny + (int64_t)g.n[1] * nz);
+        if (*w == 0) atomicOr(w, 1);
+    }
+}
+
+// Caller particle i moved d2 (squared) since the build: past the bound, the
+// tiles around its record's tile give the inner list up.
+__device__ __forceinline__ void inner_mark(const InnerMark &m, int64_t i, double d2)
+{
+    if (!m.next || d2 <= m.thr2) return;
+    const int32_t e = m.cell_of[i];
+    int c[3];
+    for (int a = 0; a < 3; ++a) c[a] = (int)((e / m.g.stride[a]) % m.g.e[a]) - m.g.h[a];
+    inner_mark_tiles(m.next, c[0] / STAGE_K, c[1], c[2], m.tiles_x, m.g);
+}
+
+// The words already set carried over to the next copy (grid-stride over
+// the tiles; every thread of the launch takes part).
+__device__ __forceinline__ void inner_carry(const InnerMark &m)
+{
+    if (!m.next) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m.ntiles; k += stride)
+        if (m.cur[k]) atomicOr(m.next + k, 1);
+}
 
 // Device buffers that grow on demand.
 struct DevBuf {
@@ -197,7 +251,7 @@ struct mdlj_ctx {
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
         b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart, b_vsort,
         b_vsort2, b_xrsort, b_tinv, b_sorted2, b_fxrec, b_fxrec2, b_fxspec, b_tunev, b_nbr_in,
-        b_nlen_in;
+        b_nlen_in, b_tilebad;
     int64_t nhalo = 0;            // entries of b_halo
     int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 
@@ -256,11 +310,12 @@ struct mdlj_ctx {
     bool fx_valid = false;
     double fx_c[3] = {0, 0, 0}, fx_s = 0.0;
     // pruned inner list of the staged Verlet-list kernels (b_nbr_in,
-    // b_nlen_in; validity words FLAG_INNER_STATE + 0/1): prune enables it;
-    // inner: 1 when the list build wrote one for the current lists;
-    // inner_par: the word launches read
-    bool prune = true;
+    // b_nlen_in; two copies of inner_ntiles tile words in b_tilebad): prune
+    // enables it; inner: 1 when the list build wrote one for the current
+    // lists; inner_par: the copy launches read now
+    bool prune = false;
     int inner = 0, inner_par = 0;
+    int64_t inner_ntiles = 0;
     // allocation-free calls (mdlj_compute_forces_noalloc): no device buffer,
     // pinned word or timing event may be created or grown (ensure() and the
     // others refuse), and the energy/virial partials of the force kernels go
@@ -296,11 +351,9 @@ mdlj_status partial_buffer(mdlj_ctx *ctx, int64_t nvals, double **out);
     } while (0)
 
 // --- pruned inner list (vl.hip) -------------------------------------------
-// Validity words of the inner list for a kernel that moves particles:
-// *cur the one launches read now, *next the one it writes (both null when
-// there is no inner list); thr_in2 the squared displacement bound.  The
-// caller calls inner_flip after queueing that kernel.
-void inner_words(mdlj_ctx *ctx, const int32_t **cur, int32_t **next, double *thr_in2);
+// The tile words for a kernel that moves particles (cur/next null when
+// there is no inner list).  The caller calls inner_flip after queueing it.
+InnerMark inner_marker(mdlj_ctx *ctx);
 void inner_flip(mdlj_ctx *ctx);
 
 // --- binning (bin.hip) ----------------------------------------------------

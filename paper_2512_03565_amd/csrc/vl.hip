@@ -87,7 +87,6 @@ __global__ __launch_bounds__(256) void k_vl_build(const PosT *__restrict__ rec,
 // and one halo cell either side), the order in which the force kernel
 // stages them into LDS; 16 bits, row-major per i, padded to a multiple of 8
 // with the index one past the staged particles (a far-away padding entry).
-constexpr int STAGE_K = 4;
 
 __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__ rec,
                                                         const int32_t *__restrict__ start,
@@ -686,18 +685,6 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
                                             const int32_t *__restrict__ fxspec, const KickArgs &ka,
                                             const InnerList &il)
 {
-    // the list this launch reads: the pruned inner rows while they hold every
-    // pair inside the cutoff (a uniform decision, from a word that earlier
-    // launches wrote), else the full rows
-    bool use_in = false, in_bad0 = false;
-    if (il.cur) {
-        in_bad0 = __builtin_amdgcn_readfirstlane(*il.cur) != 0;
-        use_in = !in_bad0;
-    }
-    // fused step: a word already set stays set in the next one
-    if (KD && in_bad0 && ka.in_bad && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(ka.in_bad, 1);
-    const uint16_t *__restrict__ nbr = use_in ? il.nbr : nbr_full;
-    const int32_t *__restrict__ len = use_in ? il.len : len_full;
     // FP32 pair law: fixed-point staged records; fxs is their scale and tab
     // holds sig^2 fxs^2, 24 eps fxs and rc^2 fxs^2, so that every pair
     // quantity comes out in its own units.  FP64 law: FP64 coordinates.
@@ -710,6 +697,7 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     __shared__ int seg_c[10];
     __shared__ LdsTable<T> lt;
     __shared__ double red[2 * NW];
+    __shared__ int s_moved;  // fused step: a particle crossed the inner list's bound
     const double rc2 = tab.rc2d;
     const int tid = threadIdx.x;
     // the wavefront index as a uniform value (i-group bases in scalar registers)
@@ -727,6 +715,15 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
     const int cz = (int)(rr / (uint32_t)g.n[1]);
     const int cx0 = tx * STAGE_K;
     const int ncx = min(STAGE_K, g.n[0] - cx0);
+    // the list this tile reads: the pruned inner rows while they hold every
+    // pair inside the cutoff, else the full rows (a uniform decision, from
+    // the tile's word, which earlier launches wrote)
+    bool use_in = false;
+    if (il.tile_cur) {
+        use_in = __builtin_amdgcn_readfirstlane(il.tile_cur[tile]) == 0;
+    }
+    const uint16_t *__restrict__ nbr = use_in ? il.nbr : nbr_full;
+    const int32_t *__restrict__ len = use_in ? il.len : len_full;
     const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
                        cx0 + g.h[0];
     const int ib = start[ei], ie = start[ei + ncx];
@@ -737,6 +734,7 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
         seg_b[tid] = start[ej];
         seg_c[tid + 1] = start[ej + ncx + 2] - start[ej];
     }
+    if (KD && tid == 9) s_moved = 0;
     // compact index of the tile's first particle (cells of a tile are consecutive)
     const int64_t c0 = (int64_t)cx0 + (int64_t)g.n[0] * (cy + (int64_t)g.n[1] * cz);
     const int64_t t0 = ibase[c0];
@@ -921,11 +919,8 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
             const double dy = __shfl_down(d, 1, SEG), dz = __shfl_down(d, 2, SEG);
             const double d2 = d * d + dy * dy + dz * dz;
             if (act && l == 0 && !(d2 <= ka.thr2)) atomicOr(ka.flag, 1);
-            // the inner list's bound, once per wavefront until it is crossed
-            if (ka.in_bad && !in_bad0) {
-                const uint64_t m = __builtin_amdgcn_ballot_w64(act && l == 0 && !(d2 <= ka.thr_in2));
-                if (m != 0 && lane == 0) atomicOr(ka.in_bad, 1);
-            }
+            // a particle of the tile crossed the inner list's bound
+            if (act && l == 0 && !(d2 <= ka.thr_in2)) s_moved = 1;
         } else if (act && l == 0) {
             fo.fx[i] = a.fx;
             fo.fy[i] = a.fy;
@@ -935,6 +930,27 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
             bu += a.u;
             // the fixed-point path sums 24 eps s6 (2 s6 - 1) fxs
             bw += FX ? a.w * (1.0 / fxs) : a.w;
+        }
+    }
+    if constexpr (KD) {
+        // the inner list's bound crossed in this tile: the next launch gives
+        // up the inner rows in the 27 tiles around it (every tile whose
+        // staged rows include cells of this one)
+        if (il.tile_cur) {
+            __syncthreads();
+            // the tile's coordinates again (not kept live through the loop)
+            const int64_t tl = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+            if (s_moved && tid < 27) {
+                const int ux = (int)((uint32_t)tl % (uint32_t)tiles_x);
+                const uint32_t ur = (uint32_t)tl / (uint32_t)tiles_x;
+                const int uy = (int)(ur % (uint32_t)g.n[1]), uz = (int)(ur / (uint32_t)g.n[1]);
+                const int nx = (ux + tid % 3 - 1 + tiles_x) % tiles_x;
+                const int ny = (uy + (tid / 3) % 3 - 1 + g.n[1]) % g.n[1];
+                const int nz = (uz + tid / 9 - 1 + g.n[2]) % g.n[2];
+                atomicOr(il.tile_next + nx + (int64_t)tiles_x * (ny + (int64_t)g.n[1] * nz), 1);
+            }
+            // a word already set stays set in the next copy
+            if (tid == 32 && il.tile_cur[tl]) atomicOr(il.tile_next + tl, 1);
         }
     }
     if (E) {
@@ -1223,11 +1239,11 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         if (ctx->inner == 1) {
             il.nbr = (uint16_t *)ctx->b_nbr_in.p;
             il.len = (int32_t *)ctx->b_nlen_in.p;
-            il.cur = (const int32_t *)ctx->b_flags.p + FLAG_INNER_STATE + ctx->inner_par;
-        }
-        if (kd) {
-            const int32_t *cur = nullptr;
-            inner_words(ctx, &cur, &kk.in_bad, &kk.thr_in2);
+            int32_t *tw = (int32_t *)ctx->b_tilebad.p;
+            il.tile_cur = tw + ctx->inner_par * nbt;
+            il.tile_next = tw + (ctx->inner_par ^ 1) * nbt;
+            const double h = 0.5 * PRUNE_FRACTION * ctx->skin;
+            kk.thr_in2 = h * h;
         }
         const KickArgs none = {};
 #define VL_LDS(GG, VV)                                                                          \
@@ -1469,17 +1485,21 @@ mdlj_status vl_list_entries(mdlj_ctx *ctx, int64_t *entries)
     return MDLJ_OK;
 }
 
-void inner_words(mdlj_ctx *ctx, const int32_t **cur, int32_t **next, double *thr_in2)
+InnerMark inner_marker(mdlj_ctx *ctx)
 {
-    *cur = nullptr;
-    *next = nullptr;
-    *thr_in2 = 0.0;
-    if (ctx->inner != 1) return;
-    int32_t *w = (int32_t *)ctx->b_flags.p + FLAG_INNER_STATE;
-    *cur = w + ctx->inner_par;
-    *next = w + (ctx->inner_par ^ 1);
+    InnerMark m = {};
+    if (ctx->inner != 1) return m;
+    int32_t *tw = (int32_t *)ctx->b_tilebad.p;
+    const int64_t nt = ctx->inner_ntiles;
+    m.cur = tw + ctx->inner_par * nt;
+    m.next = tw + (ctx->inner_par ^ 1) * nt;
+    m.cell_of = (const int32_t *)ctx->b_cell_of.p;
+    m.g = ctx->grid;
+    m.tiles_x = (int)ceil_div(ctx->grid.n[0], STAGE_K);
+    m.ntiles = nt;
     const double h = 0.5 * PRUNE_FRACTION * ctx->skin;
-    *thr_in2 = h * h;
+    m.thr2 = h * h;
+    return m;
 }
 
 void inner_flip(mdlj_ctx *ctx)
@@ -1554,11 +1574,15 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         // kernels' lists (an allocation-free call goes without it rather
         // than grow its buffers)
         bool inner = false;
+        const int64_t ntiles = ceil_div(g.n[0], STAGE_K) * g.n[1] * g.n[2];
         if (tiled && local && !cfg.newton3 && ctx->prune && ctx->skin > 0.0) {
             const size_t ib = esize * (size_t)(n * cap + slack), lb = sizeof(int32_t) * (size_t)n;
-            if (!ctx->no_alloc || (ctx->b_nbr_in.bytes >= ib && ctx->b_nlen_in.bytes >= lb)) {
+            const size_t tb = 2 * sizeof(int32_t) * (size_t)ntiles;
+            if (!ctx->no_alloc || (ctx->b_nbr_in.bytes >= ib && ctx->b_nlen_in.bytes >= lb &&
+                                   ctx->b_tilebad.bytes >= tb)) {
                 STCHK(ensure(ctx, ctx->b_nbr_in, ib));
                 STCHK(ensure(ctx, ctx->b_nlen_in, lb));
+                STCHK(ensure(ctx, ctx->b_tilebad, tb));
                 inner = true;
             }
         }
@@ -1612,10 +1636,11 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         if (hmax[0] <= cap) {
             ctx->nbr_cap = cap;
             if (inner) {
-                int32_t *w = (int32_t *)ctx->b_flags.p + FLAG_INNER_STATE;
-                HIPCHK(ctx, hipMemsetAsync(w, 0, 2 * sizeof(int32_t), ctx->stream));
+                HIPCHK(ctx, hipMemsetAsync(ctx->b_tilebad.p, 0, 2 * sizeof(int32_t) * ntiles,
+                                           ctx->stream));
                 ctx->inner = 1;
                 ctx->inner_par = 0;
+                ctx->inner_ntiles = ntiles;
             }
             return MDLJ_OK;
         }

@@ -85,7 +85,7 @@ _SIGS = {
     "mdlj_set_species": [_ctxp, C.c_int32, C.c_double, C.c_double],
     "mdlj_set_energy_shift": [_ctxp, C.c_int32],
     "mdlj_set_pruning": [_ctxp, C.c_int32],
-    "mdlj_pruning_state": [_ctxp, C.POINTER(C.c_int32)],
+    "mdlj_pruning_state": [_ctxp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
     "mdlj_set_precision": [_ctxp, C.c_int32],
     "mdlj_set_positions": [_ctxp, _vp, _vp, _vp, C.c_int32],
     "mdlj_get_positions": [_ctxp, _vp, _vp, _vp, C.c_int32],
@@ -375,11 +375,14 @@ class System:
     def set_pruning(self, on):
         check(lib.mdlj_set_pruning(self.ctx, int(bool(on))), self.ctx)
 
-    def pruning_state(self):
-        """0 no inner list, 1 pending, 2 written and valid, 3 no longer valid."""
+    def pruning_state(self, tiles=False):
+        """0 no inner list, 1 valid everywhere, 2 given up in some tiles, 3
+        given up everywhere; with tiles=True also the count of tiles that gave
+        it up."""
         v = C.c_int32()
-        check(lib.mdlj_pruning_state(self.ctx, C.byref(v)), self.ctx)
-        return v.value
+        t = C.c_int64()
+        check(lib.mdlj_pruning_state(self.ctx, C.byref(v), C.byref(t)), self.ctx)
+        return (v.value, t.value) if tiles else v.value
 
     def set_tune_metric(self, metric):
         check(lib.mdlj_set_tune_metric(self.ctx, int(metric)), self.ctx)

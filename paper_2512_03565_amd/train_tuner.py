@@ -88,12 +88,17 @@ def main(argv=None):
     ap.add_argument("--threshold", type=float, default=0.6)
     ap.add_argument("--out", default="tuner_mlp.bin")
     ap.add_argument("--summary", default=None)
+    ap.add_argument("--save-sweep", default=None,
+                    help="also write the merged sweep (one row per scene) to this .npz")
     a = ap.parse_args(argv)
 
     import torch  # noqa: F401  (one HIP runtime: torch's)
     from paper_2512_03565_amd import mdlj, scenes
 
     F, T, meta, names = load(a.sweeps)
+    if a.save_sweep:
+        np.savez_compressed(a.save_sweep, features=F, table_us=T, names=np.array(names),
+                            meta=meta)
     ok = np.isfinite(T).any(1)
     F, T, meta = F[ok], T[ok], meta[ok]
     y = T.argmin(1).astype(np.int32)
@@ -104,8 +109,8 @@ def main(argv=None):
     std[std < 1e-6] = 1.0
     s = scenes.config1()
     with mdlj.System(s["pos"], s["box"], s["rc"]) as sysm:
-        if len(sysm.configs()) != T.shape[1]:
-            raise ValueError("sweep table width differs from the library's configuration space")
+        if [mdlj.config_name(c) for c in sysm.configs()] != names:
+            raise ValueError("sweep configurations differ from the library's configuration space")
         sysm.mlp_init(T.shape[1], seed=a.seed)
         sysm.mlp_set_norm(mean, std)
         loss = sysm.mlp_train(Ftr, ytr, a.epochs, a.batch, a.lr, a.seed + 1)

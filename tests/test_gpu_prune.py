@@ -2,7 +2,7 @@
 entries closer than rc + 2 skin / 3 at the build (written by the list
 build), read while no particle has moved more than skin / 3 since (the skin
 argument of section 2.1.1 with the smaller skin), the full list
-afterwards."""
+afterwards.  The inner list is off by default; these tests switch it on."""
 import numpy as np
 import pytest
 
@@ -33,8 +33,8 @@ def test_inner_list_static_parity(m, orc, prec):
         with m.System(pos, box, rc, skin=0.3, precision=prec) as on, \
                 m.System(pos, box, rc, skin=0.3, precision=prec) as off:
             on.set_config(cfg)
+            on.set_pruning(True)
             off.set_config(cfg)
-            off.set_pruning(False)
             assert on.pruning_state() == 0
             f0, _, _ = on.forces(energy=False)
             assert on.pruning_state() == 1
@@ -72,6 +72,7 @@ def test_inner_list_invalidated_by_displacement(m, orc, prec):
     tol = 1e-5 if prec == 0 else 1e-12
     with m.System(pos, box, rc, skin=0.3, rebuild_every=1000, precision=prec) as sysm:
         sysm.set_config(STAGED[0])
+        sysm.set_pruning(True)
         f, _, _ = sysm.forces()
         assert sysm.pruning_state() == 1 and np.abs(f).max() == 0.0
         # each of A, B 0.09 towards the other (< skin / 3 = 0.1): still
@@ -89,7 +90,9 @@ def test_inner_list_invalidated_by_displacement(m, orc, prec):
         p[ib, 0] -= 0.11
         sysm.set_positions(p)
         f, U, W = sysm.forces()
-        assert sysm.pruning_state() == 2
+        # the tiles around A and B gave the inner list up, the others kept it
+        state, tiles = sysm.pruning_state(tiles=True)
+        assert state == 2 and 1 <= tiles <= 54, (state, tiles)
         ref = orc.forces(p, box, rc)
         assert np.abs(ref["f"][ia]).max() > 0.01
         err = np.abs(f - ref["f"]).max() / np.abs(ref["f"]).max()
@@ -98,7 +101,12 @@ def test_inner_list_invalidated_by_displacement(m, orc, prec):
         # back within the bound: the word stays set until the next build
         sysm.set_positions(pos)
         sysm.forces()
-        assert sysm.pruning_state() == 2
+        assert sysm.pruning_state(tiles=True) == (state, tiles)
+        # every particle moved past the bound (0.07 per axis, 0.12 < skin / 2):
+        # no tile keeps it
+        sysm.set_positions(pos + 0.07)
+        sysm.forces()
+        assert sysm.pruning_state() == 3
         sysm.rebuild()
         assert sysm.pruning_state() == 1
         sysm.forces()
@@ -109,8 +117,8 @@ def test_inner_list_invalidated_by_displacement(m, orc, prec):
 def test_inner_list_invalidated_inside_the_fused_step(m, orc, prec):
     # A and B approach at speed 1 each (dt 0.01): after step 10 each has
     # moved 0.1 (the bound), after 11 they are inside rc.  The integrator
-    # steps inside the staged kernel must give the inner list up in time:
-    # the trajectory matches the oracle's
+    # steps inside the staged kernel must give the inner list up in time in
+    # the tiles around them: the trajectory matches the oracle's
     import torch
     pos, box, ia, ib = _pair_scene()
     rc, dt, nsteps = 2.5, 0.01, 14
@@ -121,11 +129,14 @@ def test_inner_list_invalidated_inside_the_fused_step(m, orc, prec):
     assert np.abs(f_ref[ia]).max() > 0.01
     with m.System(pos, box, rc, skin=0.3, rebuild_every=1000, precision=prec) as sysm:
         sysm.set_config(STAGED[0])
+        sysm.set_pruning(True)
         sysm.set_timing(True)
         v = [torch.tensor(np.ascontiguousarray(vel[:, k]), device="cuda") for k in range(3)]
         sysm.step_vv(v, dt, nsteps)
         _, _, nf, nb = sysm.get_timing()
-        assert sysm.pruning_state() == 2
+        # the tiles around A and B gave the inner list up, the others kept it
+        state, tiles = sysm.pruning_state(tiles=True)
+        assert state == 2 and 1 <= tiles <= 54, (state, tiles)
         pos_g = sysm.get_positions()
     assert nb == 1, nb   # one build: skin / 2 is never crossed
     vg = torch.stack(v, 1).cpu().numpy()
@@ -167,6 +178,9 @@ def test_pruning_argument_checks(m):
             m.check(m.lib.mdlj_set_pruning(sysm.ctx, 2), sysm.ctx)
         sysm.set_config(STAGED[0])
         sysm.forces()
+        assert sysm.pruning_state() == 0  # off by default
+        sysm.set_pruning(True)
+        sysm.forces()
         assert sysm.pruning_state() == 1
         # switching it off drops the inner list at once
         sysm.set_pruning(False)
@@ -176,5 +190,6 @@ def test_pruning_argument_checks(m):
     # no skin: no inner list
     with m.System(s["pos"], s["box"], s["rc"], skin=0.0) as sysm:
         sysm.set_config(STAGED[0])
+        sysm.set_pruning(True)
         sysm.forces()
         assert sysm.pruning_state() == 0
