@@ -199,6 +199,133 @@ __global__ void k_pair_search(ClusterGeom cg, const double *__restrict__ bb,
     atomic_max_rare(maxlen, cnt);
 }
 
+// The same search with one wavefront per cluster I.  Phase 1: lane w takes
+// search window w (column offset dy, dx and z shift sz, in the loop order of
+// k_pair_search) and finds its range of candidate clusters by binary search
+// on the slab keys; a scan over the wavefront gives each window its offset
+// in one flattened candidate sequence (per wavefront in LDS: range start,
+// offset and shift code of each of the nwin windows).  Phase 2: lane l
+// tests candidates k0 + l of that sequence, and passing entries are
+// compacted in order with a ballot, so the list is the one k_pair_search
+// writes, entry for entry.
+constexpr int PS_TB = 256;
+
+__global__ __launch_bounds__(PS_TB) void k_pair_search_w(
+    ClusterGeom cg, const double *__restrict__ bb, const int32_t *__restrict__ slabr,
+    const int32_t *__restrict__ ccol, const int32_t *__restrict__ cbase, int half, int32_t cap,
+    int32_t *__restrict__ list, int32_t *__restrict__ len, int32_t *__restrict__ maxlen, int nwin)
+{
+    extern __shared__ int32_t psh[];
+    const int lane = threadIdx.x & (MDLJ_WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / MDLJ_WAVE);
+    const int64_t I = (int64_t)blockIdx.x * (PS_TB / MDLJ_WAVE) + wv;
+    if (I >= cg.nclu) return;  // whole wavefronts; no workgroup barrier below
+    int32_t *wlo = psh + (size_t)wv * 3 * nwin;
+    int32_t *woff = wlo + nwin;
+    int32_t *wcode = woff + nwin;
+    double ilo[3], ihi[3];
+    for (int a = 0; a < 3; ++a) {
+        ilo[a] = bb[6 * I + a];
+        ihi[a] = bb[6 * I + 3 + a];
+    }
+    const int col = ccol[I];
+    const int cx = col % cg.ncx, cy = col / cg.ncx;
+    const double R = sqrt(cg.R2);
+    const int nxw = 2 * cg.hx + 1;
+    int32_t total = 0;
+    for (int w0 = 0; w0 < nwin; w0 += MDLJ_WAVE) {
+        const int w = w0 + lane;
+        int32_t lo = 0, cnt = 0, code = 0;
+        if (w < nwin) {
+            const int sz = w % 3 - 1;
+            const int dx = (w / 3) % nxw - cg.hx;
+            const int dy = w / (3 * nxw) - cg.hy;
+            int ny = cy + dy, sy = 0;
+            while (ny < 0) { ny += cg.ncy; --sy; }
+            while (ny >= cg.ncy) { ny -= cg.ncy; ++sy; }
+            int nx = cx + dx, sx = 0;
+            while (nx < 0) { nx += cg.ncx; --sx; }
+            while (nx >= cg.ncx) { nx -= cg.ncx; ++sx; }
+            const double shz = sz * cg.L[2];
+            const double wl = ilo[2] - R - shz, wh = ihi[2] + R - shz;
+            if (sy >= -1 && sy <= 1 && sx >= -1 && sx <= 1 && !(wh < 0.0 || wl > cg.L[2])) {
+                const int ncol = nx + cg.ncx * ny;
+                const int32_t q0 = cbase[ncol], q1 = cbase[ncol + 1];
+                // first cluster whose last slab reaches the window, then the
+                // first from there whose first slab lies beyond it (both keys
+                // are monotone along a column)
+                int32_t a = q0, b = q1;
+                while (a < b) {
+                    const int32_t mid = (a + b) >> 1;
+                    if ((slabr[2 * (int64_t)mid + 1] + 1) * cg.slab < wl) a = mid + 1;
+                    else b = mid;
+                }
+                lo = a;
+                b = q1;
+                while (a < b) {
+                    const int32_t mid = (a + b) >> 1;
+                    if (!(slabr[2 * (int64_t)mid] * cg.slab > wh)) a = mid + 1;
+                    else b = mid;
+                }
+                cnt = a - lo;
+                code = shift_code(sx, sy, sz);
+            }
+        }
+        // exclusive offsets of the windows' ranges
+        int32_t inc = cnt;
+        for (int o = 1; o < MDLJ_WAVE; o <<= 1) {
+            const int32_t t = __shfl_up(inc, o);
+            if (lane >= o) inc += t;
+        }
+        if (w < nwin) {
+            wlo[w] = lo;
+            woff[w] = total + inc - cnt;
+            wcode[w] = code;
+        }
+        total += __shfl(inc, MDLJ_WAVE - 1);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int32_t cnt = 0;
+    for (int32_t k0 = 0; k0 < total; k0 += MDLJ_WAVE) {
+        const int32_t k = k0 + lane;
+        bool keep = false;
+        int32_t e = 0;
+        if (k < total) {
+            // the last window whose offset is <= k (empty windows share the
+            // offset of the next one, so this is the window holding k)
+            int a = 0, b = nwin - 1;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (woff[mid] <= k) a = mid;
+                else b = mid - 1;
+            }
+            const int32_t q = wlo[a] + (k - woff[a]);
+            const int code = wcode[a];
+            const int sx = code % 3 - 1, sy = (code / 3) % 3 - 1, sz = code / 9 - 1;
+            const double shx = sx * cg.L[0], shy = sy * cg.L[1], shz = sz * cg.L[2];
+            const double gx = gap(ilo[0], ihi[0], bb[6 * (int64_t)q] + shx, bb[6 * (int64_t)q + 3] + shx);
+            const double gy = gap(ilo[1], ihi[1], bb[6 * (int64_t)q + 1] + shy, bb[6 * (int64_t)q + 4] + shy);
+            const double gz = gap(ilo[2], ihi[2], bb[6 * (int64_t)q + 2] + shz, bb[6 * (int64_t)q + 5] + shz);
+            keep = gx * gx + gy * gy + gz * gz < cg.R2;
+            // Newton 3: I < J, or I == J with the zero shift or one of each
+            // +- pair
+            if (half) keep = keep && (q > I || (q == I && code >= 13));
+            e = (int32_t)q | (code << CODE_SHIFT);
+        }
+        const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+        const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)cnt));
+        if (keep && pos < (uint32_t)cap) list[I * cap + pos] = e;
+        cnt += (int32_t)__builtin_popcountll(m);
+    }
+    if (lane == 0) {
+        len[I] = cnt;
+        atomic_max_rare(maxlen, cnt);
+    }
+}
+
 __device__ __forceinline__ void decode(int32_t e, const double *L, int32_t &J, double &sx,
                                        double &sy, double &sz)
 {
@@ -568,7 +695,14 @@ mdlj_status vcl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
     for (int attempt = 0; attempt < 3; ++attempt) {
         STCHK(ensure(ctx, ctx->b_nbr, sizeof(int32_t) * (nclu > 0 ? nclu : 1) * cap));
         HIPCHK(ctx, hipMemsetAsync(maxlen, 0, sizeof(int32_t), s));
-        if (nclu > 0)
+        // one wavefront per cluster while its search windows fit the LDS
+        const int nwin = (2 * cg.hy + 1) * (2 * cg.hx + 1) * 3;
+        const size_t plds = sizeof(int32_t) * 3 * (size_t)nwin * (PS_TB / MDLJ_WAVE);
+        if (nclu > 0 && plds <= 32768)
+            k_pair_search_w<<<ceil_div(nclu, PS_TB / MDLJ_WAVE), PS_TB, plds, s>>>(
+                cg, (const double *)ctx->b_cstart.p, slabr, ccol, cbase, cfg.newton3 ? 1 : 0,
+                (int32_t)cap, (int32_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen, nwin);
+        else if (nclu > 0)
             k_pair_search<<<ceil_div(nclu, 128), 128, 0, s>>>(
                 cg, (const double *)ctx->b_cstart.p, slabr, ccol, cbase, cfg.newton3 ? 1 : 0,
                 (int32_t)cap, (int32_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen);

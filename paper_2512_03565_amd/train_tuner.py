@@ -26,8 +26,9 @@ def load(paths):
     """Features, tables, metadata and configuration names of the sweeps,
     one row per scene (by scene index).  Columns are matched by
     configuration name: the longest name list is the space; a sweep of the
-    same scenes that timed other configurations fills their columns (a
-    value already present is kept)."""
+    same scenes that timed other (or the same) configurations fills their
+    columns, a later file's finite value replacing an earlier one (so a
+    re-timing of some configurations after a kernel change goes last)."""
     data = [np.load(p, allow_pickle=False) for p in paths]
     names = max((list(d["names"]) for d in data), key=len)
     rows = {}
@@ -39,7 +40,7 @@ def load(paths):
                 rows[sid] = [f, np.full(len(names), np.inf), mt]
             row = rows[sid][1]
             for c, v in zip(cols, t):
-                if not np.isfinite(row[c]) and np.isfinite(v):
+                if np.isfinite(v):
                     row[c] = v
     sids = sorted(rows)
     F = np.array([rows[s][0] for s in sids], np.float32)
