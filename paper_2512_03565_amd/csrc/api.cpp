@@ -238,13 +238,16 @@ static mdlj_status rebuild(mdlj_ctx *ctx, const mdlj_config &c)
         Grid g;
         if (!make_grid(ctx->box, rmin, h, false, &g))
             return set_err(ctx, MDLJ_ERR_GEOMETRY, "grid set-up failed");
-        STCHK(bin_particles(ctx, g));
+        STCHK(bin_particles(ctx, g, c.nbr_algo == MDLJ_NBR_VL));
         if (c.nbr_algo == MDLJ_NBR_VL) {
+            // the reference positions (wrapped by the binning) are queued
+            // before the build, which waits for its sizes
+            STCHK(save_reference(ctx));
             STCHK(vl_build(ctx, c));
             STCHK(build_halo_list(ctx));
         }
     }
-    if (c.nbr_algo != MDLJ_NBR_LC) STCHK(save_reference(ctx));
+    if (c.nbr_algo == MDLJ_NBR_VCL) STCHK(save_reference(ctx));
     ctx->rec_at_build = c.nbr_algo == MDLJ_NBR_VL;
     ctx->built = true;
     ctx->built_cfg = c;

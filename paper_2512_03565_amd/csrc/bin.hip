@@ -54,11 +54,13 @@ __device__ __forceinline__ int64_t source_cell(int64_t e, const Grid &g)
     return src;
 }
 
+// Also the binning flags (words 0-3) and the list build's maxima (12-15,
+// which the build's publishing kernel clears again after each build).
 __global__ void k_clear_bins(int32_t *__restrict__ count, int64_t ncell, int32_t *__restrict__ flags)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < ncell) count[e] = 0;
-    if (e < 4) flags[e] = 0;
+    if (e < 4 || (e >= 12 && e < 16)) flags[e] = 0;
 }
 
 __global__ void k_bin_count(int64_t n, double *__restrict__ x, double *__restrict__ y,
@@ -479,9 +481,8 @@ mdlj_status exclusive_scan(mdlj_ctx *ctx, const int32_t *in, int32_t *out, int64
     return MDLJ_OK;
 }
 
-mdlj_status build_ilist(mdlj_ctx *ctx)
+mdlj_status build_ilist(mdlj_ctx *ctx, const Grid &g)
 {
-    const Grid &g = ctx->grid;
     STCHK(ensure(ctx, ctx->b_icnt, sizeof(int32_t) * (g.ncell_int + 1) * 2));
     STCHK(ensure(ctx, ctx->b_ilist, sizeof(int32_t) * ctx->n));
     int32_t *icnt = (int32_t *)ctx->b_icnt.p;
@@ -536,7 +537,7 @@ bool make_grid(const double *L, const double *r_min, const int *h, bool z_fastes
     return true;
 }
 
-mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
+mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g, bool interior_list)
 {
     const int64_t n = ctx->n;
     if (g.ncell_ext >= (int64_t)1 << 31) return set_err(ctx, MDLJ_ERR_GEOMETRY, "too many cells");
@@ -562,6 +563,9 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g)
     HIPCHK(ctx, hipGetLastError());
     STCHK(exclusive_scan(ctx, (const int32_t *)ctx->b_cnt_ext.p, start, g.ncell_ext));
     HIPCHK(ctx, hipGetLastError());
+    // the compact interior order needs only the counts and cell starts:
+    // queued before the wait below, so that it runs while the host waits
+    if (interior_list) STCHK(build_ilist(ctx, g));
     // non-finite flag, record total and largest occupancy to the host in
     // one small kernel
     STCHK(ensure_host_flag(ctx));

@@ -531,6 +531,16 @@ mdlj_status leave_sorted(mdlj_ctx *ctx)
     return MDLJ_OK;
 }
 
+mdlj_status enter_sorted_early(mdlj_ctx *ctx, const mdlj_config &c)
+{
+    if (!ctx->kd_req || ctx->sorted_active || c.nbr_algo != MDLJ_NBR_VL || !c.staged ||
+        c.newton3 || ctx->rebuild_every < 2)
+        return MDLJ_OK;
+    // the records were just made from the positions the lists are built for
+    ctx->rec_at_build = true;
+    return enter_sorted(ctx);
+}
+
 mdlj_status positions_for_rebuild(mdlj_ctx *ctx)
 {
     if (!ctx->sorted_active) return MDLJ_OK;

@@ -359,7 +359,9 @@ void inner_flip(mdlj_ctx *ctx);
 // --- binning (bin.hip) ----------------------------------------------------
 // Bins the caller-order positions into g (wrapping them in place), writes
 // the sorted real + halo records and slot_of[i] (slot of caller particle i).
-mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g);
+// interior_list: also the compact interior order (build_ilist), queued
+// before the host waits for the binning's sizes.
+mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g, bool interior_list = false);
 // Halo slots carry forces applied to images by Newton-3 kernels: add them
 // onto the slot of the particle they copy.
 mdlj_status fold_forces(mdlj_ctx *ctx, const ForceOut &fo);
@@ -372,8 +374,9 @@ mdlj_status reduce_partials(mdlj_ctx *ctx, const double *partial, int64_t nblock
 mdlj_status check_types(mdlj_ctx *ctx, bool *ok);
 // Exclusive scan of n int32 counts; out[n] receives the total.
 mdlj_status exclusive_scan(mdlj_ctx *ctx, const int32_t *in, int32_t *out, int64_t n);
-// Compact list (length n) of the slots of real particles in sorted order.
-mdlj_status build_ilist(mdlj_ctx *ctx);
+// Compact list (length n) of the slots of real particles in sorted order,
+// for grid g (binned, its cell starts written).
+mdlj_status build_ilist(mdlj_ctx *ctx, const Grid &g);
 mdlj_status check_finite(mdlj_ctx *ctx, const double *x, const double *y, const double *z,
                          int64_t n, bool *ok);
 
@@ -410,6 +413,11 @@ mdlj_status positions_for_rebuild(mdlj_ctx *ctx);
 // Before a force call that may fuse the integrator step: decide (kd_go)
 // and, if the state is still in caller order, carry it into sorted order.
 mdlj_status kd_prepare(mdlj_ctx *ctx, const mdlj_config &c, bool energy);
+// Inside the integrator, after the records of a staged Verlet-list build
+// are made: carry the velocities into the new sorted order now (the step
+// continues in sorted order), so that it runs while the host waits for the
+// build's sizes.  Nothing otherwise.
+mdlj_status enter_sorted_early(mdlj_ctx *ctx, const mdlj_config &c);
 // Arguments of the fused step from the context's current buffers.
 mdlj_status kd_args(mdlj_ctx *ctx, KickArgs *ka);
 

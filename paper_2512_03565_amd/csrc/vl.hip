@@ -187,11 +187,13 @@ __device__ __forceinline__ void half_runs(const int (*rs)[STAGE_K + 3],
 }
 
 // host[0..3] = src[0..3] (system-scope stores to pinned memory)
-__global__ void k_publish4(const int32_t *__restrict__ src, int32_t *host, uint32_t seq)
+__global__ void k_publish4(int32_t *__restrict__ src, int32_t *host, uint32_t seq)
 {
     if (threadIdx.x == 0) {
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 4; ++k) {
             __hip_atomic_store(host + k, src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            src[k] = 0;  // cleared for the next build
+        }
         // after the values: the host waits for this word
         __hip_atomic_store((uint32_t *)host + 4, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
@@ -1511,7 +1513,7 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
 {
     const Grid &g = ctx->grid;
     const int64_t n = ctx->n;
-    STCHK(build_ilist(ctx));
+    // the compact interior order (ilist, ibase) comes with the binning
     const double rl = ctx->rc + ctx->skin;
     const double vol = ctx->box[0] * ctx->box[1] * ctx->box[2];
     const double est = (double)n / vol * 4.18879020478639 * rl * rl * rl * (cfg.newton3 ? 0.5 : 1.0);
@@ -1562,11 +1564,13 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
     // a row of the tiled build may run past its capacity before the host
     // sees it (it then rebuilds): slack of the longest possible row
     const int64_t slack = rowmajor ? 27 * (int64_t)ctx->max_cell + 8 : 0;
+    bool overlap = false;
     for (int attempt = 0; attempt < 3; ++attempt) {
         if ((double)cap * (double)n * (double)esize > 64e9)
             return set_err(ctx, MDLJ_ERR_OVERFLOW, "Verlet lists too large");
         STCHK(ensure(ctx, ctx->b_nbr, esize * (n * cap + slack)));
-        HIPCHK(ctx, hipMemsetAsync(maxlen, 0, 4 * sizeof(int32_t), ctx->stream));
+        // the four maxima start at zero: cleared by the binning and by the
+        // publishing kernel after each build
         const int64_t sk = rowmajor ? 1 : n;
         const int64_t st = rowmajor ? cap : 1;
         const bool tiled = tile_ok;
@@ -1608,6 +1612,19 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         const uint32_t seq = ++ctx->flag_seq;
         k_publish4<<<1, 64, 0, ctx->stream>>>(maxlen, ctx->d_hflag + 8, seq);
         HIPCHK(ctx, hipGetLastError());
+        if (!overlap) {
+            // work of the next force call that needs neither the lists nor
+            // their sizes, queued before the host waits for the sizes: the
+            // fixed-point words of the new records (an error there is left
+            // to the force launch to report) and the integrator's move to
+            // the new sorted order
+            overlap = true;
+            if (local && ctx->prec == MDLJ_PREC_F32PAIR_F64ACC) {
+                double fxs;
+                (void)fx_words(ctx, &fxs);
+            }
+            STCHK(enter_sorted_early(ctx, cfg));
+        }
         STCHK(wait_host_words(ctx, 12, seq));
         const int32_t hmax[4] = {ctx->h_flag[8], ctx->h_flag[9], ctx->h_flag[10], ctx->h_flag[11]};
         if (tiled && (hmax[2] > cmax || hmax[3] > ccand)) {
