@@ -234,10 +234,15 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(int64_t n,
     }
 }
 
+// Both kernels below write records up to the total *total (the end of the
+// cell starts); when it exceeds cap, the records their buffers hold, they
+// write nothing (the host grows the buffers and runs them again).
 __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
                           const int32_t *__restrict__ rank, const int32_t *__restrict__ start,
-                          int32_t *__restrict__ sorted_orig)
+                          int32_t *__restrict__ sorted_orig, const int32_t *__restrict__ total,
+                          int64_t cap)
 {
+    if ((int64_t)*total > cap) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t e = cell_of[i];
@@ -268,8 +273,9 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, const int32_t *__restrict_
                                               PosT *__restrict__ rec,
                                               int32_t *__restrict__ slot_of,
                                               char4 *__restrict__ img,
-                                              int32_t *__restrict__ hstart)
+                                              int32_t *__restrict__ hstart, int64_t cap)
 {
+    if ((int64_t)start[g.ncell_ext] > cap) return;
     const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FILL_LANES;
     const int sub = threadIdx.x & (FILL_LANES - 1);
     // a group of lanes past the last cell has no records: every lane of a
@@ -566,28 +572,48 @@ mdlj_status bin_particles(mdlj_ctx *ctx, const Grid &g, bool interior_list)
     // the compact interior order needs only the counts and cell starts:
     // queued before the wait below, so that it runs while the host waits
     if (interior_list) STCHK(build_ilist(ctx, g));
+    // the records' scatter and fill, queued before the wait below when the
+    // buffers of the last binning hold at least the particles and their
+    // earlier number of images (they check the actual total themselves);
+    // the halo starts and slot map have sizes known here
+    STCHK(ensure(ctx, ctx->b_hstart, sizeof(int32_t) * g.ncell_ext));
+    int64_t cap = std::min<int64_t>({(int64_t)(ctx->b_sorted.bytes / sizeof(PosT)) - 1,
+                                     (int64_t)(ctx->b_misc.bytes / sizeof(int32_t)),
+                                     (int64_t)(ctx->b_img.bytes / sizeof(char4))});
+    const int32_t *total = start + g.ncell_ext;
+    auto scatter_fill = [&]() -> mdlj_status {
+        k_scatter<<<ceil_div(n, TB), TB, 0, s>>>(n, (int32_t *)ctx->b_cell_of.p,
+                                                  (int32_t *)ctx->b_rank.p, start,
+                                                  (int32_t *)ctx->b_misc.p, total, cap);
+        k_fill<<<ceil_div(g.ncell_ext, TB / FILL_LANES), TB, 0, s>>>(
+            g, start, (const int32_t *)ctx->b_misc.p, ctx->x, ctx->y, ctx->z, ctx->type,
+            (PosT *)ctx->b_sorted.p, (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p,
+            (int32_t *)ctx->b_hstart.p, cap);
+        HIPCHK(ctx, hipGetLastError());
+        return MDLJ_OK;
+    };
     // non-finite flag, record total and largest occupancy to the host in
-    // one small kernel
+    // one small kernel, ahead of the scatter and fill, so that the host
+    // can go on while they run
     STCHK(ensure_host_flag(ctx));
     const uint32_t seq = ++ctx->flag_seq;
     k_publish_bin<<<1, 64, 0, s>>>(flags, start + g.ncell_ext, ctx->d_hflag + 4, seq);
     HIPCHK(ctx, hipGetLastError());
+    const bool early = cap >= n;
+    if (early) STCHK(scatter_fill());
     STCHK(wait_host_words(ctx, 7, seq));
     const int32_t host[3] = {ctx->h_flag[4], ctx->h_flag[5], ctx->h_flag[6]};
     if (host[0]) return set_err(ctx, MDLJ_ERR_NONFINITE, "non-finite particle position");
     const int64_t n_ext = host[1];
     if (n_ext < n) return set_err(ctx, MDLJ_ERR_HIP, "binning lost particles");
     ctx->max_cell = host[2];
-    STCHK(ensure(ctx, ctx->b_sorted, sizeof(PosT) * (n_ext + 1)));
-    STCHK(ensure(ctx, ctx->b_misc, sizeof(int32_t) * n_ext));
-    STCHK(ensure(ctx, ctx->b_img, sizeof(char4) * n_ext));
-    int32_t *unordered = (int32_t *)ctx->b_misc.p;
-    k_scatter<<<ceil_div(n, TB), TB, 0, s>>>(n, (int32_t *)ctx->b_cell_of.p,
-                                              (int32_t *)ctx->b_rank.p, start, unordered);
-    STCHK(ensure(ctx, ctx->b_hstart, sizeof(int32_t) * g.ncell_ext));
-    k_fill<<<ceil_div(g.ncell_ext, TB / FILL_LANES), TB, 0, s>>>(
-        g, start, unordered, ctx->x, ctx->y, ctx->z, ctx->type, (PosT *)ctx->b_sorted.p,
-        (int32_t *)ctx->b_slot_of.p, (char4 *)ctx->b_img.p, (int32_t *)ctx->b_hstart.p);
+    if (!early || n_ext > cap) {
+        STCHK(ensure(ctx, ctx->b_sorted, sizeof(PosT) * (n_ext + 1)));
+        STCHK(ensure(ctx, ctx->b_misc, sizeof(int32_t) * n_ext));
+        STCHK(ensure(ctx, ctx->b_img, sizeof(char4) * n_ext));
+        cap = n_ext;
+        STCHK(scatter_fill());
+    }
     ctx->fx_valid = false;
     HIPCHK(ctx, hipGetLastError());
     ctx->grid = g;
