@@ -39,10 +39,10 @@ def run(start, count, samples, out, n_max, only=None):
                     cfgs = sysm.configs()
                     tab = np.full(len(cfgs), np.inf)
                     for name in only:
-                        k = names.index(name)
-                        sysm.set_config(cfgs[k])
+                        j = names.index(name)
+                        sysm.set_config(cfgs[j])
                         try:
-                            tab[k] = sysm.tune(mdlj.TUNE_FIXED, samples)[1]
+                            tab[j] = sysm.tune(mdlj.TUNE_FIXED, samples)[1]
                         except mdlj.MdljError:
                             pass  # not valid for this scene
                 else:
