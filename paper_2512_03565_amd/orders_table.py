@@ -11,10 +11,16 @@ Lorentz-Berthelot): Verlet cluster lists with clusters of 4 and 8, FP32 pair
 arithmetic with FP64 accumulation against the all-FP64 kernels; force-kernel
 time over --reps evaluations.
 
+sizes: the headline's scene (FCC at rho 0.75, rc 2.5, skin 0.3, T 1.0)
+from 32k to 16M particles on one GPU, each tuned by the full search and
+then run for --steps velocity-Verlet steps: what one GPU's share of a
+larger system costs at each size.
+
 Prints one JSON line per row.
 
     python -m paper_2512_03565_amd.orders_table orders --steps 200
     python -m paper_2512_03565_amd.orders_table precision --reps 20
+    python -m paper_2512_03565_amd.orders_table sizes --steps 100
 """
 import argparse
 import json
@@ -97,15 +103,64 @@ def precision(reps):
                                   "force_us": us, "mpairs_per_s": pairs / us}), flush=True)
 
 
+# the largest as a cube: its box (280 sigma) stays inside the FP32 staged
+# kernel's fixed-point frame, which a 220 x 220 x 440 box of the same
+# count would leave
+SIZES = [(16, 16, 32), (32, 32, 64), (50, 50, 100), (80, 80, 160), (160, 160, 160)]
+
+
+def sizes(steps):
+    import torch
+    from paper_2512_03565_amd import mdlj, scenes
+    for nc in SIZES:
+        pos_h, box = scenes.fcc_lattice(nc[0], nc[1], nc[2], 0.75, 0.05, 1013)
+        n = len(pos_h)
+        vel0 = scenes.mb_velocities(n, 1.0, 1.0, seed=1014)
+        pos = torch.tensor(pos_h, dtype=torch.float64, device="cuda")
+        del pos_h
+        with mdlj.System(pos, box, 2.5, skin=0.3, rebuild_every=10,
+                         stream=torch.cuda.current_stream()) as sysm:
+            pairs = sysm.count_pairs()
+            t0 = time.perf_counter()
+            cfg, tuned_us = sysm.tune(mdlj.TUNE_EXHAUSTIVE, 4)
+            tune_s = time.perf_counter() - t0
+            vel = [torch.tensor(np.ascontiguousarray(vel0[:, k]), device="cuda") for k in range(3)]
+            sysm.step_vv(vel, 0.002, 10)
+            torch.cuda.synchronize()
+            sysm.set_timing(True)
+            t0 = time.perf_counter()
+            sysm.step_vv(vel, 0.002, steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            f_us, b_us, nf, nb = sysm.get_timing()
+            fused_us, nfused = sysm.get_timing_fused()
+            sysm.set_timing(False)
+        print(json.dumps({"table": "sizes", "fcc_cells": list(nc), "particles": n,
+                          "useful_pairs": pairs, "config": mdlj.config_name(cfg),
+                          "tuning_s": tune_s, "steps": steps, "ms_per_step": 1e3 * wall / steps,
+                          "mpairs_per_s": pairs * steps / wall / 1e6,
+                          "ns_per_particle_step": 1e9 * wall / steps / n,
+                          "force_us": f_us / max(nf, 1),
+                          "fused_us": fused_us / nfused if nfused else None,
+                          "rebuild_us": b_us / max(nb, 1)}), flush=True)
+        del pos, vel, sysm
+        torch.cuda.empty_cache()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("table", choices=["orders", "precision"])
+    ap.add_argument("table", choices=["orders", "precision", "sizes"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--scene", choices=["100k", "1M"], default="100k")
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
     a = ap.parse_args(argv)
-    orders(a.steps, a.scene, a.prec) if a.table == "orders" else precision(a.reps)
+    if a.table == "orders":
+        orders(a.steps, a.scene, a.prec)
+    elif a.table == "precision":
+        precision(a.reps)
+    else:
+        sizes(a.steps)
     return 0
 
 
