@@ -607,7 +607,8 @@ mdlj_status mdlj_destroy(mdlj_ctx *ctx)
                       &ctx->b_xref,    &ctx->b_mlp,     &ctx->b_feat,    &ctx->b_halo,    &ctx->b_hstart,
                       &ctx->b_vsort,   &ctx->b_vsort2,  &ctx->b_xrsort,  &ctx->b_tinv,
                       &ctx->b_sorted2, &ctx->b_fxrec, &ctx->b_fxrec2, &ctx->b_fxspec,
-                      &ctx->b_tunev,   &ctx->b_nbr_in,  &ctx->b_nlen_in, &ctx->b_tilebad};
+                      &ctx->b_tunev,   &ctx->b_nbr_in,  &ctx->b_nlo_in,  &ctx->b_tilebad,
+                      &ctx->b_nlo};
     for (DevBuf *b : bufs) free_buf(*b);
     delete ctx;
     return MDLJ_OK;

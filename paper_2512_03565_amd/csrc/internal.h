@@ -122,7 +122,7 @@ constexpr int STAGE_K = 4;
 // word is clear.
 struct InnerList {
     const uint16_t *nbr;
-    const int32_t *len;
+    const int2 *lo;           // per row: length, start less t cap
     const int32_t *tile_cur;  // null: no inner list
     int32_t *tile_next;       // written by the fused integrator step
 };
@@ -251,7 +251,7 @@ struct mdlj_ctx {
         b_partial, b_flags, b_nbr, b_nlen, b_ref, b_disp, b_misc, b_clu, b_cpair, b_cstart,
         b_fold, b_cnt_ext, b_img, b_icnt, b_ilist, b_xref, b_mlp, b_feat, b_halo, b_hstart, b_vsort,
         b_vsort2, b_xrsort, b_tinv, b_sorted2, b_fxrec, b_fxrec2, b_fxspec, b_tunev, b_nbr_in,
-        b_nlen_in, b_tilebad;
+        b_nlo_in, b_tilebad, b_nlo;
     int64_t nhalo = 0;            // entries of b_halo
     int halo_key[6] = {0, 0, 0, 0, 0, 0};  // grid (n, h) the halo list was made for
 
@@ -310,7 +310,7 @@ struct mdlj_ctx {
     bool fx_valid = false;
     double fx_c[3] = {0, 0, 0}, fx_s = 0.0;
     // pruned inner list of the staged Verlet-list kernels (b_nbr_in,
-    // b_nlen_in; two copies of inner_ntiles tile words in b_tilebad): prune
+    // b_nlo_in; two copies of inner_ntiles tile words in b_tilebad): prune
     // enables it; inner: 1 when the list build wrote one for the current
     // lists; inner_par: the copy launches read now
     bool prune = false;

@@ -87,6 +87,9 @@ __global__ __launch_bounds__(256) void k_vl_build(const PosT *__restrict__ rec,
 // and one halo cell either side), the order in which the force kernel
 // stages them into LDS; 16 bits, row-major per i, padded to a multiple of 8
 // with the index one past the staged particles (a far-away padding entry).
+// The staged kernel reads each row's length and start from lo[t] = {len[t],
+// start of row t less t cap}: the tiled build packs the rows of a tile,
+// this per-particle build leaves each at t cap.
 
 __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__ rec,
                                                         const int32_t *__restrict__ start,
@@ -95,6 +98,7 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
                                                         Grid g, int64_t n, double rl2,
                                                         int32_t cap, uint16_t *__restrict__ nbr,
                                                         int32_t *__restrict__ len,
+                                                        int2 *__restrict__ lo,
                                                         int32_t *__restrict__ maxlen,
                                                         int32_t *__restrict__ maxnb)
 {
@@ -135,6 +139,7 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
         }
         for (int32_t k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k) out[k] = (uint16_t)base;
         len[t] = cnt;
+        lo[t] = make_int2(cnt, 0);
     }
     for (int o = 32; o > 0; o >>= 1) {
         cnt = max(cnt, __shfl_xor(cnt, o));
@@ -155,6 +160,16 @@ __global__ __launch_bounds__(256) void k_vl_build_local(const PosT *__restrict__
 // contiguous run.  The lists equal those of the per-particle builds above
 // entry for entry (a partner at distance zero, which only the particle
 // itself can be, is left out by the distance test).
+//
+// Local rows are packed: the rows a wavefront writes (its i's, every NW-th
+// of the tile) follow one another, each from where the last one ended
+// (its length rounded up to 8 entries, at most cap), inside a region of
+// cap entries per row that follows the regions of the lower wavefronts; a
+// tile's rows then fill one run of the array from t0 cap on, and a reader
+// fetches no unused row capacity.  lo[t] holds the row's length and its
+// start less t cap.  Which wavefront takes which i is fixed, so the layout is the same
+// on every build of the same lists.
+//
 // LOCAL: 16-bit staged indices, rows padded with C (the staged count);
 // otherwise sorted-record slots at nbr[t * st + k * sk], padded with `pad`.
 // HALF keeps partners with a larger caller index only.
@@ -243,8 +258,8 @@ static_assert(2 * MDLJ_WAVE + 9 * (STAGE_K + 2) <= BUILD_TB, "tile too wide for 
 static_assert(2 * STAGE_K <= 16, "tile too wide for the set-up");
 
 // INNER (local lists only): the pruned inner list too, the entries closer
-// than sqrt(rin2) in list order, into rows of in_nbr (same layout) and
-// lengths in_len.
+// than sqrt(rin2) in list order, into rows of in_nbr (same layout, packed
+// the same way, with lengths and starts in in_lo).
 template <bool LOCAL, bool HALF, bool ELL, bool INNER>
 __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     const PosT *__restrict__ rec, const int32_t *__restrict__ start,
@@ -252,7 +267,8 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
     double rl2, int trim, int cmax, int ccand, int64_t n, int32_t cap, int32_t pad,
     void *__restrict__ nbr_out, int32_t *__restrict__ len, int32_t *__restrict__ maxlen,
     int32_t *__restrict__ maxnb, int32_t *__restrict__ maxnc, int remap,
-    uint16_t *__restrict__ in_nbr, int32_t *__restrict__ in_len, double rin2)
+    uint16_t *__restrict__ in_nbr, double rin2,
+    int2 *__restrict__ lo, int2 *__restrict__ in_lo)
 {
     static_assert(!INNER || (LOCAL && !HALF && !ELL), "inner lists are local full lists");
     constexpr int NW = BUILD_TB / MDLJ_WAVE;
@@ -403,6 +419,15 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
 #pragma unroll
     for (int q = 0; q < STAGE_K - 1; ++q) cs[q] = q + 1 < ncx ? rs[4][q + 2] : INT_MAX;
     int32_t wmax = 0;
+    // local rows: the start of the wavefront's region (rows of the lower
+    // wavefronts, cap entries each) and of its next row, from t0 cap on
+    int64_t ro = 0, rio = 0;
+    if constexpr (LOCAL) {
+        const int m = ie - ib;
+        int rows = 0;
+        for (int w = 0; w < wv; ++w) rows += w < m ? (m - 1 - w) / NW + 1 : 0;
+        ro = rio = (int64_t)rows * cap;
+    }
     // The wavefront's i's are ib + wv + NW k.  Their set-up (staged index,
     // candidate list, coordinates) is done for up to 64 of them at once, one
     // per lane, and read back one i at a time with readlane.
@@ -437,9 +462,9 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
             const int pb = __builtin_amdgcn_readlane(pb_l, k);
             const int pe = __builtin_amdgcn_readlane(pe_l, k);
             const int64_t t = t0 + (i - ib);
-            uint16_t *row16 = (uint16_t *)nbr_out + t * cap;
+            uint16_t *row16 = (uint16_t *)nbr_out + t0 * cap + ro;
             int32_t *row32 = (int32_t *)nbr_out + (ELL ? t : t * cap);
-            uint16_t *irow = INNER ? in_nbr + t * cap : nullptr;
+            uint16_t *irow = INNER ? in_nbr + t0 * cap + rio : nullptr;
             uint32_t cnt = 0, icnt = 0;
             // two trips of 64 candidates in flight; the list is padded to
             // whole trips with the padding record, which no test passes
@@ -511,11 +536,16 @@ __global__ __launch_bounds__(BUILD_TB) void k_vl_build_tile(
                     row32[ELL ? (int64_t)q * n : q] = pad;
             }
             if (lane == 0) len[t] = (int32_t)cnt;
+            if constexpr (LOCAL) {
+                if (lane == 0) lo[t] = make_int2((int)cnt, (int)(ro - (int64_t)(i - ib) * cap));
+                ro += pe8;
+            }
             if constexpr (INNER) {
                 const int32_t ie8 = min((int32_t)((icnt + 7) & ~7u), cap);
                 const int32_t qi = (int32_t)icnt + lane;
                 if (qi < ie8) irow[qi] = (uint16_t)C;
-                if (lane == 0) in_len[t] = (int32_t)icnt;
+                if (lane == 0) in_lo[t] = make_int2((int)icnt, (int)(rio - (int64_t)(i - ib) * cap));
+                rio += ie8;
             }
             wmax = max(wmax, (int32_t)cnt);
         }
@@ -680,7 +710,7 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
                                             const int32_t *__restrict__ start,
                                             const int32_t *__restrict__ ibase, const Grid &g,
                                             int tiles_x, const uint16_t *__restrict__ nbr_full,
-                                            const int32_t *__restrict__ len_full, int32_t cap,
+                                            const int2 *__restrict__ lo_full, int32_t cap,
                                             int64_t n, int cmax, const LJTable<T> &tab,
                                             const ForceOut &fo, int remap, double fxs,
                                             const FxWords *__restrict__ fxr,
@@ -725,7 +755,7 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
         use_in = __builtin_amdgcn_readfirstlane(il.tile_cur[tile]) == 0;
     }
     const uint16_t *__restrict__ nbr = use_in ? il.nbr : nbr_full;
-    const int32_t *__restrict__ len = use_in ? il.len : len_full;
+    const int2 *__restrict__ lo = use_in ? il.lo : lo_full;
     const int64_t ei = (int64_t)(cy + g.h[1]) * g.stride[1] + (int64_t)(cz + g.h[2]) * g.stride[2] +
                        cx0 + g.h[0];
     const int ib = start[ei], ie = start[ei + ncx];
@@ -787,9 +817,10 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
         }
     };
     load_kd();
-    int32_t L = len[min(t, n - 1)];
-    L = act ? L : 0;
-    uint32_t vo = (uint32_t)(((t - t0) * cap + V * l) * 2);
+    // row t: its length and its start less t cap (tile-packed rows)
+    const int2 q = lo[min(t, n - 1)];
+    int32_t L = act ? q.x : 0;
+    uint32_t vo = (uint32_t)(((t - t0) * cap + q.y + V * l) * 2);
     uint4 wa = list_words<V>(lr, vo);
     uint4 wb = list_words<V>(lr, vo + 2 * KS);
     __syncthreads();
@@ -854,9 +885,9 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
             load_i(act ? i : ib);
             load_kd();
             frame(xi, yi, zi);
-            L = len[min(t, n - 1)];
-            L = act ? L : 0;
-            vo = (uint32_t)(((t - t0) * cap + V * l) * 2);
+            const int2 qn = lo[min(t, n - 1)];
+            L = act ? qn.x : 0;
+            vo = (uint32_t)(((t - t0) * cap + qn.y + V * l) * 2);
             wa = list_words<V>(lr, vo);
             wb = list_words<V>(lr, vo + 2 * KS);
         }
@@ -978,14 +1009,14 @@ __device__ __forceinline__ void vl_lds_body(const PosT *__restrict__ rec,
 #define VL_LDS_PARAMS                                                                            \
     const PosT *__restrict__ rec, const int32_t *__restrict__ start,                            \
         const int32_t *__restrict__ ibase, Grid g, int tiles_x, const uint16_t *__restrict__ nbr, \
-        const int32_t *__restrict__ len, int32_t cap, int64_t n, int cmax, LJTable<T> tab,      \
+        const int2 *__restrict__ lo, int32_t cap, int64_t n, int cmax, LJTable<T> tab,          \
         ForceOut fo, int remap, double fxs, const FxWords *__restrict__ fxr,                     \
         const int32_t *__restrict__ fxspec, KickArgs ka, InnerList il
 
 template <typename T, bool E, bool MS, int G, int V, bool KD>
 __global__ __launch_bounds__(VL_LDS_TB) void k_vl_lds(VL_LDS_PARAMS)
 {
-    vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, len, cap, n, cmax, tab, fo,
+    vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, lo, cap, n, cmax, tab, fo,
                                     remap, fxs, fxr, fxspec, ka, il);
 }
 
@@ -997,7 +1028,7 @@ template <typename T, bool E, bool MS, int G, int V, bool KD>
 __global__ __launch_bounds__(VL_LDS_TB) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 k_vl_lds_w8(VL_LDS_PARAMS)
 {
-    vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, len, cap, n, cmax, tab, fo,
+    vl_lds_body<T, E, MS, G, V, KD>(rec, start, ibase, g, tiles_x, nbr, lo, cap, n, cmax, tab, fo,
                                     remap, fxs, fxr, fxspec, ka, il);
 }
 #undef VL_LDS_PARAMS
@@ -1233,6 +1264,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         const int64_t nbt = (int64_t)tiles_x * g.n[1] * g.n[2];
         const int32_t *ibase = (const int32_t *)ctx->b_icnt.p + g.ncell_int + 1;
         const uint16_t *nbr16 = (const uint16_t *)ctx->b_nbr.p;
+        const int2 *lo = (const int2 *)ctx->b_nlo.p;
         const int32_t *start = (const int32_t *)ctx->b_start.p;
         // the fused integrator step only with forces alone (no energies)
         const bool kd = kdp != nullptr && !E;
@@ -1240,7 +1272,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         InnerList il = {};
         if (ctx->inner == 1) {
             il.nbr = (uint16_t *)ctx->b_nbr_in.p;
-            il.len = (int32_t *)ctx->b_nlen_in.p;
+            il.lo = (const int2 *)ctx->b_nlo_in.p;
             int32_t *tw = (int32_t *)ctx->b_tilebad.p;
             il.tile_cur = tw + ctx->inner_par * nbt;
             il.tile_next = tw + (ctx->inner_par ^ 1) * nbt;
@@ -1254,7 +1286,7 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         if constexpr (FX && !MS && GG >= 8) {                                                   \
             if (kd) {                                                                           \
                 k_vl_lds_w8<T, false, MS, GG, VV, true><<<nbt, VL_LDS_TB, lds, s>>>(            \
-                    rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, \
+                    rec, start, ibase, g, tiles_x, nbr16, lo, cap, n, cmax, tx, fo, remap, fxs, \
                     fxr, fxspec, kk, il);                                                       \
                 done = true;                                                                    \
             }                                                                                   \
@@ -1262,11 +1294,11 @@ int64_t launch_vl(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &tab, 
         if (done) break;                                                                        \
         if (kd)                                                                                 \
             k_vl_lds<T, false, MS, GG, VV, true><<<nbt, VL_LDS_TB, lds, s>>>(                   \
-                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr,   \
+                rec, start, ibase, g, tiles_x, nbr16, lo, cap, n, cmax, tx, fo, remap, fxs, fxr,   \
                 fxspec, kk, il);                                                                \
         else                                                                                    \
             k_vl_lds<T, E, MS, GG, VV, false><<<nbt, VL_LDS_TB, lds, s>>>(                      \
-                rec, start, ibase, g, tiles_x, nbr16, len, cap, n, cmax, tx, fo, remap, fxs, fxr,   \
+                rec, start, ibase, g, tiles_x, nbr16, lo, cap, n, cmax, tx, fo, remap, fxs, fxr,   \
                 fxspec, none, il);                                                              \
     } while (0)
         switch (key) {
@@ -1369,17 +1401,18 @@ mdlj_status launch_build_tile(mdlj_ctx *ctx, bool local, bool half, bool ell, do
     const int64_t n = ctx->n;
     hipStream_t s = ctx->stream;
     uint16_t *in_nbr = inner ? (uint16_t *)ctx->b_nbr_in.p : nullptr;
-    int32_t *in_len = inner ? (int32_t *)ctx->b_nlen_in.p : nullptr;
+    int2 *lo = local ? (int2 *)ctx->b_nlo.p : nullptr;
+    int2 *in_lo = inner ? (int2 *)ctx->b_nlo_in.p : nullptr;
 #define VL_BT(L, H, E)                                                                          \
     k_vl_build_tile<L, H, E, false><<<nbt, BUILD_TB, lds, s>>>(                                 \
         rec, start, hstart, ibase, g, tiles_x, rl2, trim ? 1 : 0, cmax, ccand, n, cap, pad, nbr, \
-        len, maxlen, maxnb, maxnc, 1, nullptr, nullptr, 0.0)
+        len, maxlen, maxnb, maxnc, 1, nullptr, 0.0, lo, nullptr)
     if (local) {
         if (half || ell) return set_err(ctx, MDLJ_ERR_ARG, "local lists are full row-major lists");
         if (inner)
             k_vl_build_tile<true, false, false, true><<<nbt, BUILD_TB, lds, s>>>(
                 rec, start, hstart, ibase, g, tiles_x, rl2, trim ? 1 : 0, cmax, ccand, n, cap, pad,
-                nbr, len, maxlen, maxnb, maxnc, 1, in_nbr, in_len, rin2);
+                nbr, len, maxlen, maxnb, maxnc, 1, in_nbr, rin2, lo, in_lo);
         else
             VL_BT(true, false, false);
     } else if (ell) {
@@ -1424,7 +1457,8 @@ __global__ __launch_bounds__(256) void k_vl_pairs(const PosT *__restrict__ rec,
                                                   const int32_t *__restrict__ ilist,
                                                   const int32_t *__restrict__ cell_of, Grid g,
                                                   int64_t n, int64_t nrec, const void *nbr,
-                                                  const int32_t *__restrict__ len, int32_t cap,
+                                                  const int32_t *__restrict__ len,
+                                                  const int2 *__restrict__ lo, int32_t cap,
                                                   int layout, const int64_t *__restrict__ off,
                                                   int32_t *__restrict__ pi,
                                                   int32_t *__restrict__ pj)
@@ -1454,7 +1488,7 @@ __global__ __launch_bounds__(256) void k_vl_pairs(const PosT *__restrict__ rec,
     for (int32_t k = 0; k < L; ++k) {
         int64_t sj = -1;
         if (layout == 2) {
-            int32_t q = ((const uint16_t *)nbr)[t * cap + k];
+            int32_t q = ((const uint16_t *)nbr)[t * cap + lo[t].y + k];
             for (int r = 0; r < 9 && sj < 0; ++r) {
                 if (q < rl[r]) sj = rb[r] + q;
                 else q -= rl[r];
@@ -1521,6 +1555,8 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
     if (ctx->nbr_cap > cap && ctx->built_cfg.newton3 == cfg.newton3) cap = ctx->nbr_cap;
     cap = (cap + 7) & ~(int64_t)7;
     STCHK(ensure(ctx, ctx->b_nlen, sizeof(int32_t) * n));
+    // local lists: each row's length and start for the staged kernel
+    if (cfg.staged) STCHK(ensure(ctx, ctx->b_nlo, sizeof(int2) * n));
     int32_t *maxlen = (int32_t *)ctx->b_flags.p + 12;
     int32_t *maxnb = (int32_t *)ctx->b_flags.p + 14;
     const bool rowmajor = cfg.order != MDLJ_ORD_I_PER_LANE;
@@ -1580,12 +1616,12 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
         bool inner = false;
         const int64_t ntiles = ceil_div(g.n[0], STAGE_K) * g.n[1] * g.n[2];
         if (tiled && local && !cfg.newton3 && ctx->prune && ctx->skin > 0.0) {
-            const size_t ib = esize * (size_t)(n * cap + slack), lb = sizeof(int32_t) * (size_t)n;
+            const size_t ib = esize * (size_t)(n * cap + slack), lb = sizeof(int2) * (size_t)n;
             const size_t tb = 2 * sizeof(int32_t) * (size_t)ntiles;
-            if (!ctx->no_alloc || (ctx->b_nbr_in.bytes >= ib && ctx->b_nlen_in.bytes >= lb &&
+            if (!ctx->no_alloc || (ctx->b_nbr_in.bytes >= ib && ctx->b_nlo_in.bytes >= lb &&
                                    ctx->b_tilebad.bytes >= tb)) {
                 STCHK(ensure(ctx, ctx->b_nbr_in, ib));
-                STCHK(ensure(ctx, ctx->b_nlen_in, lb));
+                STCHK(ensure(ctx, ctx->b_nlo_in, lb));
                 STCHK(ensure(ctx, ctx->b_tilebad, tb));
                 inner = true;
             }
@@ -1598,7 +1634,8 @@ mdlj_status vl_build(mdlj_ctx *ctx, const mdlj_config &cfg)
             k_vl_build_local<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
                 (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
                 (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, g, n, rl * rl,
-                (int32_t)cap, (uint16_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p, maxlen, maxnb);
+                (int32_t)cap, (uint16_t *)ctx->b_nbr.p, (int32_t *)ctx->b_nlen.p,
+                (int2 *)ctx->b_nlo.p, maxlen, maxnb);
         } else {
             k_vl_build<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
                 (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
@@ -1695,7 +1732,8 @@ mdlj_status vl_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj, int64
         k_vl_pairs<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(
             (const PosT *)ctx->b_sorted.p, (const int32_t *)ctx->b_start.p,
             (const int32_t *)ctx->b_ilist.p, (const int32_t *)ctx->b_cell_of.p, ctx->grid, n,
-            ctx->n_ext, ctx->b_nbr.p, (const int32_t *)ctx->b_nlen.p, (int32_t)ctx->nbr_cap, layout,
+            ctx->n_ext, ctx->b_nbr.p, (const int32_t *)ctx->b_nlen.p,
+            layout == 2 ? (const int2 *)ctx->b_nlo.p : nullptr, (int32_t)ctx->nbr_cap, layout,
             d_off, d_out, d_out + total);
         e = hipGetLastError();
     }
