@@ -91,7 +91,11 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2,
  *                VL/VCL: unused (0).
  *   CLUSTER_TILE tile_i x tile_j = 64 lanes of one wavefront, tile_i i's and
  *                tile_j j's per step (LC: 16x4, 8x8; VCL: cluster_size x
- *                64/cluster_size).
+ *                64/cluster_size), or for VCL also cluster_size x 4 lanes
+ *                per cluster pair with 64/(4 cluster_size) cluster pairs
+ *                (each its own cluster I) per wavefront: 4x4 x 4 pairs for
+ *                cluster size 4, 8x4 x 2 pairs for cluster size 8 (the
+ *                4 j-lanes then take half of a j-cluster per step).
  *   WAVE_PER_I   tile_i = g, the i-particles per wavefront (LC: 1, 2, 4;
  *                VL: 1, 2, 4, 8, 16); each gets 64/g lanes.  tile_j = 64/g,
  *                except for staged VL, where tile_j = v, the list entries
@@ -124,9 +128,9 @@ enum { MDLJ_TUNE_FIXED = 0, MDLJ_TUNE_EXHAUSTIVE = 1, MDLJ_TUNE_LEARNED = 2,
  * 16x4: tile_i i's per step, tile_j lanes each over its partners); swap =
  * 1, the partners (I_PER_LANE, tile_i = 1: each lane one partner, the own
  * particles broadcast to all lanes).  VCL CLUSTER_TILE: swap = 0 runs the
- * lanes over j fastest (the 2/(VL/2) fill widened to 64 lanes), swap = 1
- * over i fastest (the (VL/2)/2 fill), both cluster_size i's by
- * 64/cluster_size j's.  swap is 0 for every other configuration.
+ * lanes of a cluster pair over j fastest (the 2/(VL/2) fill widened), swap
+ * = 1 over i fastest (the (VL/2)/2 fill), both cluster_size i's by tile_j
+ * j's.  swap is 0 for every other configuration.
  */
 typedef struct {
     int32_t nbr_algo;
@@ -294,7 +298,10 @@ mdlj_status mdlj_neighbor_stats(mdlj_ctx *ctx, int64_t *list_entries, int32_t *e
  *     64-lane wavefronts (*layout receives 0 or 1): i-per-lane orders take
  *     layout 1 with 64 i's; wave-per-i and the linked-cell tiles layout 0
  *     with tile_i i's; the VCL cluster tiles layout swap with cluster_size
- *     i's.  The kernels take their lane offsets from the same function.
+ *     i's, and with several cluster pairs per wavefront the lanes in groups
+ *     of tile_i x tile_j, group q mapped like one pair's lanes with i and j
+ *     offset by q tile_i and q tile_j.  The kernels take their lane offsets
+ *     from the same function.
  */
 mdlj_status mdlj_lane_map(int32_t layout, int32_t ai, int32_t width, int32_t lane, int32_t *i,
                           int32_t *j);
@@ -345,11 +352,13 @@ mdlj_status mdlj_get_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj,
  * first and averages the rest, the lower index winning ties; LEARNED asks
  * the network and falls back to EXHAUSTIVE when its confidence is below the
  * threshold set by mdlj_mlp_set_threshold (default 0.6) or no network is
- * loaded; EARLY_STOP is the full search with early stopping (the decision
+ * loaded (a network of K classes chooses among the first K configurations
+ * of config_at order; its fallback searches them all); EARLY_STOP is the full search with early stopping (the decision
  * rule of mdlj_tune_select_early with warm_factor +inf, i.e. the warm-up
  * cycle is not judged, and margin 0.1), the
  * configurations visited by descending network probability when a network
- * for this search space is loaded, else in config_at order.  The chosen
+ * is loaded (configurations beyond its K classes last, in config_at order),
+ * else in config_at order.  The chosen
  * configuration is made current; *chosen and *step_us (microseconds per MD
  * step of the chosen one, may be NULL) are written.  The context's kernel
  * timing (mdlj_set_timing) does not count the tuning steps.
@@ -473,7 +482,9 @@ mdlj_status mdlj_features(mdlj_ctx *ctx, float *features8);
 
 /*
  * Learned tuner (data-driven tuning, section 6): a network 8 -> 64 -> 64 ->
- * K (ReLU, softmax over the K configurations of config_at order), FP32,
+ * K (ReLU, softmax over the first K configurations of config_at order: a
+ * network trained before configurations were added to the end of the
+ * search space keeps choosing among those it knows), FP32,
  * trained and evaluated on the device by the library's own kernels.
  * Parameters are one flat float array W1[64][8] b1[64] W2[64][64] b2[64]
  * W3[K][64] b3[K] (row-major [out][in]); inputs are z-scored with a stored

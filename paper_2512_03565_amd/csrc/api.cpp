@@ -150,6 +150,12 @@ static std::vector<mdlj_config> build_space()
             // the same tile with the lanes running over i fastest
             v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_CLUSTER_TILE, m, 64 / m, m, n3, 0, 1});
         }
+    // Verlet cluster lists, a second tile shape: cluster_size x 4 lanes per
+    // cluster pair, 64 / (4 cluster_size) cluster pairs per wavefront (after
+    // the shapes above, so that their indices stay as they were)
+    for (int m : {4, 8})
+        for (int n3 : {0, 1})
+            for (int sw : {0, 1}) v.push_back({MDLJ_NBR_VCL, MDLJ_ORD_CLUSTER_TILE, m, 4, m, n3, 0, sw});
     return v;
 }
 
@@ -932,6 +938,18 @@ mdlj_status mdlj_config_lane_map(const mdlj_config *cfg, int32_t lane, int32_t *
     } else if (cfg->nbr_algo == MDLJ_NBR_VCL) {
         lay = cfg->swap ? LANE_J_MAJOR : LANE_I_MAJOR;
         ai = cfg->cluster_size;
+        // several cluster pairs per wavefront: lane groups of tile_i x
+        // tile_j lanes, group q with its own cluster (i offset q tile_i)
+        // and its own j-lanes (offset q tile_j)
+        const int w = cfg->tile_i * cfg->tile_j;
+        if (cfg->tile_i == ai && cfg->tile_j >= 1 && w < MDLJ_WAVE && w >= 1 && MDLJ_WAVE % w == 0) {
+            const int q = lane / w;
+            const LanePair p = lane_pair(lay, ai, w, lane % w);
+            *layout = lay;
+            *i = q * cfg->tile_i + p.i;
+            *j = q * cfg->tile_j + p.j;
+            return MDLJ_OK;
+        }
     } else {
         ai = cfg->tile_i;
     }

@@ -317,10 +317,18 @@ mdlj_status features_dev(mdlj_ctx *ctx, float *f8)
     return MDLJ_OK;
 }
 
+// A network covers the first mlp_k configurations of the search space
+// (configurations added to the space after it was trained come after those
+// it knows, so its output k still names space[k]).
+static bool mlp_usable(const mdlj_ctx *ctx)
+{
+    return ctx->mlp_loaded && ctx->mlp_k >= 1 && ctx->mlp_k <= (int)ctx->space.size();
+}
+
 mdlj_status mlp_rank(mdlj_ctx *ctx, std::vector<int> &order)
 {
     order.clear();
-    if (!ctx->mlp_loaded || ctx->mlp_k != (int)ctx->space.size()) return MDLJ_OK;
+    if (!mlp_usable(ctx)) return MDLJ_OK;
     float f[DIN];
     STCHK(features_dev(ctx, f));
     std::vector<float> xn;
@@ -330,6 +338,8 @@ mdlj_status mlp_rank(mdlj_ctx *ctx, std::vector<int> &order)
     order.resize(ctx->mlp_k);
     for (int k = 0; k < ctx->mlp_k; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p[a] > p[b]; });
+    // configurations the network does not know, after those it ranks
+    for (int k = ctx->mlp_k; k < (int)ctx->space.size(); ++k) order.push_back(k);
     return MDLJ_OK;
 }
 
@@ -337,8 +347,7 @@ mdlj_status tune_learned(mdlj_ctx *ctx, int samples, mdlj_config *chosen, double
 {
     // the network predicts the fastest configuration: under the energy
     // metric the full search decides
-    if (!ctx->mlp_loaded || ctx->mlp_k != (int)ctx->space.size() ||
-        ctx->tune_metric != MDLJ_METRIC_TIME)
+    if (!mlp_usable(ctx) || ctx->tune_metric != MDLJ_METRIC_TIME)
         return tune_exhaustive(ctx, samples, chosen, us);
     float f[DIN];
     STCHK(features_dev(ctx, f));

@@ -340,20 +340,26 @@ struct BoxL {
     double L[3];
 };
 
-// Cluster tile: M x (64/M) lanes; one wavefront per cluster I.  JMAJOR =
-// false: lanes run over j fastest (the 2/(VL/2) fill widened: lane l takes
-// i = l / (64/M) and j-lane l % (64/M)); JMAJOR = true: over i fastest (the
-// (VL/2)/2 fill widened: i = l % M, j-lane l / M).  A j-lane b covers list
-// entry b / M of the step and member b % M of that entry's cluster.
-template <typename T, bool E, bool MS, bool N3, int M, bool JMAJOR>
+// Cluster tile: M x AJ lanes per cluster pair, QI = 64 / (M AJ) cluster
+// pairs per wavefront (M x 64/M: one cluster I per wavefront; M x 4: four
+// for M = 4, two for M = 8), each in its own group of W = M AJ lanes with
+// its own cluster I.  JMAJOR = false: within a group lanes run over j
+// fastest (the 2/(VL/2) fill widened: lane l takes i = l / AJ and j-lane
+// l % AJ); JMAJOR = true: over i fastest (the (VL/2)/2 fill widened: i =
+// l % M, j-lane l / M).  The j-lanes walk I's list as j-slots, entry k and
+// member m of its cluster being slot k M + m: step s gives j-lane b slot
+// s AJ + b, so a step covers AJ / M entries when AJ >= M and a fraction
+// AJ / M of one entry's cluster when AJ < M.
+template <typename T, bool E, bool MS, bool N3, int M, bool JMAJOR, int AJ>
 __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
                                                   const int32_t *__restrict__ list,
                                                   const int32_t *__restrict__ len, int64_t nclu,
                                                   int32_t cap, BoxL bl, LJTable<T> tab,
                                                   ForceOut fo, int remap)
 {
-    constexpr int AJ = MDLJ_WAVE / M;    // j lanes per i
-    constexpr int JPS = AJ / M;          // list entries per step (1 for M=8, 4 for M=4)
+    constexpr int W = M * AJ;            // lanes per cluster pair
+    constexpr int QI = MDLJ_WAVE / W;    // cluster pairs per wavefront
+    static_assert(QI * W == MDLJ_WAVE && (AJ % M == 0 || M % AJ == 0), "tile shape");
     __shared__ LdsTable<T> lt;
     const double rc2 = tab.rc2d;
     if (MS) {
@@ -361,54 +367,80 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
         __syncthreads();
     }
     const int64_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int64_t I = b * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE;
     const int lane = threadIdx.x & (MDLJ_WAVE - 1);
+    const int64_t I = (b * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE) * QI + lane / W;
     constexpr int LAYOUT = JMAJOR ? LANE_J_MAJOR : LANE_I_MAJOR;
-    const LanePair lp = lane_pair(LAYOUT, M, MDLJ_WAVE, lane);
+    const LanePair lp = lane_pair(LAYOUT, M, W, lane % W);
     const int a = lp.i;                  // i within the cluster
     const int bj = lp.j;                 // j lane
-    const int eo = bj / M;               // which list entry of the step
-    const int m = bj % M;                // j within its cluster
     Acc acc;
     acc_zero(acc);
     const bool live = I < nclu;
     const int64_t islot = live ? I * M + a : 0;
     const PosT pi = crec[islot];
     const int32_t Ln = live ? len[I] : 0;
-    for (int32_t k00 = 0; k00 < Ln; k00 += JPS * UNROLL) {
+    // A step covers JPS whole list entries (AJ >= M: the j-lane's entry of
+    // the step is eo, its member m0 on every step) or 1/SPE of one entry
+    // (AJ < M: the member also depends on the step).  The loop runs in
+    // entries (AJ >= M) or steps (AJ < M), as far as the longest list of the
+    // wavefront's groups on every lane: the shuffles need all of them.
+    constexpr int JPS = AJ >= M ? AJ / M : 1;
+    constexpr int SPE = AJ >= M ? 1 : M / AJ;
+    constexpr int TRIP = (AJ >= M ? JPS : 1) * UNROLL;
+    const int eo = AJ >= M ? bj / M : 0;
+    const int m0 = AJ >= M ? bj % M : bj;
+    int32_t Lw = Ln;
+    if constexpr (QI > 1) {
+#pragma unroll
+        for (int o = W; o < MDLJ_WAVE; o <<= 1) Lw = max(Lw, __shfl_xor(Lw, o, MDLJ_WAVE));
+    }
+    const int32_t Tw = Lw * SPE;
+    for (int32_t t00 = 0; t00 < Tw; t00 += TRIP) {
         // U steps per trip: their list and record loads are in flight together
-        int32_t J[UNROLL];
+        int32_t J[UNROLL], m[UNROLL];
         double sx[UNROLL], sy[UNROLL], sz[UNROLL];
         bool ok[UNROLL];
         PosT pj[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int32_t k = k00 + u * JPS + eo;
+            int32_t k;                   // list entry
+            if constexpr (AJ >= M) {
+                k = t00 + u * JPS + eo;
+                m[u] = m0;
+            } else {
+                const int32_t st = t00 + u;
+                k = st / SPE;
+                m[u] = (st % SPE) * AJ + m0;
+            }
             ok[u] = k < Ln;
             J[u] = 0;
             sx[u] = sy[u] = sz[u] = 0.0;
             if (ok[u]) decode(list[I * cap + k], bl.L, J[u], sx[u], sy[u], sz[u]);
         }
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) pj[u] = crec[(int64_t)J[u] * M + m];
+        for (int u = 0; u < UNROLL; ++u) pj[u] = crec[(int64_t)J[u] * M + m[u]];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             // all lanes take part in the shuffles below; masked lanes add zero
-            if (k00 + u * JPS >= Ln) break;
-            const int64_t jslot = (int64_t)J[u] * M + m;
+            if (t00 + u * (TRIP / UNROLL) >= Tw) break;
+            // the member as a loop invariant where it is one (reading the
+            // array here would keep all its elements live)
+            const int mu = AJ >= M ? m0 : m[u];
+            const int64_t jslot = (int64_t)J[u] * M + mu;
             // self cluster without shift: skip the diagonal, and with Newton-3
             // the lower triangle
             const bool self0 = ok[u] && J[u] == I && sx[u] == 0.0 && sy[u] == 0.0 && sz[u] == 0.0;
-            const bool valid = ok[u] && !(self0 && (N3 ? m <= a : m == a));
+            const bool valid = ok[u] && !(self0 && (N3 ? mu <= a : mu == a));
             const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj[u].t);
             double fxp, fyp, fzp;
             lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x + sx[u], pj[u].y + sy[u], pj[u].z + sz[u], valid,
                           p, rc2, acc, fxp, fyp, fzp);
             if (N3) {
-                // -F on j summed over the M i-lanes that share it (lanes
-                // AJ apart for j fastest, adjacent lanes for i fastest)
+                // -F on j summed over the M i-lanes of its group that share
+                // it (lanes AJ apart for j fastest, adjacent lanes for i
+                // fastest)
                 double gx = -fxp, gy = -fyp, gz = -fzp;
-                const int o0 = JMAJOR ? 1 : AJ, o1 = JMAJOR ? M : MDLJ_WAVE;
+                const int o0 = JMAJOR ? 1 : AJ, o1 = JMAJOR ? M : W;
                 for (int o = o0; o < o1; o <<= 1) {
                     gx += __shfl_xor(gx, o, MDLJ_WAVE);
                     gy += __shfl_xor(gy, o, MDLJ_WAVE);
@@ -424,8 +456,8 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
         }
     }
     // F on i summed over its AJ j-lanes: adjacent lanes for j fastest,
-    // lanes M apart for i fastest
-    for (int o = JMAJOR ? M : 1; o < (JMAJOR ? MDLJ_WAVE : AJ); o <<= 1) {
+    // lanes M apart for i fastest (within the group)
+    for (int o = JMAJOR ? M : 1; o < (JMAJOR ? W : AJ); o <<= 1) {
         acc.fx += __shfl_xor(acc.fx, o, MDLJ_WAVE);
         acc.fy += __shfl_xor(acc.fy, o, MDLJ_WAVE);
         acc.fz += __shfl_xor(acc.fz, o, MDLJ_WAVE);
@@ -528,13 +560,25 @@ int64_t launch_vcl_m(mdlj_ctx *ctx, const mdlj_config &cfg, const LJTable<T> &ta
     hipStream_t s = ctx->stream;
     const int TB = 256;
     if (cfg.order == MDLJ_ORD_CLUSTER_TILE) {
-        const int64_t nb = ceil_div(nclu, TB / MDLJ_WAVE);
-        if (cfg.swap)
-            k_vcl_tile<T, E, MS, N3, M, true><<<nb, TB, 0, s>>>(crec, list, len, nclu, cap, bl, tab,
-                                                               fo, remap);
-        else
-            k_vcl_tile<T, E, MS, N3, M, false><<<nb, TB, 0, s>>>(crec, list, len, nclu, cap, bl,
-                                                                tab, fo, remap);
+        // tile_j = j-lanes per cluster pair: 64/M (one pair per wavefront)
+        // or 4 (64/(4M) pairs per wavefront)
+        if (cfg.tile_i != M || (cfg.tile_j != MDLJ_WAVE / M && cfg.tile_j != 4)) return -1;
+        const int qi = MDLJ_WAVE / (M * cfg.tile_j);
+        const int64_t nb = ceil_div(nclu, (int64_t)(TB / MDLJ_WAVE) * qi);
+#define VCL_TILE(SW, AJ)                                                                         \
+    k_vcl_tile<T, E, MS, N3, M, SW, AJ><<<nb, TB, 0, s>>>(crec, list, len, nclu, cap, bl, tab, fo, \
+                                                          remap)
+        if (cfg.tile_j == 4) {
+            if (cfg.swap)
+                VCL_TILE(true, 4);
+            else
+                VCL_TILE(false, 4);
+        } else if (cfg.swap) {
+            VCL_TILE(true, MDLJ_WAVE / M);
+        } else {
+            VCL_TILE(false, MDLJ_WAVE / M);
+        }
+#undef VCL_TILE
         return nb * (TB / MDLJ_WAVE);
     }
     const int64_t nb = ceil_div(nclu * M, TB);

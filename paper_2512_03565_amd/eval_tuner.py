@@ -60,7 +60,9 @@ def main(argv=None):
         with mdlj.System(s["pos"], s["box"], s["rc"], s["eps"], s["sig"], types=types,
                          skin=s["skin"], rebuild_every=s["rebuild_every"]) as sysm:
             space = [mdlj.config_name(c) for c in sysm.configs()]
-            if space != names:
+            # the sweep covers the library's space, or the part of it that
+            # existed when it was taken (configurations are only appended)
+            if space[:len(names)] != names:
                 raise ValueError("sweep and library configuration spaces differ")
             cfgs = sysm.configs()
             sysm.mlp_load(a.weights)

@@ -52,6 +52,9 @@ def config_name(c) -> str:
         s += f"/k{ti}"
     elif o != ORD_I_PER_LANE:
         s += f"/{ti}x{tj}"
+        if nb == NBR_VCL and 0 < ti * tj < 64:
+            # cluster pairs per wavefront
+            s += f"x{64 // (ti * tj)}"
     return s + ("/n3" if n3 else "") + ("/lds" if st else "") + ("/swap" if sw else "")
 
 

@@ -64,7 +64,7 @@ def test_config4_4m_two_species_cluster_lists_sampled(m, orc):
     full = orc.forces(pos, box, rc, s["eps"], s["sig"], types)
     assert np.allclose(full["f"][idx], sub["f"], rtol=0, atol=1e-12 * P.frms(full["f"]))
     names = ["VCL4/cluster-tile/4x16", "VCL8/cluster-tile/8x8", "VCL4/i-per-lane",
-             "VCL8/i-per-lane/n3"]
+             "VCL8/i-per-lane/n3", "VCL4/cluster-tile/4x4x4", "VCL8/cluster-tile/8x4x2/n3"]
     with m.System(pos, box, rc, s["eps"], s["sig"], types=types, skin=s["skin"],
                   rebuild_every=s["rebuild_every"]) as sysm:
         for prec in (0, 1):

@@ -1,7 +1,7 @@
 """GPU parity of the Verlet-cluster-list kernels (cluster size 4 and 8,
-cluster-tile and i-per-lane orders, with and without Newton-3) against the
-FP64 oracle, including small and sparse periodic boxes where a cluster pair
-is seen through several images."""
+cluster-tile orders of both tile shapes and i-per-lane, with and without
+Newton-3) against the FP64 oracle, including small and sparse periodic boxes
+where a cluster pair is seen through several images."""
 import numpy as np
 import pytest
 
@@ -23,8 +23,11 @@ def vcl_configs(m):
     for M in (4, 8):
         for n3 in (0, 1):
             out.append((m.NBR_VCL, m.ORD_I_PER_LANE, 0, 0, M, n3))
-            out.append((m.NBR_VCL, m.ORD_CLUSTER_TILE, M, 64 // M, M, n3))
-            out.append((m.NBR_VCL, m.ORD_CLUSTER_TILE, M, 64 // M, M, n3, 0, 1))
+            # one cluster pair per wavefront (M x 64/M lanes) and 64/(4M)
+            # pairs per wavefront (M x 4 lanes each), j or i fastest
+            for aj in (64 // M, 4):
+                out.append((m.NBR_VCL, m.ORD_CLUSTER_TILE, M, aj, M, n3))
+                out.append((m.NBR_VCL, m.ORD_CLUSTER_TILE, M, aj, M, n3, 0, 1))
     return out
 
 

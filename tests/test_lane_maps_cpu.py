@@ -72,6 +72,39 @@ def test_configuration_lane_maps(m, cfg, layout, ai):
         assert list(i[:8]) == list(range(8)) and list(j[:8]) == [0] * 8
 
 
+# VCL tiles with several cluster pairs per wavefront: (configuration, layout,
+# cluster size, j-lanes per pair)
+GROUPED = [
+    ((2, 1, 4, 4, 4, 0), 0, 4, 4),         # VCL4 4x4 x 4 pairs, j fastest
+    ((2, 1, 4, 4, 4, 1, 0, 1), 1, 4, 4),   # the same, i fastest, Newton 3
+    ((2, 1, 8, 4, 8, 0), 0, 8, 4),         # VCL8 8x4 x 2 pairs, j fastest
+    ((2, 1, 8, 4, 8, 0, 0, 1), 1, 8, 4),   # the same, i fastest
+]
+
+
+@pytest.mark.parametrize("cfg,layout,M,aj", GROUPED)
+def test_grouped_cluster_tile_lane_maps(m, cfg, layout, M, aj):
+    lay, i, j = m.config_lane_map(cfg)
+    assert lay == layout
+    w = M * aj
+    q = np.arange(64) // w
+    # each group of w lanes is one cluster pair: its own M i's and aj j-lanes
+    assert np.array_equal(i // M, q) and np.array_equal(j // aj, q)
+    # every (i, j) of each group's M x aj block exactly once
+    blocks = {(g * M + a, g * aj + b) for g in range(64 // w) for a in range(M) for b in range(aj)}
+    assert set(zip(i.tolist(), j.tolist())) == blocks and len(blocks) == 64
+    # inside a group, the one-pair map at width w
+    ei, ej = m.lane_map(layout, M, w)
+    for g in range(64 // w):
+        sl = slice(g * w, (g + 1) * w)
+        assert np.array_equal(i[sl] - g * M, ei) and np.array_equal(j[sl] - g * aj, ej)
+    # 4 j-lanes per pair, j fastest: the first 8 lanes are the 2/(VL/2) fill
+    # of the figure
+    if layout == 0:
+        g8 = json.load(open(GOLDEN))["2/4"]
+        assert list(i[:8]) == g8["i"] and list(j[:8]) == g8["j"]
+
+
 def test_lane_map_rejects_bad_shapes(m):
     with pytest.raises(m.MdljError):
         m.lane_map(0, 3, 8)
