@@ -87,3 +87,35 @@ def test_learned_tuner_close_to_full_search_and_cheaper(m):
     assert d.any()
     assert np.mean(np.array(t_learn)[d]) < 0.5 * np.mean(np.array(t_full)[d])
     assert np.mean(t_learn) < np.mean(t_full)
+
+
+def test_network_of_fewer_classes_than_the_space(m):
+    # A network of K classes chooses among the first K configurations of the
+    # search space (configurations added to the space later come after
+    # them); early stopping visits those it ranks first and then the rest.
+    from paper_2512_03565_amd import scenes
+    s = scenes.config1()
+    with m.System(s["pos"], s["box"], s["rc"], skin=0.3) as sysm:
+        cfgs = sysm.configs()
+        names = [m.config_name(c) for c in cfgs]
+        K = 3
+        sysm.mlp_init(K, seed=1)
+        w, k = sysm.mlp_params()
+        assert k == K < len(cfgs)
+        # all weights zero, the output biases make class 0 certain
+        w[:] = 0.0
+        w[-K:] = [20.0, 0.0, 0.0]
+        sysm.mlp_set_params(w, K)
+        _, fb0 = sysm.mlp_stats()
+        print(f"[learned] {K}-class network over {len(cfgs)} configurations", flush=True)
+        chosen, _ = sysm.tune(m.TUNE_LEARNED, 2)
+        conf, fb1 = sysm.mlp_stats()
+        assert fb1 == fb0 and conf > 0.99
+        assert chosen.astuple() == cfgs[0].astuple()
+        sysm.tune(m.TUNE_EARLY_STOP, 2)
+        taken = sysm.tune_taken()
+        assert len(taken) == len(cfgs)
+        # the cluster-tile shape appended last is visited too
+        late = [j for j, nm in enumerate(names) if "4x4x4" in nm or "8x4x2" in nm]
+        assert late and min(late) >= 46
+        assert all(taken[j] >= 1 for j in late), [(names[j], taken[j]) for j in late]
