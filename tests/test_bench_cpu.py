@@ -49,3 +49,21 @@ def test_traffic_record_matches_sources_and_kernel_form(tmp_path):
     p.write_text(json.dumps(stale))
     b.TRAFFIC_FILE = str(p)
     assert b.measured_traffic(rec["config"], fused) is None
+
+
+def test_roofline_is_the_ceiling_that_takes_longer():
+    b = _bench()
+    # the headline's fused launch: 663 MFLOP of useful work and 308 MB of
+    # algorithmic bytes in 114 us; HBM alone needs 38.5 us, FP32 alone 4.2 us
+    flops, nbytes, us = 26.0 * 25.5e6, 308e6, 114.0
+    bound, other = b.rooflines(flops, us, nbytes)
+    assert bound["bound"] == "hbm" and other["bound"] == "alu"
+    assert abs(bound["frac"] - nbytes / (us * 1e-6) / 8e12) < 1e-12
+    assert abs(other["frac"] - flops / (us * 1e-6) / 157.3e12) < 1e-12
+    assert abs(bound["flop_per_byte"] - flops / nbytes) < 1e-12
+    # the same work with few bytes is bound by the FP32 ceiling
+    bound, other = b.rooflines(flops, us, 1e6)
+    assert bound["bound"] == "alu" and other["bound"] == "hbm"
+    # no lists (linked cells): only the FP32 ceiling
+    bound, other = b.rooflines(flops, us, None)
+    assert bound["bound"] == "alu" and other is None
