@@ -110,3 +110,13 @@ def test_lane_map_rejects_bad_shapes(m):
         m.lane_map(0, 3, 8)
     with pytest.raises(m.MdljError):
         m.lane_map(2, 1, 8)
+
+
+def test_cluster_tile_names(m):
+    # one cluster pair per wavefront: M x 64/M; several: M x 4 x (pairs)
+    assert m.config_name((2, 1, 4, 16, 4, 0)) == "VCL4/cluster-tile/4x16"
+    assert m.config_name((2, 1, 8, 8, 8, 1, 0, 1)) == "VCL8/cluster-tile/8x8/n3/swap"
+    assert m.config_name((2, 1, 4, 4, 4, 0)) == "VCL4/cluster-tile/4x4x4"
+    assert m.config_name((2, 1, 8, 4, 8, 1, 0, 1)) == "VCL8/cluster-tile/8x4x2/n3/swap"
+    # linked-cell tiles keep their two-number names
+    assert m.config_name((0, 1, 16, 4, 0, 0, 1)) == "LC/cluster-tile/16x4/lds"
