@@ -326,19 +326,24 @@ __global__ __launch_bounds__(PS_TB) void k_pair_search_w(
     }
 }
 
-__device__ __forceinline__ void decode(int32_t e, const double *L, int32_t &J, double &sx,
-                                       double &sy, double &sz)
-{
-    J = e & J_MASK;
-    const int code = (int)((uint32_t)e >> CODE_SHIFT);
-    sx = (double)(code % 3 - 1) * L[0];
-    sy = (double)((code / 3) % 3 - 1) * L[1];
-    sz = (double)(code / 9 - 1) * L[2];
-}
-
 struct BoxL {
     double L[3];
 };
+
+// The 27 image shifts of the codes, one table per workgroup in LDS: the
+// force kernels read a list entry's shift from it instead of decoding the
+// code arithmetically (two integer divisions, three conversions and
+// products per entry and lane).  Code 13 is the zero shift.
+constexpr int CODE_NO_SHIFT = 13;
+
+__device__ __forceinline__ void shift_table_load(double (*st)[4], const BoxL &bl, int tid)
+{
+    if (tid < 27) {
+        st[tid][0] = (double)(tid % 3 - 1) * bl.L[0];
+        st[tid][1] = (double)((tid / 3) % 3 - 1) * bl.L[1];
+        st[tid][2] = (double)(tid / 9 - 1) * bl.L[2];
+    }
+}
 
 // Cluster tile: M x AJ lanes per cluster pair, QI = 64 / (M AJ) cluster
 // pairs per wavefront (M x 64/M: one cluster I per wavefront; M x 4: four
@@ -361,11 +366,11 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
     constexpr int QI = MDLJ_WAVE / W;    // cluster pairs per wavefront
     static_assert(QI * W == MDLJ_WAVE && (AJ % M == 0 || M % AJ == 0), "tile shape");
     __shared__ LdsTable<T> lt;
+    __shared__ double shifts[27][4];
     const double rc2 = tab.rc2d;
-    if (MS) {
-        lds_table_load(lt, tab, threadIdx.x, blockDim.x);
-        __syncthreads();
-    }
+    if (MS) lds_table_load(lt, tab, threadIdx.x, blockDim.x);
+    shift_table_load(shifts, bl, threadIdx.x);
+    __syncthreads();
     const int64_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int lane = threadIdx.x & (MDLJ_WAVE - 1);
     const int64_t I = (b * (blockDim.x / MDLJ_WAVE) + threadIdx.x / MDLJ_WAVE) * QI + lane / W;
@@ -397,8 +402,7 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
     const int32_t Tw = Lw * SPE;
     for (int32_t t00 = 0; t00 < Tw; t00 += TRIP) {
         // U steps per trip: their list and record loads are in flight together
-        int32_t J[UNROLL], m[UNROLL];
-        double sx[UNROLL], sy[UNROLL], sz[UNROLL];
+        int32_t J[UNROLL], m[UNROLL], code[UNROLL];
         bool ok[UNROLL];
         PosT pj[UNROLL];
 #pragma unroll
@@ -413,9 +417,13 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
                 m[u] = (st % SPE) * AJ + m0;
             }
             ok[u] = k < Ln;
-            J[u] = 0;
-            sx[u] = sy[u] = sz[u] = 0.0;
-            if (ok[u]) decode(list[I * cap + k], bl.L, J[u], sx[u], sy[u], sz[u]);
+            // one load per step on every lane (a load in a branch is waited
+            // for at the branch's end): a lane past its list reads the last
+            // entry of its own row, a lane without a list (no cluster, or an
+            // empty one) cluster 0; their pairs are masked below
+            const int32_t e = list[(live ? I : 0) * cap + min(k, max(Ln - 1, 0))];
+            J[u] = Ln > 0 ? (e & J_MASK) : 0;
+            code[u] = ok[u] ? (int)((uint32_t)e >> CODE_SHIFT) : CODE_NO_SHIFT;
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) pj[u] = crec[(int64_t)J[u] * M + m[u]];
@@ -429,11 +437,12 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
             const int64_t jslot = (int64_t)J[u] * M + mu;
             // self cluster without shift: skip the diagonal, and with Newton-3
             // the lower triangle
-            const bool self0 = ok[u] && J[u] == I && sx[u] == 0.0 && sy[u] == 0.0 && sz[u] == 0.0;
+            const bool self0 = ok[u] && J[u] == I && code[u] == CODE_NO_SHIFT;
             const bool valid = ok[u] && !(self0 && (N3 ? mu <= a : mu == a));
             const PairP<T> p = pair_params<T, MS>(tab, lt, pi.t, pj[u].t);
+            const double *sh = shifts[code[u]];
             double fxp, fyp, fzp;
-            lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x + sx[u], pj[u].y + sy[u], pj[u].z + sz[u], valid,
+            lj_pair<T, E>(pi.x, pi.y, pi.z, pj[u].x + sh[0], pj[u].y + sh[1], pj[u].z + sh[2], valid,
                           p, rc2, acc, fxp, fyp, fzp);
             if (N3) {
                 // -F on j summed over the M i-lanes of its group that share
@@ -487,11 +496,11 @@ __global__ __launch_bounds__(256) void k_vcl_ipl(const PosT *__restrict__ crec,
                                                  ForceOut fo, int remap)
 {
     __shared__ LdsTable<T> lt;
+    __shared__ double shifts[27][4];
     const double rc2 = tab.rc2d;
-    if (MS) {
-        lds_table_load(lt, tab, threadIdx.x, blockDim.x);
-        __syncthreads();
-    }
+    if (MS) lds_table_load(lt, tab, threadIdx.x, blockDim.x);
+    shift_table_load(shifts, bl, threadIdx.x);
+    __syncthreads();
     const int64_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int64_t g = b * blockDim.x + threadIdx.x;  // global lane
     const int64_t I = g / M;
@@ -503,10 +512,11 @@ __global__ __launch_bounds__(256) void k_vcl_ipl(const PosT *__restrict__ crec,
     Acc acc;
     acc_zero(acc);
     for (int32_t k = 0; k < Ln; ++k) {
-        int32_t J;
-        double sx, sy, sz;
-        decode(list[I * cap + k], bl.L, J, sx, sy, sz);
-        const bool self0 = J == I && sx == 0.0 && sy == 0.0 && sz == 0.0;
+        const int32_t e = list[I * cap + k];
+        const int32_t J = e & J_MASK;
+        const int code = (int)((uint32_t)e >> CODE_SHIFT);
+        const double sx = shifts[code][0], sy = shifts[code][1], sz = shifts[code][2];
+        const bool self0 = J == I && code == CODE_NO_SHIFT;
         for (int mm = 0; mm < M; ++mm) {
             const int64_t jslot = (int64_t)J * M + mm;
             const PosT pj = crec[jslot];
