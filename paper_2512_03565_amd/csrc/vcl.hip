@@ -418,9 +418,11 @@ __global__ __launch_bounds__(256) void k_vcl_tile(const PosT *__restrict__ crec,
             }
             ok[u] = k < Ln;
             // one load per step on every lane (a load in a branch is waited
-            // for at the branch's end): a lane past its list reads the last
-            // entry of its own row, a lane without a list (no cluster, or an
-            // empty one) cluster 0; their pairs are masked below
+            // for at the branch's end), always inside the list array: a lane
+            // past its list reads the last entry of its own row; a lane
+            // without a list (no cluster, or an empty list) reads the first
+            // word of its row (or of row 0), which it ignores for cluster 0
+            // and the zero shift.  The pairs of both are masked below.
             const int32_t e = list[(live ? I : 0) * cap + min(k, max(Ln - 1, 0))];
             J[u] = Ln > 0 ? (e & J_MASK) : 0;
             code[u] = ok[u] ? (int)((uint32_t)e >> CODE_SHIFT) : CODE_NO_SHIFT;
