@@ -355,7 +355,7 @@ mdlj_status mdlj_get_pairs(mdlj_ctx *ctx, int64_t cap, int32_t *pi, int32_t *pj,
  * loaded (a network of K classes chooses among the first K configurations
  * of config_at order; its fallback searches them all); EARLY_STOP is the full search with early stopping (the decision
  * rule of mdlj_tune_select_early with warm_factor +inf, i.e. the warm-up
- * cycle is not judged, and margin 0.1), the
+ * cycle is not scored, and margin 0.1), the
  * configurations visited by descending network probability when a network
  * is loaded (configurations beyond its K classes last, in config_at order),
  * else in config_at order.  The chosen

@@ -332,7 +332,7 @@ mdlj_status tune_exhaustive(mdlj_ctx *ctx, int samples, mdlj_config *chosen, dou
 
 // Early-stopping constants of the live search: a configuration is dropped
 // when its first timed cycle is more than 10% above the best step time so
-// far.  Its warm-up cycle is not judged: besides the structure build it
+// far.  Its warm-up cycle is not scored: besides the structure build it
 // carries one-time costs (device buffers allocated the first time a
 // structure of that kind is built) that outweigh the steps of small scenes.
 constexpr double EARLY_WARM = std::numeric_limits<double>::infinity();
