@@ -21,6 +21,15 @@ Writes a JSON summary.
 
     python -m paper_2512_03565_amd.eval_tuner sweep_0.npz sweep_1000.npz \
         --weights paper_2512_03565_amd/data/tuner_mlp.bin --out eval.json
+
+Offline (no GPU), after some configurations were timed again on the
+held-out scenes (``sweep.py --configs``): the sweep-table regret of the
+decisions an evaluation recorded, against the sweep's timings and against
+the same timings with the re-timed columns replaced.
+
+    python -m paper_2512_03565_amd.eval_tuner paper_2512_03565_amd/data/tuner_sweep.npz \
+        --retimed paper_2512_03565_amd/data/tuner_sweep_vcl_heldout.npz \
+        --decisions paper_2512_03565_amd/data/tuner_eval.json
 """
 import argparse
 import json
@@ -30,10 +39,63 @@ import time
 import numpy as np
 
 
+def retimed_regret(names, table, sids, retimed, decisions):
+    """Sweep-table regret t(decision) / t(fastest) of recorded decisions,
+    before and after replacing the columns `retimed` holds (finite values
+    only) for the scenes it holds.  names, table [S, K] and sids describe
+    the sweep; retimed is (names, table, sids) of the re-timing; decisions
+    are the evaluation's scene records (a fallback ran the full search,
+    which finds the fastest: regret 0).  Returns per-scene ratios (before,
+    after) and the number of scenes whose fastest configuration changed."""
+    row = {int(s): k for k, s in enumerate(sids)}
+    rnames, rtable, rsids = retimed
+    cols = [names.index(n) for n in rnames]
+    rrow = {int(s): k for k, s in enumerate(rsids)}
+    before, after, changed = [], [], 0
+    for d in decisions:
+        sid = int(d["scene"])
+        if sid not in row or sid not in rrow:
+            continue
+        t0 = np.asarray(table[row[sid]], float)
+        t1 = t0.copy()
+        for c, v in zip(cols, rtable[rrow[sid]]):
+            if np.isfinite(v):
+                t1[c] = v
+        changed += int(np.argmin(t1) != np.argmin(t0))
+        if d["fallback"]:
+            before.append(1.0)
+            after.append(1.0)
+        else:
+            c = names.index(d["chosen"])
+            before.append(t0[c] / t0.min())
+            after.append(t1[c] / t1.min())
+    return np.array(before), np.array(after), changed
+
+
+def offline(a):
+    from paper_2512_03565_amd.train_tuner import load
+    F, T, meta, names = load(a.sweeps)
+    r = np.load(a.retimed, allow_pickle=False)
+    with open(a.decisions) as f:
+        dec = json.load(f)["scenes"]
+    b, c, changed = retimed_regret(names, T, meta[:, 0], (list(r["names"]), r["table_us"],
+                                                            r["meta"][:, 0]), dec)
+    g = lambda x: float(np.exp(np.log(x).mean()) - 1)
+    print(json.dumps({"scenes": int(len(b)), "fastest_changed": changed,
+                      "regret_geomean_before": g(b), "regret_geomean_after": g(c),
+                      "within_5pct_before": float((b <= 1.05).mean()),
+                      "within_5pct_after": float((c <= 1.05).mean()),
+                      "regret_max_before": float(b.max() - 1),
+                      "regret_max_after": float(c.max() - 1)}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("sweeps", nargs="+")
-    ap.add_argument("--weights", required=True)
+    ap.add_argument("--weights", default=None)
+    ap.add_argument("--retimed", default=None, help="offline: re-timed columns (.npz)")
+    ap.add_argument("--decisions", default=None, help="offline: an evaluation's JSON")
     ap.add_argument("--first", type=int, default=1600, help="first held-out scene index")
     ap.add_argument("--count", type=int, default=400)
     ap.add_argument("--samples", type=int, default=10)
@@ -41,6 +103,12 @@ def main(argv=None):
     ap.add_argument("--full-every", type=int, default=4)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
+    if a.retimed:
+        if not a.decisions:
+            ap.error("--retimed needs --decisions")
+        return offline(a)
+    if not a.weights:
+        ap.error("--weights is required")
 
     import torch  # noqa: F401  (one HIP runtime: torch's)
     from paper_2512_03565_amd import mdlj, scenes

@@ -42,3 +42,28 @@ def test_best_single_configuration():
     # c cannot run everywhere; a: (1, 2, 1) -> 2^(1/3); b: (1.2, 1, 1.1)
     assert name == "b" and k == 1
     assert g == pytest.approx((1.2 * 1.0 * 1.1) ** (1 / 3))
+
+
+def test_regret_of_recorded_decisions_after_a_retiming():
+    from paper_2512_03565_amd.eval_tuner import retimed_regret
+    names = ["a", "b", "c"]
+    table = np.array([[1.0, 2.0, 3.0],     # scene 10: a fastest
+                      [2.0, 1.0, 4.0],     # scene 11: b fastest
+                      [1.0, 1.5, 2.0]])    # scene 12: a fastest
+    sids = [10, 11, 12]
+    # c timed again: now fastest on scene 10; on 11 it could not run (inf
+    # keeps the old value); scene 12 not re-timed
+    retimed = (["a", "b", "c"], np.array([[np.inf, np.inf, 0.5], [np.inf, np.inf, np.inf]]),
+               [10, 11])
+    dec = [{"scene": 10, "chosen": "a", "fallback": False},
+           {"scene": 11, "chosen": "a", "fallback": False},
+           {"scene": 12, "chosen": "b", "fallback": True}]
+    before, after, changed = retimed_regret(names, table, sids, retimed, dec)
+    # scene 12 is not in the re-timing and is skipped
+    assert changed == 1
+    assert np.allclose(before, [1.0, 2.0])
+    assert np.allclose(after, [2.0, 2.0])
+    # a fallback ran the full search: no regret either way
+    dec[1]["fallback"] = True
+    before, after, _ = retimed_regret(names, table, sids, retimed, dec)
+    assert np.allclose(before, [1.0, 1.0]) and np.allclose(after, [2.0, 1.0])
